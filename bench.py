@@ -1,0 +1,222 @@
+"""Benchmark of the oMAP hot path on one MI355X.
+
+One step = the whole path for one maze: ingest (pack the occupancy, store
+sources / targets), propagate with the run-time determined layer count, and
+extract the path of every target.  Inputs are resident in HBM before timing.
+
+Default workload: the 23170 x 23170 maze (Bernoulli(0.40) + 50,000 filled
+rectangles, 16 sources, 4096 targets on the largest component; seeded,
+synthetic).  Metric: Gcell-updates/s = cells x effective layers / step time,
+with effective layers S_J = L* + 1 (the layers the plain layer-by-layer method
+needs to reach and confirm the fixpoint; L* is the path's own run-time
+determined layer count, which the tests check against BFS).
+
+Prints one JSON line.  --workload batch | serve run the batched / serving forms
+instead (see their docstrings).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import subprocess
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0                  # MI355X HBM3E
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12   # 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz, 32-bit ops
+BYTES_PER_CELL_UPDATE = 8.125          # int32 read + int32 write + 1 mask bit
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_info():
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    return model, cores
+
+
+def cpu_baseline(m, budget_s: float = 12.0):
+    """The CPU oracle (literal network + simple path walk) on a bounded sample of
+    the same maze: a full-width band of rows, a fixed number of layers chosen so
+    the run takes about `budget_s` seconds on all host cores."""
+    import oracle
+    model, cores = cpu_info()
+    threads = max(1, min(cores, 16))
+    rows = min(m.H, 1024)
+    band = np.ascontiguousarray(m.occ[:rows])
+    free = np.argwhere(band == 0)
+    rng = np.random.default_rng(0)
+    src = free[rng.integers(0, len(free), 16)].astype(np.int32)
+    tgt = free[rng.integers(0, len(free), 256)].astype(np.int32)
+    t0 = time.perf_counter()
+    oracle.layers(band, src, 4, threads=threads)
+    t_probe = max(time.perf_counter() - t0, 1e-3) / 4
+    L = int(max(8, min(4096, budget_s / t_probe)))
+    t0 = time.perf_counter()
+    A, _ = oracle.layers(band, src, L, threads=threads)
+    t_layers = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    ln, off, cells = oracle.walk(A, src, tgt)
+    t_walk = time.perf_counter() - t0
+    rate = band.size * L / t_layers / 1e9
+    return {
+        "value": round(rate, 4), "unit": "Gcell-updates/s", "cores": threads, "kind": "oracle",
+        "sample": f"literal oMAP layers on rows 0..{rows - 1} (all {m.W} columns) of the same maze, "
+                  f"{L} layers, 16 sources; {t_layers:.1f} s; walk of 256 targets {t_walk:.2f} s",
+        "cpu_model": model, "host_cores": cores,
+        "walk_paths_per_s": round(len(tgt) / max(t_walk, 1e-9), 1),
+    }
+
+
+def bench_plain(args):
+    import torch
+    import paper_2004_00540_amd as omap
+    import workloads
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    t0 = time.perf_counter()
+    if args.workload == "c3":
+        m = workloads.config3()
+    elif args.workload == "c2":
+        m = workloads.config2()
+    else:
+        m = workloads.config1()
+    log(f"generated {m.name} in {time.perf_counter() - t0:.1f} s")
+    occ = torch.from_numpy(m.occ).to(dev)
+    N = m.H * m.W
+    opts = dict(temporal_depth=args.depth, tile_rows=args.tile_rows, schedule=args.schedule)
+    stream = torch.cuda.current_stream()
+    plan = omap.Plan(occ, m.sources, m.targets, **opts)
+    nt = len(m.targets)
+    lengths = torch.empty(nt, dtype=torch.int32, device=dev)
+    offsets = torch.empty(nt + 1, dtype=torch.int64, device=dev)
+    info = plan.propagate(omap.AUTO)
+    _, _, cells0 = plan.paths()
+    cells = torch.empty(max(cells0.numel(), 1), dtype=torch.int32, device=dev)
+    L_star = info["layers"]
+    S_J = L_star + 1
+    log(f"info {info}")
+
+    def step():
+        plan.load(occ, m.sources, m.targets)
+        plan.propagate(omap.AUTO, sync=False)
+        plan.extract_into(lengths, offsets, cells)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev[0].record(stream)
+    for _ in range(args.steps):
+        step()
+    ev[1].record(stream)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / args.steps
+    ms = ev[0].elapsed_time(ev[1]) / args.steps
+
+    # phase split of one step (events on the plan's stream)
+    ph = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    ph[0].record(stream)
+    plan.load(occ, m.sources, m.targets)
+    ph[1].record(stream)
+    plan.propagate(omap.AUTO, sync=False)
+    ph[2].record(stream)
+    plan.extract_into(lengths, offsets, cells)
+    ph[3].record(stream)
+    torch.cuda.synchronize()
+    t_load, t_prop, t_ext = (ph[i].elapsed_time(ph[i + 1]) for i in range(3))
+
+    # sweep-kernel timing with HIP events around every launch
+    plan.profile(True)
+    plan.propagate(omap.AUTO, sync=False)
+    prof = plan.profile_read()
+    plan.profile(False)
+    plan.close()
+
+    step_s = wall
+    gcups = N * S_J / step_s / 1e9
+    alg_bytes = prof["cell_updates"] * BYTES_PER_CELL_UPDATE
+    kern_s = prof["ms"] / 1e3
+    achieved = alg_bytes / kern_s / 1e9 if kern_s > 0 else 0.0
+    ops_per_cell = 4.5
+    alu_tops = prof["cell_updates"] * ops_per_cell / kern_s / 1e12 if kern_s > 0 else 0.0
+    out = {
+        "metric": "Gcell-updates/s", "value": round(gcups, 3), "unit": "Gcell-updates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(step_s * 1e3, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": m.name, "cells": N, "sources": len(m.sources), "targets": nt,
+                   "layers_run_time": L_star, "effective_layers": S_J,
+                   "temporal_depth": args.depth or 16, "tile_rows": args.tile_rows or 64,
+                   "schedule": "dense" if args.schedule else "active"},
+        "paths_per_s": round(nt / step_s, 1),
+        "path_cells": int(cells0.numel()),
+        "phase_ms": {"ingest": round(t_load, 3), "propagate": round(t_prop, 3), "extract": round(t_ext, 3)},
+        "event_ms_per_step": round(ms, 3),
+        "sweep_kernel": {"launches": prof["launches"], "ms_total": round(prof["ms"], 3),
+                         "avg_us": round(prof["ms"] * 1e3 / max(prof["launches"], 1), 2),
+                         "cell_updates": prof["cell_updates"],
+                         "dense_cell_updates": N * S_J},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None},
+        "roofline_alu": {"bound": "alu", "achieved": round(alu_tops, 2), "peak": round(VALU_PEAK_TOPS, 1),
+                         "unit": "Tops/s", "frac": round(alu_tops / VALU_PEAK_TOPS, 4),
+                         "ops_per_cell_update": ops_per_cell},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(m, args.cpu_budget)
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "batch", "serve"])
+    ap.add_argument("--depth", type=int, default=0)
+    ap.add_argument("--tile-rows", type=int, default=0)
+    ap.add_argument("--schedule", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=12.0)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the path runs on a single MI355X "
+              "(multi-GPU sharding is a design note, not part of this build)", file=sys.stderr)
+        sys.exit(2)
+    if args.workload in ("c1", "c2", "c3"):
+        out = bench_plain(args)
+    elif args.workload == "batch":
+        from bench_forms import bench_batch
+        out = bench_batch(args)
+    else:
+        from bench_forms import bench_serve
+        out = bench_serve(args)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

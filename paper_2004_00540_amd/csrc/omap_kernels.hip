@@ -1,0 +1,613 @@
+// Device kernels of the oMAP planner for gfx950 (CDNA4, wave64).
+//
+// The network of the paper (Sec. Methods, "Activity Map Generation"; Fig. net)
+// applies L identical layers  A <- ReLU(maxpool3x3(A) + I_e + I_s)  starting
+// from A_0 = I_s.  The kernels run the same layers in an integer encoding with
+// a per-layer decrement: V_0 = K at the sources and 0 elsewhere, and
+//     V'(x) = 0                                   x an obstacle
+//     V'(x) = max(V(x), max over the 3x3 window of V - 1)   otherwise
+// With K = L + 1 the fixpoint of this update equals A_L exactly (both are
+// max(0, L + 1 - d(x)) with d the 8-neighbour step distance to the nearest
+// source), it is reached after at most L sweeps, and further sweeps leave it
+// unchanged.  Because the update is monotone and bounded by that fixpoint, any
+// schedule of tile updates that keeps visiting tiles whose neighbourhood
+// changed reaches the same bits; the tests compare against the paper's literal
+// layers.  With K = 2^31 - 1 the fixpoint is K - d and the run-time determined
+// layer count L* is K minus the smallest positive value.
+//
+// In registers an obstacle is the value 0x80000000 (the sign bit).  Signed
+// max-pooling ignores it; the update  max_u32(V, sat_sub_u32(m, 1))  keeps it
+// (0x80000000 is above any activity as unsigned) and clamps free cells at 0,
+// so one unsigned max and one saturating subtract implement decrement, ReLU and
+// obstacle masking together.
+
+#include "omap_internal.h"
+
+namespace omap {
+
+// ---------------------------------------------------------------------------
+// helpers
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ int max3i(int a, int b, int c) { return max(max(a, b), c); }
+
+__device__ __forceinline__ uint32_t sat_dec(uint32_t x) {
+    return __builtin_elementwise_sub_sat(x, 1u);
+}
+
+// Lane l receives lane l-1's value (DPP wave_shr:1).  Lane 0 has no source
+// and reads 0; the kernels only use that lane's result inside the halo.
+__device__ __forceinline__ int from_left_lane(int v) {
+    return __builtin_amdgcn_mov_dpp(v, 0x138, 0xF, 0xF, true);
+}
+
+// Lane l receives lane l+1's value (DPP wave_shl:1); lane 63 reads 0.
+__device__ __forceinline__ int from_right_lane(int v) {
+    return __builtin_amdgcn_mov_dpp(v, 0x130, 0xF, 0xF, true);
+}
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & (kLanes - 1); }
+
+// ---------------------------------------------------------------------------
+// ingest: occupancy bytes -> obstacle bit mask
+// ---------------------------------------------------------------------------
+
+__global__ void k_pack_mask(const uint8_t* __restrict__ occ, int32_t H, int32_t W,
+                            uint32_t* __restrict__ mask, int32_t mpitch) {
+    const int64_t n = (int64_t)H * mpitch;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t r = (int32_t)(i / mpitch);
+        const int32_t w = (int32_t)(i - (int64_t)r * mpitch);
+        const int32_t c0 = w * 32;
+        const uint8_t* row = occ + (int64_t)r * W;
+        uint32_t word = 0;
+        if (c0 + 32 <= W) {
+#pragma unroll
+            for (int b = 0; b < 32; ++b) word |= (row[c0 + b] != 0 ? 1u : 0u) << b;
+        } else {
+            for (int b = 0; b < 32; ++b) {
+                const int32_t c = c0 + b;
+                const uint32_t bit = (c >= W) ? 1u : (row[c] != 0 ? 1u : 0u);
+                word |= bit << b;
+            }
+        }
+        mask[i] = word;
+    }
+}
+
+__global__ void k_fill(int32_t* __restrict__ p, int64_t n4, int32_t value) {
+    int4 v = make_int4(value, value, value, value);
+    int4* q = reinterpret_cast<int4*>(p);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4;
+         i += (int64_t)gridDim.x * blockDim.x)
+        q[i] = v;
+}
+
+__global__ void k_check_sources(const uint32_t* __restrict__ mask, int32_t mpitch,
+                                const int32_t* __restrict__ src, int32_t n,
+                                int32_t* __restrict__ bad) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t r = src[2 * i], c = src[2 * i + 1];
+    const uint32_t w = mask[(int64_t)r * mpitch + (c >> 5)];
+    if ((w >> (c & 31)) & 1u) atomicAdd(bad, 1);
+}
+
+// Seed V := K at the sources (both buffers) and schedule the tiles whose
+// interior or halo holds a source.
+__global__ void k_seed(const MazeDev* __restrict__ mazes, int32_t slot, const int32_t* __restrict__ src,
+                       int32_t n, int32_t tile_rows, int32_t tile_cols, uint8_t* __restrict__ flags,
+                       int32_t* __restrict__ maze_changed, int32_t* __restrict__ bad) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const MazeDev md = mazes[slot];
+    const int32_t r = src[2 * i], c = src[2 * i + 1];
+    const uint32_t w = md.mask[(int64_t)r * md.mpitch + (c >> 5)];
+    if ((w >> (c & 31)) & 1u) {
+        atomicAdd(bad, 1);
+        return;
+    }
+    const int64_t x = (int64_t)r * md.pitch + c;
+    md.V[0][x] = md.K;
+    md.V[1][x] = md.K;
+    const int ty = r / tile_rows, tx = c / tile_cols;
+    for (int dy = -1; dy <= 1; ++dy)
+        for (int dx = -1; dx <= 1; ++dx) {
+            const int ny = ty + dy, nx = tx + dx;
+            if (ny >= 0 && ny < md.tiles_y && nx >= 0 && nx < md.tiles_x)
+                flags[md.tile_base + ny * md.tiles_x + nx] = 1;
+        }
+    maze_changed[slot] = 1;
+}
+
+// ---------------------------------------------------------------------------
+// the sweep: T layers per tile visit, one wave per tile
+// ---------------------------------------------------------------------------
+//
+// A tile is `rows` x TW interior cells (TW = 256 - 2T) at (r0, c0).  The wave
+// streams the 256-column strip [c0 - T, c0 - T + 256) from row r0 - T down to
+// row r0 + rows + T - 1; lane l holds columns c0 - T + 4l .. +3.  Stage s of
+// a T-stage register pipeline applies layer s+1 to the rows stage s-1 emits,
+// one row behind it, keeping its last two input rows in registers.  Cells
+// within s of the strip's edges after s layers are wrong (their neighbours
+// were not loaded), and that region is exactly the halo; the interior is exact
+// after T layers (trapezoidal temporal blocking).  Out-of-grid positions load
+// as obstacles, which is the zero padding of the paper's pooling.
+
+// One row step of the pipeline.  Stage s keeps its last three input rows in
+// st[s][0..2]; on the step with P = i mod 3 the newest row (i) sits in slot P,
+// row i-1 in slot (P+2) mod 3 and row i-2 in slot (P+1) mod 3.  Stage s writes
+// its output row straight into stage s+1's slot P, whose previous content
+// (row i-3 of that stage) is dead, so no register copies are needed.
+template <int T, int P>
+__device__ __forceinline__ void sweep_row(uint32_t (&st)[T][3][4], uint32_t (&out)[4]) {
+    constexpr int PA = (P + 1) % 3, PB = (P + 2) % 3;
+#pragma unroll
+    for (int s = 0; s < T; ++s) {
+        const uint32_t* a = st[s][PA];   // row above the centre
+        const uint32_t* b = st[s][PB];   // centre row
+        const uint32_t* c = st[s][P];    // row below the centre
+        const int v0 = max3i((int)a[0], (int)b[0], (int)c[0]);
+        const int v1 = max3i((int)a[1], (int)b[1], (int)c[1]);
+        const int v2 = max3i((int)a[2], (int)b[2], (int)c[2]);
+        const int v3 = max3i((int)a[3], (int)b[3], (int)c[3]);
+        const int left = from_left_lane(v3);
+        const int right = from_right_lane(v0);
+        const uint32_t h0 = (uint32_t)max3i(left, v0, v1);
+        const uint32_t h1 = (uint32_t)max3i(v0, v1, v2);
+        const uint32_t h2 = (uint32_t)max3i(v1, v2, v3);
+        const uint32_t h3 = (uint32_t)max3i(v2, v3, right);
+        uint32_t* o = (s + 1 < T) ? st[s + 1 < T ? s + 1 : s][P] : out;
+        o[0] = max(b[0], sat_dec(h0));
+        o[1] = max(b[1], sat_dec(h1));
+        o[2] = max(b[2], sat_dec(h2));
+        o[3] = max(b[3], sat_dec(h3));
+    }
+}
+
+template <int T, int P>
+__device__ __forceinline__ void sweep_iter(uint32_t (&st)[T][3][4], const MazeDev& md,
+                                           const int32_t* __restrict__ Vin,
+                                           int32_t* __restrict__ Vout, int R, int r0, int r_end,
+                                           int col, bool col_ok, bool inner,
+                                           uint64_t& sum_in, uint64_t& sum_out) {
+    uint32_t* c = st[0][P];
+    if (R >= 0 && R < md.H && col_ok) {
+        const int4 v = *reinterpret_cast<const int4*>(Vin + (int64_t)R * md.pitch + col);
+        const uint32_t w = md.mask[(int64_t)R * md.mpitch + (col >> 5)] >> (col & 31);
+        c[0] = (uint32_t)v.x | ((w & 1u) << 31);
+        c[1] = (uint32_t)v.y | ((w & 2u) << 30);
+        c[2] = (uint32_t)v.z | ((w & 4u) << 29);
+        c[3] = (uint32_t)v.w | ((w & 8u) << 28);
+    } else {
+        c[0] = c[1] = c[2] = c[3] = kObstacleBit;
+    }
+    if (inner && R >= r0 && R < r_end)
+        sum_in += (uint64_t)(c[0] & 0x7fffffffu) + (c[1] & 0x7fffffffu) + (c[2] & 0x7fffffffu) +
+                  (c[3] & 0x7fffffffu);
+    uint32_t out[4];
+    sweep_row<T, P>(st, out);
+    const int Ro = R - T;
+    if (inner && Ro >= r0 && Ro < r_end) {
+        int4 o;
+        o.x = (int)(out[0] & 0x7fffffffu);
+        o.y = (int)(out[1] & 0x7fffffffu);
+        o.z = (int)(out[2] & 0x7fffffffu);
+        o.w = (int)(out[3] & 0x7fffffffu);
+        *reinterpret_cast<int4*>(Vout + (int64_t)Ro * md.pitch + col) = o;
+        sum_out += (uint64_t)(uint32_t)o.x + (uint32_t)o.y + (uint32_t)o.z + (uint32_t)o.w;
+    }
+}
+
+// Returns true (wave-uniform) if any interior cell of the tile changed.
+template <int T>
+__device__ bool sweep_tile(const MazeDev& md, int ty, int tx, int tile_rows, int parity) {
+    constexpr int TW = kStripCols - 2 * T;
+    const int lane = lane_id();
+    const int r0 = ty * tile_rows;
+    const int r_end = min(r0 + tile_rows, md.H);
+    const int col = tx * TW - T + kColsPerLane * lane;
+    const bool col_ok = col >= 0 && col < md.pitch;
+    const bool inner = lane >= T / 4 && lane < kLanes - T / 4 && col < md.W;
+    const int32_t* __restrict__ Vin = md.V[parity];
+    int32_t* __restrict__ Vout = md.V[parity ^ 1];
+
+    uint32_t st[T][3][4];
+#pragma unroll
+    for (int s = 0; s < T; ++s)
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) st[s][k][j] = kObstacleBit;
+
+    uint64_t sum_in = 0, sum_out = 0;
+    const int n_iter = (r_end - r0) + 2 * T;   // rows r0-T .. r_end+T-1
+    for (int i = 0; i < n_iter; i += 3) {
+        const int R = r0 - T + i;
+        sweep_iter<T, 0>(st, md, Vin, Vout, R, r0, r_end, col, col_ok, inner, sum_in, sum_out);
+        sweep_iter<T, 1>(st, md, Vin, Vout, R + 1, r0, r_end, col, col_ok, inner, sum_in, sum_out);
+        sweep_iter<T, 2>(st, md, Vin, Vout, R + 2, r0, r_end, col, col_ok, inner, sum_in, sum_out);
+    }
+    return __ballot(sum_in != sum_out) != 0;
+}
+
+template <int T>
+__global__ __launch_bounds__(kBlockThreads) void k_sweep(RoundArgs a) {
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = lane_id();
+    if (blockIdx.x == 0 && threadIdx.x == 0) *a.count_out = 0;
+    const int n = __builtin_amdgcn_readfirstlane(*a.count_in);
+    const int stride = gridDim.x * kWavesPerBlock;
+    for (int i = blockIdx.x * kWavesPerBlock + wave; i < n; i += stride) {
+        const int g = a.list_in[i];
+        const int slot = a.tile_maze[g];
+        const MazeDev md = a.mazes[slot];
+        const int lt = g - md.tile_base;
+        const int ty = lt / md.tiles_x;
+        const int tx = lt - ty * md.tiles_x;
+        if (sweep_tile<T>(md, ty, tx, a.tile_rows, a.parity)) {
+            if (lane < 9) {
+                const int ny = ty + lane / 3 - 1, nx = tx + lane % 3 - 1;
+                if (ny >= 0 && ny < md.tiles_y && nx >= 0 && nx < md.tiles_x)
+                    a.flags[md.tile_base + ny * md.tiles_x + nx] = 1;
+            }
+            if (lane == 0) a.maze_changed[slot] = 1;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// schedule: next round's tile list from the change flags
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_build(RoundArgs a) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = lane_id();
+    bool act = false;
+    int slot = -1;
+    int64_t cells = 0;
+    if (g < a.n_tile_ids) {
+        slot = a.tile_maze[g];
+        const bool flagged = a.flags[g] != 0;
+        if (flagged) a.flags[g] = 0;
+        if (slot >= 0 && a.maze_state[slot] == kMazeRunning) {
+            act = a.dense ? (a.maze_changed[slot] != 0) : flagged;
+            if (act) {
+                const MazeDev md = a.mazes[slot];
+                const int lt = g - md.tile_base;
+                const int ty = lt / md.tiles_x, tx = lt - ty * md.tiles_x;
+                const int rows = min(a.tile_rows, md.H - ty * a.tile_rows);
+                const int cols = min(a.tile_cols, md.W - tx * a.tile_cols);
+                cells = (int64_t)rows * cols;
+            }
+        }
+    }
+    const unsigned long long bal = __ballot(act);
+    if (bal == 0) return;
+    const int leader = __ffsll(bal) - 1;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(a.count_out, __popcll(bal));
+    base = __shfl(base, leader);
+    if (act) a.list_out[base + __popcll(bal & ((1ull << lane) - 1ull))] = g;
+    // per-maze counts, aggregated over lanes of the leader's maze
+    const int lead_slot = __shfl(slot, leader);
+    const bool same = act && slot == lead_slot;
+    const unsigned long long bs = __ballot(same);
+    int64_t csum = same ? cells : 0;
+    for (int off = 32; off > 0; off >>= 1) csum += __shfl_xor(csum, off);
+    if (lane == leader) {
+        atomicAdd(&a.maze_active[lead_slot], (int)__popcll(bs));
+        atomicAdd((unsigned long long*)&a.maze_cells[lead_slot], (unsigned long long)csum);
+    }
+    if (act && !same) {
+        atomicAdd(&a.maze_active[slot], 1);
+        atomicAdd((unsigned long long*)&a.maze_cells[slot], (unsigned long long)cells);
+    }
+}
+
+__global__ void k_update(RoundArgs a) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= a.n_slots) return;
+    const int act = a.maze_active[m];
+    const int64_t cells = a.maze_cells[m];
+    if (a.maze_state[m] == kMazeRunning) {
+        if (act > 0) {
+            a.maze_rounds[m] += 1;
+            a.maze_visits[m] += act;
+            a.maze_cell_visits[m] += cells;
+            atomicAdd(a.total_cells, (unsigned long long)cells);
+        } else {
+            a.maze_state[m] = kMazeDone;
+        }
+    }
+    a.maze_active[m] = 0;
+    a.maze_cells[m] = 0;
+    a.maze_changed[m] = 0;
+}
+
+// ---------------------------------------------------------------------------
+// finalize: smallest positive activity and reached-cell count per maze
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_reduce(const MazeDev* __restrict__ mazes,
+                                                const int32_t* __restrict__ tile_maze,
+                                                int32_t tile_begin, const int32_t* __restrict__ sel,
+                                                int32_t tile_rows, int32_t tile_cols, int32_t parity,
+                                                int32_t* __restrict__ maze_min,
+                                                unsigned long long* __restrict__ maze_reached) {
+    const int g = tile_begin + blockIdx.x;
+    const int slot = tile_maze[g];
+    if (slot < 0 || (sel != nullptr && sel[slot] == 0)) return;
+    const MazeDev md = mazes[slot];
+    const int lt = g - md.tile_base;
+    const int ty = lt / md.tiles_x, tx = lt - ty * md.tiles_x;
+    const int r0 = ty * tile_rows, c0 = tx * tile_cols;
+    const int rows = min(tile_rows, md.H - r0), cols = min(tile_cols, md.W - c0);
+    const int32_t* V = md.V[parity];
+    int vmin = 0x7fffffff;
+    int cnt = 0;
+    for (int k = threadIdx.x; k < rows * cols; k += blockDim.x) {
+        const int r = r0 + k / cols, c = c0 + k % cols;
+        const int v = V[(int64_t)r * md.pitch + c];
+        if (v > 0) {
+            vmin = min(vmin, v);
+            ++cnt;
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        vmin = min(vmin, __shfl_xor(vmin, off));
+        cnt += __shfl_xor(cnt, off);
+    }
+    __shared__ int smin[4], scnt[4];
+    const int w = threadIdx.x >> 6;
+    if (lane_id() == 0) {
+        smin[w] = vmin;
+        scnt[w] = cnt;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int m = smin[0], n = scnt[0];
+        for (int k = 1; k < (int)(blockDim.x >> 6); ++k) {
+            m = min(m, smin[k]);
+            n += scnt[k];
+        }
+        if (n > 0) {
+            atomicMin(&maze_min[slot], m);
+            atomicAdd(&maze_reached[slot], (unsigned long long)n);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// paths: lengths, offsets, gradient walk (one lane per target)
+// ---------------------------------------------------------------------------
+
+__global__ void k_path_lengths(const MazeDev* __restrict__ mazes, const int32_t* __restrict__ tslot,
+                               const int32_t* __restrict__ trc, int32_t n, int32_t parity,
+                               int32_t* __restrict__ len) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const MazeDev md = mazes[tslot[i]];
+    const int32_t r = trc[2 * i], c = trc[2 * i + 1];
+    const int v = md.V[parity][(int64_t)r * md.pitch + c];
+    len[i] = v > 0 ? md.K - v : -1;
+}
+
+__global__ __launch_bounds__(1024) void k_scan(const int32_t* __restrict__ len, int32_t n,
+                                               int64_t* __restrict__ off) {
+    __shared__ int64_t part[1024];
+    const int t = threadIdx.x;
+    const int chunk = (n + 1023) / 1024;
+    const int b = min(n, t * chunk), e = min(n, b + chunk);
+    int64_t s = 0;
+    for (int i = b; i < e; ++i) s += len[i] >= 0 ? (int64_t)len[i] + 1 : 0;
+    part[t] = s;
+    __syncthreads();
+    for (int d = 1; d < 1024; d <<= 1) {
+        const int64_t v = t >= d ? part[t - d] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    int64_t base = t ? part[t - 1] : 0;
+    if (t == 0) off[0] = 0;
+    for (int i = b; i < e; ++i) {
+        base += len[i] >= 0 ? (int64_t)len[i] + 1 : 0;
+        off[i + 1] = base;
+    }
+}
+
+__global__ void k_walk(const MazeDev* __restrict__ mazes, const int32_t* __restrict__ tslot,
+                       const int32_t* __restrict__ trc, int32_t n, int32_t parity,
+                       const int32_t* __restrict__ len, const int64_t* __restrict__ off,
+                       int32_t* __restrict__ cells) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int steps = len[i];
+    if (steps < 0) return;
+    const MazeDev md = mazes[tslot[i]];
+    const int32_t* __restrict__ V = md.V[parity];
+    int r = trc[2 * i], c = trc[2 * i + 1];
+    int64_t o = off[i];
+    cells[o++] = r * md.W + c;
+    for (int s = 0; s < steps; ++s) {
+        // the 8 neighbours in the fixed order; first maximum wins
+        const bool up = r > 0, dn = r + 1 < md.H, lf = c > 0, rt = c + 1 < md.W;
+        const int32_t* row_u = V + (int64_t)(r - 1) * md.pitch;
+        const int32_t* row_m = V + (int64_t)r * md.pitch;
+        const int32_t* row_d = V + (int64_t)(r + 1) * md.pitch;
+        int nv[8];
+        nv[0] = (up && lf) ? row_u[c - 1] : -1;
+        nv[1] = up ? row_u[c] : -1;
+        nv[2] = (up && rt) ? row_u[c + 1] : -1;
+        nv[3] = lf ? row_m[c - 1] : -1;
+        nv[4] = rt ? row_m[c + 1] : -1;
+        nv[5] = (dn && lf) ? row_d[c - 1] : -1;
+        nv[6] = dn ? row_d[c] : -1;
+        nv[7] = (dn && rt) ? row_d[c + 1] : -1;
+        int best = 0, bv = nv[0];
+#pragma unroll
+        for (int k = 1; k < 8; ++k)
+            if (nv[k] > bv) {
+                bv = nv[k];
+                best = k;
+            }
+        r += (best < 3) ? -1 : (best < 5 ? 0 : 1);
+        c += (best == 0 || best == 3 || best == 5) ? -1 : ((best == 1 || best == 6) ? 0 : 1);
+        cells[o++] = r * md.W + c;
+    }
+}
+
+// O = V - offset where V > 0, else 0 (offset = K - L - 1 maps the encoding back
+// to the paper's activity values).
+__global__ void k_activity(const MazeDev* __restrict__ mazes, int32_t slot, int32_t parity,
+                           int32_t offset, int32_t* __restrict__ dst, int64_t dpitch,
+                           int32_t col_blocks) {
+    const MazeDev md = mazes[slot];
+    const int64_t b = blockIdx.x;
+    const int32_t r = (int32_t)(b / col_blocks);
+    const int32_t c = (int32_t)(b - (int64_t)r * col_blocks) * blockDim.x + threadIdx.x;
+    if (r >= md.H || c >= md.W) return;
+    const int v = md.V[parity][(int64_t)r * md.pitch + c];
+    dst[(int64_t)r * dpitch + c] = v > 0 ? v - offset : 0;
+}
+
+// Device self-check of the cross-lane moves and the saturating decrement.
+__global__ void k_selftest(int32_t* out) {
+    const int l = lane_id();
+    out[l] = from_left_lane(l + 100);
+    out[64 + l] = from_right_lane(l + 100);
+    if (l == 0) {
+        out[128] = (int32_t)sat_dec(0u);
+        out[129] = (int32_t)sat_dec(5u);
+        out[130] = (int32_t)sat_dec(kObstacleBit);
+        out[131] = (int32_t)max(kObstacleBit, sat_dec(0x7fffffffu));
+        out[132] = max3i((int)kObstacleBit, 3, -5);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launch wrappers
+// ---------------------------------------------------------------------------
+
+static int grid_for(int64_t n, int block, int cap = 1 << 20) {
+    int64_t g = (n + block - 1) / block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (int)g;
+}
+
+hipError_t launch_pack_mask(const uint8_t* occ, int32_t H, int32_t W, uint32_t* mask,
+                            int32_t mpitch, hipStream_t s) {
+    const int64_t n = (int64_t)H * mpitch;
+    hipLaunchKernelGGL(k_pack_mask, dim3(grid_for(n, 256, 65536)), dim3(256), 0, s, occ, H, W, mask,
+                       mpitch);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(int32_t* p, int64_t n_elems, int32_t value, hipStream_t s) {
+    const int64_t n4 = n_elems / 4;   // callers pass multiples of 4
+    hipLaunchKernelGGL(k_fill, dim3(grid_for(n4, 256, 65536)), dim3(256), 0, s, p, n4, value);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_sources(const uint32_t* mask, int32_t mpitch, const int32_t* src_rc,
+                                int32_t n_src, int32_t* bad_count, hipStream_t s) {
+    hipLaunchKernelGGL(k_check_sources, dim3(grid_for(n_src, 256)), dim3(256), 0, s, mask, mpitch,
+                       src_rc, n_src, bad_count);
+    return hipGetLastError();
+}
+
+hipError_t launch_seed(const MazeDev* mazes, int32_t slot, const int32_t* src_rc, int32_t n_src,
+                       int32_t tile_rows, int32_t tile_cols, uint8_t* flags, int32_t* maze_changed,
+                       int32_t* bad_count, hipStream_t s) {
+    hipLaunchKernelGGL(k_seed, dim3(grid_for(n_src, 256)), dim3(256), 0, s, mazes, slot, src_rc,
+                       n_src, tile_rows, tile_cols, flags, maze_changed, bad_count);
+    return hipGetLastError();
+}
+
+hipError_t launch_sweep(int T, const RoundArgs& a, int32_t grid, hipStream_t s) {
+    switch (T) {
+        case 4: hipLaunchKernelGGL(k_sweep<4>, dim3(grid), dim3(kBlockThreads), 0, s, a); break;
+        case 8: hipLaunchKernelGGL(k_sweep<8>, dim3(grid), dim3(kBlockThreads), 0, s, a); break;
+        case 12: hipLaunchKernelGGL(k_sweep<12>, dim3(grid), dim3(kBlockThreads), 0, s, a); break;
+        case 16: hipLaunchKernelGGL(k_sweep<16>, dim3(grid), dim3(kBlockThreads), 0, s, a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_build(const RoundArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL(k_build, dim3(grid_for(a.n_tile_ids, 256)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_update(const RoundArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL(k_update, dim3(grid_for(a.n_slots, 256)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce(const MazeDev* mazes, const int32_t* tile_maze, int32_t tile_begin,
+                         int32_t tile_end, const int32_t* slot_select, int32_t tile_rows,
+                         int32_t tile_cols, int32_t parity, int32_t* maze_min,
+                         unsigned long long* maze_reached, hipStream_t s) {
+    if (tile_end <= tile_begin) return hipSuccess;
+    hipLaunchKernelGGL(k_reduce, dim3(tile_end - tile_begin), dim3(256), 0, s, mazes, tile_maze,
+                       tile_begin, slot_select, tile_rows, tile_cols, parity, maze_min,
+                       maze_reached);
+    return hipGetLastError();
+}
+
+hipError_t launch_path_lengths(const MazeDev* mazes, const int32_t* tgt_slot, const int32_t* tgt_rc,
+                               int32_t n_tgt, int32_t parity, int32_t* len, hipStream_t s) {
+    if (n_tgt <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_path_lengths, dim3(grid_for(n_tgt, 256)), dim3(256), 0, s, mazes, tgt_slot,
+                       tgt_rc, n_tgt, parity, len);
+    return hipGetLastError();
+}
+
+hipError_t launch_scan_offsets(const int32_t* len, int32_t n, int64_t* offsets, hipStream_t s) {
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, len, n, offsets);
+    return hipGetLastError();
+}
+
+hipError_t launch_walk(const MazeDev* mazes, const int32_t* tgt_slot, const int32_t* tgt_rc,
+                       int32_t n_tgt, int32_t parity, const int32_t* len, const int64_t* offsets,
+                       int32_t* cells, hipStream_t s) {
+    if (n_tgt <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_walk, dim3(grid_for(n_tgt, 64)), dim3(64), 0, s, mazes, tgt_slot, tgt_rc,
+                       n_tgt, parity, len, offsets, cells);
+    return hipGetLastError();
+}
+
+hipError_t launch_activity(const MazeDev* mazes, int32_t slot, int32_t H, int32_t W,
+                           int32_t parity, int32_t offset, int32_t* dst, int64_t dpitch,
+                           hipStream_t s) {
+    const int32_t col_blocks = (W + 255) / 256;
+    const int64_t blocks = (int64_t)H * col_blocks;
+    hipLaunchKernelGGL(k_activity, dim3((uint32_t)blocks), dim3(256), 0, s, mazes, slot, parity,
+                       offset, dst, dpitch, col_blocks);
+    return hipGetLastError();
+}
+
+hipError_t launch_selftest(int32_t* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_selftest, dim3(1), dim3(64), 0, s, out);
+    return hipGetLastError();
+}
+
+int sweep_max_waves_per_cu(int T) {
+    int blocks = 0;
+    hipError_t e = hipErrorInvalidValue;
+    switch (T) {
+        case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_sweep<4>, kBlockThreads, 0); break;
+        case 8: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_sweep<8>, kBlockThreads, 0); break;
+        case 12: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_sweep<12>, kBlockThreads, 0); break;
+        case 16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_sweep<16>, kBlockThreads, 0); break;
+        default: break;
+    }
+    if (e != hipSuccess || blocks < 1) blocks = 1;
+    return blocks * kWavesPerBlock;
+}
+
+}  // namespace omap

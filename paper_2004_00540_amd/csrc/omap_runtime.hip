@@ -1,0 +1,1336 @@
+// Host runtime of the oMAP planner: the multi-maze tile scheduler (Solver)
+// behind the single-maze plan, the batch and the serving engine, and the C ABI
+// declared in include/omap.h.
+//
+// All device work of a handle is ordered on one HIP stream.  A propagation is a
+// sequence of rounds; one round is three launches: the tile sweep (T layers on
+// every scheduled tile), the schedule build (next round's tile list from the
+// change flags) and a per-maze update (counters, convergence).  The host reads
+// the scheduled-tile count back only every few rounds, so the device never
+// waits for a per-layer host handshake (the paper's appendix measures that
+// handshake as the dominant cost of running one layer per call).
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <new>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "omap.h"
+#include "omap_internal.h"
+
+namespace omap {
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+
+static thread_local std::string g_last_error = "no error";
+
+static omap_status_t fail(omap_status_t st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = std::string(omap_status_string(st)) + ": " + buf;
+    return st;
+}
+
+#define HIP_TRY(expr)                                                                   \
+    do {                                                                                \
+        hipError_t _e = (expr);                                                         \
+        if (_e != hipSuccess)                                                           \
+            return fail(_e == hipErrorOutOfMemory ? OMAP_ERR_OUT_OF_MEMORY : OMAP_ERR_HIP, \
+                        "%s failed: %s", #expr, hipGetErrorString(_e));                 \
+    } while (0)
+
+#define OK_TRY(expr)                         \
+    do {                                     \
+        omap_status_t _s = (expr);           \
+        if (_s != OMAP_OK) return _s;        \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// options
+// ---------------------------------------------------------------------------
+
+struct Options {
+    int T = 16;          // layers per tile visit
+    int TH = 64;         // interior rows per tile
+    int TW = kStripCols - 2 * 16;
+    int dense = 0;
+    int check = 0;       // 0 = adaptive
+};
+
+static omap_status_t resolve_options(const omap_options* o, Options* out) {
+    Options r;
+    if (o) {
+        if (o->temporal_depth != 0) {
+            if (o->temporal_depth != 4 && o->temporal_depth != 8 && o->temporal_depth != 12 &&
+                o->temporal_depth != 16)
+                return fail(OMAP_ERR_INVALID_ARG, "temporal_depth must be 4, 8, 12 or 16 (got %d)",
+                            o->temporal_depth);
+            r.T = o->temporal_depth;
+        }
+        if (o->tile_rows != 0) {
+            if (o->tile_rows < 2 || o->tile_rows > 4096 || (o->tile_rows & 1))
+                return fail(OMAP_ERR_INVALID_ARG, "tile_rows must be even in [2, 4096] (got %d)",
+                            o->tile_rows);
+            r.TH = o->tile_rows;
+        }
+        if (o->schedule != OMAP_SCHEDULE_ACTIVE && o->schedule != OMAP_SCHEDULE_DENSE)
+            return fail(OMAP_ERR_INVALID_ARG, "schedule must be ACTIVE or DENSE (got %d)", o->schedule);
+        r.dense = o->schedule == OMAP_SCHEDULE_DENSE;
+        if (o->check_interval < 0) return fail(OMAP_ERR_INVALID_ARG, "check_interval < 0");
+        r.check = o->check_interval;
+    }
+    if (r.TH < r.T)
+        return fail(OMAP_ERR_INVALID_ARG, "tile_rows (%d) must be >= temporal_depth (%d)", r.TH, r.T);
+    r.TW = kStripCols - 2 * r.T;
+    *out = r;
+    return OMAP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// device memory: direct allocation or a sub-allocated arena
+// ---------------------------------------------------------------------------
+
+class DeviceMemory {
+   public:
+    virtual ~DeviceMemory() {}
+    virtual void* alloc(size_t bytes) = 0;   // nullptr on failure
+    virtual void release(void* p) = 0;
+};
+
+class DirectMemory : public DeviceMemory {
+   public:
+    void* alloc(size_t bytes) override {
+        void* p = nullptr;
+        if (hipMalloc(&p, bytes ? bytes : 256) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        return p;
+    }
+    void release(void* p) override {
+        if (p) (void)hipFree(p);
+    }
+};
+
+// One hipMalloc of the whole budget, carved into 256-byte aligned blocks by a
+// best-fit free list.  Reuse after release is safe in stream order because all
+// work of the owner runs on one stream.
+class ArenaMemory : public DeviceMemory {
+   public:
+    ~ArenaMemory() override {
+        if (base_) (void)hipFree(base_);
+    }
+    bool init(size_t bytes) {
+        bytes = (bytes + 255) & ~size_t(255);
+        if (hipMalloc(&base_, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            base_ = nullptr;
+            return false;
+        }
+        size_ = bytes;
+        free_[0] = bytes;
+        return true;
+    }
+    void* alloc(size_t bytes) override {
+        bytes = (bytes + 255) & ~size_t(255);
+        if (bytes == 0) bytes = 256;
+        auto best = free_.end();
+        for (auto it = free_.begin(); it != free_.end(); ++it)
+            if (it->second >= bytes && (best == free_.end() || it->second < best->second)) best = it;
+        if (best == free_.end()) return nullptr;
+        const size_t off = best->first, len = best->second;
+        free_.erase(best);
+        if (len > bytes) free_[off + bytes] = len - bytes;
+        used_[off] = bytes;
+        in_use_ += bytes;
+        return static_cast<char*>(base_) + off;
+    }
+    void release(void* p) override {
+        if (!p) return;
+        const size_t off = static_cast<char*>(p) - static_cast<char*>(base_);
+        auto u = used_.find(off);
+        if (u == used_.end()) return;
+        size_t start = off, len = u->second;
+        in_use_ -= len;
+        used_.erase(u);
+        auto nx = free_.lower_bound(start);
+        if (nx != free_.end() && nx->first == start + len) {
+            len += nx->second;
+            nx = free_.erase(nx);
+        }
+        if (nx != free_.begin()) {
+            auto pv = std::prev(nx);
+            if (pv->first + pv->second == start) {
+                start = pv->first;
+                len += pv->second;
+                free_.erase(pv);
+            }
+        }
+        free_[start] = len;
+    }
+    size_t size() const { return size_; }
+    size_t in_use() const { return in_use_; }
+
+   private:
+    void* base_ = nullptr;
+    size_t size_ = 0, in_use_ = 0;
+    std::map<size_t, size_t> free_;   // offset -> length
+    std::map<size_t, size_t> used_;
+};
+
+// ---------------------------------------------------------------------------
+// geometry
+// ---------------------------------------------------------------------------
+
+struct Geometry {
+    int32_t H, W, pitch, mpitch, tiles_x, tiles_y;
+    int64_t v_bytes, m_bytes;
+};
+
+static Geometry make_geometry(int32_t H, int32_t W, const Options& o) {
+    Geometry g;
+    g.H = H;
+    g.W = W;
+    g.pitch = (W + 63) / 64 * 64;
+    g.mpitch = g.pitch / 32;
+    g.tiles_x = (W + o.TW - 1) / o.TW;
+    g.tiles_y = (H + o.TH - 1) / o.TH;
+    g.v_bytes = (int64_t)g.pitch * H * 4;
+    g.m_bytes = (int64_t)g.mpitch * H * 4;
+    return g;
+}
+
+static int64_t maze_device_bytes(int32_t H, int32_t W, const Options& o) {
+    const Geometry g = make_geometry(H, W, o);
+    return 2 * g.v_bytes + g.m_bytes + 4096;
+}
+
+static omap_status_t validate_problem(int32_t H, int32_t W, const void* occ,
+                                      const int32_t* src, int32_t n_src, const int32_t* tgt,
+                                      int32_t n_tgt) {
+    if (H < 1 || W < 1) return fail(OMAP_ERR_INVALID_ARG, "height and width must be >= 1 (%d x %d)", H, W);
+    if ((int64_t)H * W >= (int64_t(1) << 31))
+        return fail(OMAP_ERR_TOO_LARGE, "height*width = %lld >= 2^31", (long long)H * W);
+    if (!occ) return fail(OMAP_ERR_INVALID_ARG, "occupancy pointer is NULL");
+    if (n_src < 1) return fail(OMAP_ERR_NO_SOURCES, "at least one source is required");
+    if (!src) return fail(OMAP_ERR_INVALID_ARG, "sources pointer is NULL");
+    if (n_tgt < 0) return fail(OMAP_ERR_INVALID_ARG, "n_targets < 0");
+    if (n_tgt > 0 && !tgt) return fail(OMAP_ERR_INVALID_ARG, "targets pointer is NULL");
+    for (int32_t i = 0; i < n_src; ++i)
+        if (src[2 * i] < 0 || src[2 * i] >= H || src[2 * i + 1] < 0 || src[2 * i + 1] >= W)
+            return fail(OMAP_ERR_SOURCE_OUT_OF_BOUNDS, "source %d at (%d, %d) outside %d x %d", i,
+                        src[2 * i], src[2 * i + 1], H, W);
+    for (int32_t i = 0; i < n_tgt; ++i)
+        if (tgt[2 * i] < 0 || tgt[2 * i] >= H || tgt[2 * i + 1] < 0 || tgt[2 * i + 1] >= W)
+            return fail(OMAP_ERR_TARGET_OUT_OF_BOUNDS, "target %d at (%d, %d) outside %d x %d", i,
+                        tgt[2 * i], tgt[2 * i + 1], H, W);
+    return OMAP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Solver: resident mazes advanced together by tile rounds
+// ---------------------------------------------------------------------------
+
+struct Slot {
+    bool used = false;
+    Geometry g{};
+    int32_t tile_base = 0, n_tiles = 0;
+    int32_t* V[2] = {nullptr, nullptr};
+    uint32_t* mask = nullptr;
+    int32_t* d_src = nullptr;
+    std::vector<int32_t> src, tgt;
+    int32_t K = 0;
+    int64_t L_req = 0;
+    int64_t layers = -1;        // L or L* once finalized
+    int64_t reached = 0;
+    bool started = false, finalized = false;
+};
+
+class Solver {
+   public:
+    hipStream_t stream = nullptr;
+    Options opt;
+    DeviceMemory* mem = nullptr;
+    int32_t cap_slots = 0, cap_tiles = 0;
+    std::vector<Slot> slots;
+    std::map<int32_t, int32_t> free_tiles;   // tile id range begin -> length
+    int32_t tile_hwm = 0;                     // 1 + highest tile id ever handed out
+
+    MazeDev* d_mazes = nullptr;
+    int32_t* d_tile_maze = nullptr;
+    int32_t* d_list[2] = {nullptr, nullptr};
+    int32_t* d_count = nullptr;               // [2]
+    uint8_t* d_flags = nullptr;
+    int32_t *d_changed = nullptr, *d_active = nullptr, *d_state = nullptr;
+    int64_t *d_cells = nullptr, *d_rounds = nullptr, *d_visits = nullptr, *d_cell_visits = nullptr;
+    unsigned long long* d_total_cells = nullptr;
+    int32_t* d_min = nullptr;
+    unsigned long long* d_reached = nullptr;
+    int32_t* d_bad = nullptr;
+    int32_t* d_sel = nullptr;
+    int32_t* h_pinned = nullptr;              // 64 int32 of pinned host scratch
+    void* d_scratch = nullptr;                // grow-only path scratch
+    size_t scratch_bytes = 0;
+
+    int parity = 0;
+    int grid = 0;
+    std::vector<void*> owned;                 // solver-level device allocations
+
+    // profiling of the sweep kernel
+    bool prof = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_events;
+    int64_t prof_launches = 0;
+    double prof_ms = 0;
+    unsigned long long prof_cells0 = 0;
+
+    ~Solver() { destroy(); }
+
+    void destroy() {
+        for (auto& s : slots)
+            if (s.used) free_slot_buffers(s);
+        slots.clear();
+        for (void* p : owned) (void)hipFree(p);
+        owned.clear();
+        if (d_scratch) (void)hipFree(d_scratch);
+        d_scratch = nullptr;
+        scratch_bytes = 0;
+        if (h_pinned) (void)hipHostFree(h_pinned);
+        h_pinned = nullptr;
+        for (auto& e : prof_events) {
+            (void)hipEventDestroy(e.first);
+            (void)hipEventDestroy(e.second);
+        }
+        prof_events.clear();
+    }
+
+    template <class Tp>
+    omap_status_t dalloc(Tp** p, size_t n) {
+        void* q = nullptr;
+        HIP_TRY(hipMalloc(&q, n * sizeof(Tp) + 16));
+        owned.push_back(q);
+        *p = static_cast<Tp*>(q);
+        return OMAP_OK;
+    }
+
+    omap_status_t init(hipStream_t s, const Options& o, DeviceMemory* m, int32_t slots_cap,
+                       int32_t tiles_cap) {
+        stream = s;
+        opt = o;
+        mem = m;
+        cap_slots = slots_cap;
+        cap_tiles = tiles_cap;
+        slots.assign(cap_slots, Slot());
+        free_tiles.clear();
+        free_tiles[0] = cap_tiles;
+        OK_TRY(dalloc(&d_mazes, cap_slots));
+        OK_TRY(dalloc(&d_tile_maze, cap_tiles));
+        OK_TRY(dalloc(&d_list[0], cap_tiles));
+        OK_TRY(dalloc(&d_list[1], cap_tiles));
+        OK_TRY(dalloc(&d_count, 2));
+        OK_TRY(dalloc(&d_flags, cap_tiles));
+        OK_TRY(dalloc(&d_changed, cap_slots));
+        OK_TRY(dalloc(&d_active, cap_slots));
+        OK_TRY(dalloc(&d_state, cap_slots));
+        OK_TRY(dalloc(&d_cells, cap_slots));
+        OK_TRY(dalloc(&d_rounds, cap_slots));
+        OK_TRY(dalloc(&d_visits, cap_slots));
+        OK_TRY(dalloc(&d_cell_visits, cap_slots));
+        OK_TRY(dalloc(&d_total_cells, 1));
+        OK_TRY(dalloc(&d_min, cap_slots));
+        OK_TRY(dalloc(&d_reached, cap_slots));
+        OK_TRY(dalloc(&d_bad, 1));
+        OK_TRY(dalloc(&d_sel, cap_slots));
+        HIP_TRY(hipHostMalloc((void**)&h_pinned, 64 * sizeof(int32_t), hipHostMallocDefault));
+        HIP_TRY(hipMemsetAsync(d_tile_maze, 0xff, sizeof(int32_t) * cap_tiles, stream));
+        HIP_TRY(hipMemsetAsync(d_flags, 0, cap_tiles, stream));
+        HIP_TRY(hipMemsetAsync(d_count, 0, 2 * sizeof(int32_t), stream));
+        HIP_TRY(hipMemsetAsync(d_changed, 0, sizeof(int32_t) * cap_slots, stream));
+        HIP_TRY(hipMemsetAsync(d_active, 0, sizeof(int32_t) * cap_slots, stream));
+        HIP_TRY(hipMemsetAsync(d_state, 0, sizeof(int32_t) * cap_slots, stream));
+        HIP_TRY(hipMemsetAsync(d_cells, 0, sizeof(int64_t) * cap_slots, stream));
+        HIP_TRY(hipMemsetAsync(d_rounds, 0, sizeof(int64_t) * cap_slots, stream));
+        HIP_TRY(hipMemsetAsync(d_visits, 0, sizeof(int64_t) * cap_slots, stream));
+        HIP_TRY(hipMemsetAsync(d_cell_visits, 0, sizeof(int64_t) * cap_slots, stream));
+        HIP_TRY(hipMemsetAsync(d_total_cells, 0, sizeof(unsigned long long), stream));
+        int dev = 0;
+        HIP_TRY(hipGetDevice(&dev));
+        int cus = 0;
+        HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        const int waves = sweep_max_waves_per_cu(opt.T);
+        grid = std::max(1, cus * std::max(1, waves / kWavesPerBlock));
+        const int need = (cap_tiles + kWavesPerBlock - 1) / kWavesPerBlock;
+        grid = std::max(1, std::min(grid, need));
+        HIP_TRY(hipStreamSynchronize(stream));
+        return OMAP_OK;
+    }
+
+    RoundArgs round_args() const {
+        RoundArgs a;
+        a.mazes = d_mazes;
+        a.tile_maze = d_tile_maze;
+        a.n_tile_ids = tile_hwm;
+        a.list_in = d_list[parity];
+        a.count_in = d_count + parity;
+        a.list_out = d_list[parity ^ 1];
+        a.count_out = d_count + (parity ^ 1);
+        a.flags = d_flags;
+        a.maze_changed = d_changed;
+        a.maze_active = d_active;
+        a.maze_cells = d_cells;
+        a.maze_state = d_state;
+        a.maze_rounds = d_rounds;
+        a.maze_visits = d_visits;
+        a.maze_cell_visits = d_cell_visits;
+        a.total_cells = d_total_cells;
+        a.n_slots = cap_slots;
+        a.parity = parity;
+        a.tile_rows = opt.TH;
+        a.tile_cols = opt.TW;
+        a.dense = opt.dense;
+        return a;
+    }
+
+    void free_slot_buffers(Slot& s) {
+        mem->release(s.V[0]);
+        mem->release(s.V[1]);
+        mem->release(s.mask);
+        mem->release(s.d_src);
+        s.V[0] = s.V[1] = nullptr;
+        s.mask = nullptr;
+        s.d_src = nullptr;
+    }
+
+    omap_status_t upload_desc(int32_t k) {
+        const Slot& s = slots[k];
+        MazeDev md;
+        md.H = s.g.H;
+        md.W = s.g.W;
+        md.pitch = s.g.pitch;
+        md.mpitch = s.g.mpitch;
+        md.tiles_x = s.g.tiles_x;
+        md.tiles_y = s.g.tiles_y;
+        md.tile_base = s.tile_base;
+        md.K = s.K;
+        md.V[0] = s.V[0];
+        md.V[1] = s.V[1];
+        md.mask = s.mask;
+        HIP_TRY(hipMemcpyAsync(d_mazes + k, &md, sizeof md, hipMemcpyHostToDevice, stream));
+        HIP_TRY(hipStreamSynchronize(stream));   // md lives on this stack frame
+        return OMAP_OK;
+    }
+
+    bool take_tiles(int32_t n, int32_t* base) {
+        for (auto it = free_tiles.begin(); it != free_tiles.end(); ++it) {
+            if (it->second >= n) {
+                *base = it->first;
+                const int32_t rest = it->second - n, nb = it->first + n;
+                free_tiles.erase(it);
+                if (rest > 0) free_tiles[nb] = rest;
+                tile_hwm = std::max(tile_hwm, *base + n);
+                return true;
+            }
+        }
+        return false;
+    }
+
+    void give_tiles(int32_t base, int32_t n) {
+        auto nx = free_tiles.lower_bound(base);
+        int32_t b = base, len = n;
+        if (nx != free_tiles.end() && nx->first == b + len) {
+            len += nx->second;
+            nx = free_tiles.erase(nx);
+        }
+        if (nx != free_tiles.begin()) {
+            auto pv = std::prev(nx);
+            if (pv->first + pv->second == b) {
+                b = pv->first;
+                len += pv->second;
+                free_tiles.erase(pv);
+            }
+        }
+        free_tiles[b] = len;
+    }
+
+    int32_t free_slot_index() const {
+        for (int32_t k = 0; k < cap_slots; ++k)
+            if (!slots[k].used) return k;
+        return -1;
+    }
+
+    // Pack and validate one maze into slot k (synchronous).
+    omap_status_t pack(int32_t k, const uint8_t* occ_dev, const int32_t* src, int32_t n_src,
+                       const int32_t* tgt, int32_t n_tgt) {
+        Slot& s = slots[k];
+        OK_TRY(validate_problem(s.g.H, s.g.W, occ_dev, src, n_src, tgt, n_tgt));
+        mem->release(s.d_src);
+        s.d_src = static_cast<int32_t*>(mem->alloc(sizeof(int32_t) * 2 * n_src));
+        if (!s.d_src) return fail(OMAP_ERR_OUT_OF_MEMORY, "source list (%d sources)", n_src);
+        HIP_TRY(launch_pack_mask(occ_dev, s.g.H, s.g.W, s.mask, s.g.mpitch, stream));
+        HIP_TRY(hipMemcpyAsync(s.d_src, src, sizeof(int32_t) * 2 * n_src, hipMemcpyHostToDevice, stream));
+        HIP_TRY(hipMemsetAsync(d_bad, 0, sizeof(int32_t), stream));
+        HIP_TRY(launch_check_sources(s.mask, s.g.mpitch, s.d_src, n_src, d_bad, stream));
+        HIP_TRY(hipMemcpyAsync(h_pinned, d_bad, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+        HIP_TRY(hipStreamSynchronize(stream));
+        if (h_pinned[0] != 0)
+            return fail(OMAP_ERR_SOURCE_ON_OBSTACLE, "%d source(s) lie on obstacles", h_pinned[0]);
+        s.src.assign(src, src + 2 * n_src);
+        s.tgt.assign(tgt ? tgt : src, tgt ? tgt + 2 * n_tgt : src);
+        if (!tgt) s.tgt.clear();
+        s.started = s.finalized = false;
+        s.layers = -1;
+        return OMAP_OK;
+    }
+
+    // Allocate slot buffers and a tile id range, then pack (synchronous).
+    omap_status_t add(int32_t H, int32_t W, const uint8_t* occ_dev, const int32_t* src,
+                      int32_t n_src, const int32_t* tgt, int32_t n_tgt, int32_t* slot_out) {
+        OK_TRY(validate_problem(H, W, occ_dev, src, n_src, tgt, n_tgt));
+        const int32_t k = free_slot_index();
+        if (k < 0) return fail(OMAP_ERR_OUT_OF_MEMORY, "no free maze slot (capacity %d)", cap_slots);
+        Slot& s = slots[k];
+        s = Slot();
+        s.g = make_geometry(H, W, opt);
+        const int64_t nt = (int64_t)s.g.tiles_x * s.g.tiles_y;
+        if (nt > cap_tiles || !take_tiles((int32_t)nt, &s.tile_base))
+            return fail(OMAP_ERR_OUT_OF_MEMORY, "no tile ids left for %lld tiles", (long long)nt);
+        s.n_tiles = (int32_t)nt;
+        s.V[0] = static_cast<int32_t*>(mem->alloc(s.g.v_bytes));
+        s.V[1] = static_cast<int32_t*>(mem->alloc(s.g.v_bytes));
+        s.mask = static_cast<uint32_t*>(mem->alloc(s.g.m_bytes));
+        s.used = true;
+        if (!s.V[0] || !s.V[1] || !s.mask) {
+            remove(k);
+            return fail(OMAP_ERR_OUT_OF_MEMORY, "activity and mask buffers for %d x %d", H, W);
+        }
+        omap_status_t st = pack(k, occ_dev, src, n_src, tgt, n_tgt);
+        if (st != OMAP_OK) {
+            const std::string msg = g_last_error;
+            remove(k);
+            g_last_error = msg;
+            return st;
+        }
+        std::vector<int32_t> ids(s.n_tiles, k);
+        HIP_TRY(hipMemcpyAsync(d_tile_maze + s.tile_base, ids.data(), sizeof(int32_t) * ids.size(),
+                               hipMemcpyHostToDevice, stream));
+        OK_TRY(upload_desc(k));
+        *slot_out = k;
+        return OMAP_OK;
+    }
+
+    omap_status_t remove(int32_t k) {
+        Slot& s = slots[k];
+        if (!s.used) return OMAP_OK;
+        if (s.n_tiles > 0) {
+            std::vector<int32_t> ids(s.n_tiles, -1);
+            HIP_TRY(hipMemcpyAsync(d_tile_maze + s.tile_base, ids.data(),
+                                   sizeof(int32_t) * ids.size(), hipMemcpyHostToDevice, stream));
+            const int32_t idle = kMazeIdle;
+            HIP_TRY(hipMemcpyAsync(d_state + k, &idle, sizeof idle, hipMemcpyHostToDevice, stream));
+            HIP_TRY(hipStreamSynchronize(stream));
+            give_tiles(s.tile_base, s.n_tiles);
+        }
+        free_slot_buffers(s);
+        s = Slot();
+        return OMAP_OK;
+    }
+
+    // Reset slot k's activity and seed it for L layers (L < 0: run-time L).
+    // Stream-ordered; the maze joins the schedule at the next round's build.
+    omap_status_t start(int32_t k, int64_t L) {
+        Slot& s = slots[k];
+        if (L < -1) return fail(OMAP_ERR_INVALID_ARG, "max_layers must be >= 0 or OMAP_AUTO_LAYERS");
+        if (L >= 0 && L + 1 > 0x7fffffffLL)
+            return fail(OMAP_ERR_TOO_LARGE, "L + 1 = %lld does not fit int32 activity", (long long)(L + 1));
+        s.L_req = L;
+        s.K = L < 0 ? 0x7fffffff : (int32_t)(L + 1);
+        OK_TRY(upload_desc(k));
+        HIP_TRY(launch_fill(s.V[0], s.g.v_bytes / 4, 0, stream));
+        HIP_TRY(launch_fill(s.V[1], s.g.v_bytes / 4, 0, stream));
+        HIP_TRY(hipMemsetAsync(d_bad, 0, sizeof(int32_t), stream));
+        HIP_TRY(launch_seed(d_mazes, k, s.d_src, (int32_t)(s.src.size() / 2), opt.TH, opt.TW, d_flags,
+                            d_changed, d_bad, stream));
+        const int32_t running = kMazeRunning;
+        const int64_t zero = 0;
+        HIP_TRY(hipMemcpyAsync(d_state + k, &running, sizeof(int32_t), hipMemcpyHostToDevice, stream));
+        HIP_TRY(hipMemcpyAsync(d_rounds + k, &zero, sizeof zero, hipMemcpyHostToDevice, stream));
+        HIP_TRY(hipMemcpyAsync(d_visits + k, &zero, sizeof zero, hipMemcpyHostToDevice, stream));
+        HIP_TRY(hipMemcpyAsync(d_cell_visits + k, &zero, sizeof zero, hipMemcpyHostToDevice, stream));
+        HIP_TRY(hipStreamSynchronize(stream));   // host sources of the copies above
+        s.started = true;
+        s.finalized = false;
+        s.layers = -1;
+        return OMAP_OK;
+    }
+
+    omap_status_t reset_schedule() {
+        HIP_TRY(hipMemsetAsync(d_count + parity, 0, sizeof(int32_t), stream));
+        return OMAP_OK;
+    }
+
+    omap_status_t round() {
+        const RoundArgs a = round_args();
+        if (prof) {
+            std::pair<hipEvent_t, hipEvent_t> ev;
+            HIP_TRY(hipEventCreate(&ev.first));
+            HIP_TRY(hipEventCreate(&ev.second));
+            HIP_TRY(hipEventRecord(ev.first, stream));
+            HIP_TRY(launch_sweep(opt.T, a, grid, stream));
+            HIP_TRY(hipEventRecord(ev.second, stream));
+            prof_events.push_back(ev);
+        } else {
+            HIP_TRY(launch_sweep(opt.T, a, grid, stream));
+        }
+        HIP_TRY(launch_build(a, stream));
+        HIP_TRY(launch_update(a, stream));
+        parity ^= 1;
+        return OMAP_OK;
+    }
+
+    omap_status_t scheduled_count(int32_t* n) {
+        HIP_TRY(hipMemcpyAsync(h_pinned, d_count + parity, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+        HIP_TRY(hipStreamSynchronize(stream));
+        *n = h_pinned[0];
+        return OMAP_OK;
+    }
+
+    // Rounds until no tile is scheduled (every started maze converged).
+    omap_status_t run_to_convergence() {
+        int g = opt.check > 0 ? opt.check : 2;
+        for (;;) {
+            for (int i = 0; i < g; ++i) OK_TRY(round());
+            int32_t n = 0;
+            OK_TRY(scheduled_count(&n));
+            if (n == 0) break;
+            if (opt.check == 0) g = std::min(g * 2, 64);
+        }
+        return OMAP_OK;
+    }
+
+    // Smallest positive activity and reached count of the selected slots
+    // (sel == nullptr: every slot), then layers = L or K - min (synchronous).
+    omap_status_t finalize(const std::vector<int32_t>& which) {
+        std::vector<int32_t> mins(cap_slots, 0x7fffffff);
+        HIP_TRY(hipMemcpyAsync(d_min, mins.data(), sizeof(int32_t) * cap_slots, hipMemcpyHostToDevice, stream));
+        HIP_TRY(hipMemsetAsync(d_reached, 0, sizeof(unsigned long long) * cap_slots, stream));
+        std::vector<int32_t> sel(cap_slots, 0);
+        for (int32_t k : which) sel[k] = 1;
+        HIP_TRY(hipMemcpyAsync(d_sel, sel.data(), sizeof(int32_t) * cap_slots, hipMemcpyHostToDevice, stream));
+        int32_t lo = tile_hwm, hi = 0;
+        for (int32_t k : which) {
+            lo = std::min(lo, slots[k].tile_base);
+            hi = std::max(hi, slots[k].tile_base + slots[k].n_tiles);
+        }
+        HIP_TRY(launch_reduce(d_mazes, d_tile_maze, lo, hi, d_sel, opt.TH, opt.TW, parity, d_min,
+                              d_reached, stream));
+        std::vector<unsigned long long> reached(cap_slots);
+        HIP_TRY(hipMemcpyAsync(mins.data(), d_min, sizeof(int32_t) * cap_slots, hipMemcpyDeviceToHost, stream));
+        HIP_TRY(hipMemcpyAsync(reached.data(), d_reached, sizeof(unsigned long long) * cap_slots,
+                               hipMemcpyDeviceToHost, stream));
+        HIP_TRY(hipStreamSynchronize(stream));
+        for (int32_t k : which) {
+            Slot& s = slots[k];
+            s.layers = s.L_req >= 0 ? s.L_req : (int64_t)s.K - mins[k];
+            s.reached = (int64_t)reached[k];
+            s.finalized = true;
+        }
+        return OMAP_OK;
+    }
+
+    // Grow-only device scratch (synchronizes only when it has to grow).
+    omap_status_t scratch(size_t bytes, char** out) {
+        if (bytes > scratch_bytes) {
+            HIP_TRY(hipStreamSynchronize(stream));
+            if (d_scratch) (void)hipFree(d_scratch);
+            d_scratch = nullptr;
+            scratch_bytes = 0;
+            const size_t want = std::max(bytes, scratch_bytes * 2);
+            HIP_TRY(hipMalloc(&d_scratch, want));
+            scratch_bytes = want;
+        }
+        *out = static_cast<char*>(d_scratch);
+        return OMAP_OK;
+    }
+
+    omap_status_t ensure_finalized(int32_t k) {
+        if (slots[k].finalized) return OMAP_OK;
+        std::vector<int32_t> one{k};
+        return finalize(one);
+    }
+
+    omap_status_t info(int32_t k, omap_propagate_info* out) {
+        OK_TRY(ensure_finalized(k));
+        int64_t v[3];
+        HIP_TRY(hipMemcpyAsync(&v[0], d_rounds + k, sizeof(int64_t), hipMemcpyDeviceToHost, stream));
+        HIP_TRY(hipMemcpyAsync(&v[1], d_visits + k, sizeof(int64_t), hipMemcpyDeviceToHost, stream));
+        HIP_TRY(hipMemcpyAsync(&v[2], d_cell_visits + k, sizeof(int64_t), hipMemcpyDeviceToHost, stream));
+        HIP_TRY(hipStreamSynchronize(stream));
+        const Slot& s = slots[k];
+        out->layers = s.layers;
+        out->rounds = v[0];
+        out->sweeps_executed = v[0] * opt.T;
+        out->tile_visits = v[1];
+        out->reached_cells = s.reached;
+        return OMAP_OK;
+    }
+
+    // Paths of the targets of `which` (in that order), written to caller
+    // buffers (device).  len/off/cells may be device pointers owned by the
+    // caller; scratch comes from `mem`.
+    omap_status_t extract(const std::vector<int32_t>& which, int32_t* len_out, int64_t* off_out,
+                          int32_t* cells_out, int64_t capacity, int64_t* needed, bool host_out) {
+        std::vector<int32_t> tslot, trc;
+        for (int32_t k : which) {
+            const Slot& s = slots[k];
+            if (!s.started) return fail(OMAP_ERR_NOT_PROPAGATED, "maze %d has not been propagated", k);
+            const int32_t n = (int32_t)(s.tgt.size() / 2);
+            tslot.insert(tslot.end(), n, k);
+            trc.insert(trc.end(), s.tgt.begin(), s.tgt.end());
+        }
+        const int32_t n = (int32_t)tslot.size();
+        auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
+        const size_t b_slot = up(sizeof(int32_t) * (n + 1)), b_rc = up(sizeof(int32_t) * (2 * n + 2));
+        const size_t b_len = up(sizeof(int32_t) * (n + 1)), b_off = up(sizeof(int64_t) * (n + 1));
+        char* base = nullptr;
+        OK_TRY(scratch(b_slot + b_rc + b_len + b_off, &base));
+        int32_t* d_tslot = reinterpret_cast<int32_t*>(base);
+        int32_t* d_trc = reinterpret_cast<int32_t*>(base + b_slot);
+        int32_t* d_len = reinterpret_cast<int32_t*>(base + b_slot + b_rc);
+        int64_t* d_off = reinterpret_cast<int64_t*>(base + b_slot + b_rc + b_len);
+        if (n > 0) {
+            HIP_TRY(hipMemcpyAsync(d_tslot, tslot.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, stream));
+            HIP_TRY(hipMemcpyAsync(d_trc, trc.data(), sizeof(int32_t) * 2 * n, hipMemcpyHostToDevice, stream));
+            HIP_TRY(launch_path_lengths(d_mazes, d_tslot, d_trc, n, parity, d_len, stream));
+        }
+        HIP_TRY(launch_scan_offsets(d_len, n, d_off, stream));
+        HIP_TRY(hipMemcpyAsync(h_pinned, d_off + n, sizeof(int64_t), hipMemcpyDeviceToHost, stream));
+        HIP_TRY(hipStreamSynchronize(stream));   // also retires the host sources of the uploads
+        int64_t total = 0;
+        std::memcpy(&total, h_pinned, sizeof total);
+        if (needed) *needed = total;
+        if (cells_out == nullptr || capacity < total)
+            return fail(OMAP_ERR_BUFFER_TOO_SMALL, "paths need %lld cells, capacity %lld",
+                        (long long)total, (long long)capacity);
+        int32_t* walk_dst = cells_out;
+        if (host_out) {
+            // the walk writes into scratch behind the offsets, then everything goes to host
+            const size_t b_cells = up(sizeof(int32_t) * (size_t)(total + 1));
+            char* base2 = nullptr;
+            OK_TRY(scratch(b_slot + b_rc + b_len + b_off + b_cells, &base2));
+            if (base2 != base) {   // scratch moved: lengths/offsets must be recomputed
+                d_tslot = reinterpret_cast<int32_t*>(base2);
+                d_trc = reinterpret_cast<int32_t*>(base2 + b_slot);
+                d_len = reinterpret_cast<int32_t*>(base2 + b_slot + b_rc);
+                d_off = reinterpret_cast<int64_t*>(base2 + b_slot + b_rc + b_len);
+                if (n > 0) {
+                    HIP_TRY(hipMemcpyAsync(d_tslot, tslot.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, stream));
+                    HIP_TRY(hipMemcpyAsync(d_trc, trc.data(), sizeof(int32_t) * 2 * n, hipMemcpyHostToDevice, stream));
+                    HIP_TRY(launch_path_lengths(d_mazes, d_tslot, d_trc, n, parity, d_len, stream));
+                }
+                HIP_TRY(launch_scan_offsets(d_len, n, d_off, stream));
+                base = base2;
+            }
+            walk_dst = reinterpret_cast<int32_t*>(base + b_slot + b_rc + b_len + b_off);
+        }
+        HIP_TRY(launch_walk(d_mazes, d_tslot, d_trc, n, parity, d_len, d_off, walk_dst, stream));
+        const hipMemcpyKind kind = host_out ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
+        if (n > 0) HIP_TRY(hipMemcpyAsync(len_out, d_len, sizeof(int32_t) * n, kind, stream));
+        HIP_TRY(hipMemcpyAsync(off_out, d_off, sizeof(int64_t) * (n + 1), kind, stream));
+        if (host_out && total > 0)
+            HIP_TRY(hipMemcpyAsync(cells_out, walk_dst, sizeof(int32_t) * total, kind, stream));
+        HIP_TRY(hipStreamSynchronize(stream));
+        return OMAP_OK;
+    }
+
+    omap_status_t activity(int32_t k, int32_t* dst, int64_t dpitch) {
+        Slot& s = slots[k];
+        if (!dst) return fail(OMAP_ERR_INVALID_ARG, "destination is NULL");
+        if (dpitch < s.g.W) return fail(OMAP_ERR_INVALID_ARG, "pitch %lld < width %d", (long long)dpitch, s.g.W);
+        if (!s.started) return fail(OMAP_ERR_NOT_PROPAGATED, "maze %d has not been propagated", k);
+        OK_TRY(ensure_finalized(k));
+        const int64_t off = (int64_t)s.K - s.layers - 1;
+        HIP_TRY(launch_activity(d_mazes, k, s.g.H, s.g.W, parity, (int32_t)off, dst, dpitch, stream));
+        return OMAP_OK;
+    }
+
+    omap_status_t profile(bool on) {
+        if (on) {
+            for (auto& e : prof_events) {
+                (void)hipEventDestroy(e.first);
+                (void)hipEventDestroy(e.second);
+            }
+            prof_events.clear();
+            prof_launches = 0;
+            prof_ms = 0;
+            HIP_TRY(hipMemcpyAsync(&prof_cells0, d_total_cells, sizeof prof_cells0, hipMemcpyDeviceToHost, stream));
+            HIP_TRY(hipStreamSynchronize(stream));
+        }
+        prof = on;
+        return OMAP_OK;
+    }
+
+    omap_status_t profile_read(int64_t* launches, double* ms, int64_t* cell_updates) {
+        HIP_TRY(hipStreamSynchronize(stream));
+        for (auto& e : prof_events) {
+            float t = 0;
+            HIP_TRY(hipEventElapsedTime(&t, e.first, e.second));
+            prof_ms += t;
+            ++prof_launches;
+            (void)hipEventDestroy(e.first);
+            (void)hipEventDestroy(e.second);
+        }
+        prof_events.clear();
+        unsigned long long cells = 0;
+        HIP_TRY(hipMemcpy(&cells, d_total_cells, sizeof cells, hipMemcpyDeviceToHost));
+        if (launches) *launches = prof_launches;
+        if (ms) *ms = prof_ms;
+        if (cell_updates) *cell_updates = (int64_t)(cells - prof_cells0) * opt.T;
+        return OMAP_OK;
+    }
+};
+
+// ---------------------------------------------------------------------------
+// handles
+// ---------------------------------------------------------------------------
+
+}  // namespace omap
+
+struct omap_plan_s {
+    omap::DirectMemory mem;
+    omap::Solver solver;
+    int32_t slot = -1;
+    bool propagated = false;
+};
+
+struct omap_batch_s {
+    omap::DirectMemory mem;
+    omap::Solver solver;
+    std::vector<int32_t> slots;
+    bool propagated = false;
+};
+
+namespace omap {
+
+struct Query {
+    int64_t id = 0;
+    int32_t H = 0, W = 0;
+    std::vector<uint8_t> occ;
+    std::vector<int32_t> src, tgt;
+    int64_t L = -1;
+    int32_t state = OMAP_QUERY_QUEUED;
+    int32_t slot = -1;
+    int64_t bytes = 0;
+    std::string error;
+    std::vector<int32_t> len;
+    std::vector<int64_t> off;
+    std::vector<int32_t> cells;
+    omap_propagate_info info{};
+};
+
+}  // namespace omap
+
+struct omap_engine_s {
+    omap::ArenaMemory mem;
+    omap::Solver solver;
+    int64_t budget = 0;
+    int32_t max_slots = 0;
+    int64_t next_id = 1;
+    int64_t done_total = 0;
+    std::deque<int64_t> waiting;
+    std::unordered_map<int64_t, omap::Query> queries;
+    std::vector<int64_t> resident;   // query ids
+};
+
+namespace omap {
+
+static int64_t query_bytes(const Query& q, const Options& o) {
+    // activity ping-pong + mask + staging of the occupancy + path scratch
+    const int64_t nt = (int64_t)q.tgt.size() / 2;
+    return maze_device_bytes(q.H, q.W, o) + (int64_t)q.H * q.W + 256 +
+           nt * 64 + nt * 4 * ((int64_t)q.H + q.W) + 4096;
+}
+
+static omap_status_t engine_admit(omap_engine_s* e) {
+    while (!e->waiting.empty() && (int32_t)e->resident.size() < e->max_slots) {
+        Query& q = e->queries[e->waiting.front()];
+        if ((int64_t)e->mem.in_use() + q.bytes > (int64_t)e->mem.size()) break;   // wait for memory
+        e->waiting.pop_front();
+        void* occ_dev = e->mem.alloc(q.occ.size());
+        if (!occ_dev) {
+            e->waiting.push_front(q.id);
+            break;
+        }
+        HIP_TRY(hipMemcpyAsync(occ_dev, q.occ.data(), q.occ.size(), hipMemcpyHostToDevice, e->solver.stream));
+        int32_t slot = -1;
+        omap_status_t st = e->solver.add(q.H, q.W, static_cast<uint8_t*>(occ_dev), q.src.data(),
+                                         (int32_t)(q.src.size() / 2), q.tgt.empty() ? nullptr : q.tgt.data(),
+                                         (int32_t)(q.tgt.size() / 2), &slot);
+        e->mem.release(occ_dev);
+        if (st != OMAP_OK) {
+            if (st == OMAP_ERR_OUT_OF_MEMORY && !e->resident.empty()) {
+                e->waiting.push_front(q.id);   // retry when something retires
+                break;
+            }
+            q.state = OMAP_QUERY_FAILED;
+            q.error = g_last_error;
+            ++e->done_total;
+            continue;
+        }
+        st = e->solver.start(slot, q.L);
+        if (st != OMAP_OK) {
+            q.state = OMAP_QUERY_FAILED;
+            q.error = g_last_error;
+            e->solver.remove(slot);
+            ++e->done_total;
+            continue;
+        }
+        q.slot = slot;
+        q.state = OMAP_QUERY_RUNNING;
+        q.occ.clear();
+        q.occ.shrink_to_fit();
+        e->resident.push_back(q.id);
+    }
+    return OMAP_OK;
+}
+
+static omap_status_t engine_retire(omap_engine_s* e) {
+    if (e->resident.empty()) return OMAP_OK;
+    std::vector<int32_t> states(e->solver.cap_slots);
+    HIP_TRY(hipMemcpyAsync(states.data(), e->solver.d_state, sizeof(int32_t) * states.size(),
+                           hipMemcpyDeviceToHost, e->solver.stream));
+    HIP_TRY(hipStreamSynchronize(e->solver.stream));
+    std::vector<int64_t> keep;
+    std::vector<int32_t> done_slots;
+    std::vector<int64_t> done_ids;
+    for (int64_t id : e->resident) {
+        Query& q = e->queries[id];
+        if (states[q.slot] == kMazeDone) {
+            done_slots.push_back(q.slot);
+            done_ids.push_back(id);
+        } else {
+            keep.push_back(id);
+        }
+    }
+    if (done_slots.empty()) return OMAP_OK;
+    OK_TRY(e->solver.finalize(done_slots));
+    for (size_t i = 0; i < done_ids.size(); ++i) {
+        Query& q = e->queries[done_ids[i]];
+        const int32_t k = done_slots[i];
+        const int32_t nt = (int32_t)(q.tgt.size() / 2);
+        q.len.assign(nt, 0);
+        q.off.assign(nt + 1, 0);
+        int64_t needed = 0;
+        std::vector<int32_t> one{k};
+        omap_status_t st = e->solver.extract(one, q.len.data(), q.off.data(), nullptr, 0, &needed, true);
+        if (st == OMAP_ERR_BUFFER_TOO_SMALL) {
+            q.cells.assign(needed, 0);
+            st = e->solver.extract(one, q.len.data(), q.off.data(), q.cells.data(), needed, &needed, true);
+        }
+        if (st != OMAP_OK) return st;
+        OK_TRY(e->solver.info(k, &q.info));
+        OK_TRY(e->solver.remove(k));
+        q.slot = -1;
+        q.state = OMAP_QUERY_DONE;
+        ++e->done_total;
+    }
+    e->resident.swap(keep);
+    return OMAP_OK;
+}
+
+}  // namespace omap
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+
+using namespace omap;
+
+#define API_GUARD_BEGIN try {
+#define API_GUARD_END                                                              \
+    }                                                                              \
+    catch (const std::bad_alloc&) {                                                \
+        return fail(OMAP_ERR_OUT_OF_MEMORY, "host allocation failed");             \
+    }                                                                              \
+    catch (...) {                                                                  \
+        return fail(OMAP_ERR_HIP, "unexpected exception");                         \
+    }
+
+extern "C" {
+
+const char* omap_version(void) { return "omap-gfx950 0.1"; }
+
+const char* omap_last_error(void) { return g_last_error.c_str(); }
+
+const char* omap_status_string(omap_status_t s) {
+    switch (s) {
+        case OMAP_OK: return "OMAP_OK";
+        case OMAP_ERR_INVALID_ARG: return "OMAP_ERR_INVALID_ARG";
+        case OMAP_ERR_TOO_LARGE: return "OMAP_ERR_TOO_LARGE";
+        case OMAP_ERR_SOURCE_OUT_OF_BOUNDS: return "OMAP_ERR_SOURCE_OUT_OF_BOUNDS";
+        case OMAP_ERR_SOURCE_ON_OBSTACLE: return "OMAP_ERR_SOURCE_ON_OBSTACLE";
+        case OMAP_ERR_NO_SOURCES: return "OMAP_ERR_NO_SOURCES";
+        case OMAP_ERR_TARGET_OUT_OF_BOUNDS: return "OMAP_ERR_TARGET_OUT_OF_BOUNDS";
+        case OMAP_ERR_NOT_PROPAGATED: return "OMAP_ERR_NOT_PROPAGATED";
+        case OMAP_ERR_BUFFER_TOO_SMALL: return "OMAP_ERR_BUFFER_TOO_SMALL";
+        case OMAP_ERR_OUT_OF_MEMORY: return "OMAP_ERR_OUT_OF_MEMORY";
+        case OMAP_ERR_HIP: return "OMAP_ERR_HIP";
+        case OMAP_ERR_NOT_FOUND: return "OMAP_ERR_NOT_FOUND";
+        case OMAP_ERR_BUSY: return "OMAP_ERR_BUSY";
+    }
+    return "OMAP_ERR_UNKNOWN";
+}
+
+omap_status_t omap_plan_create(omap_plan_t* out, int32_t height, int32_t width,
+                               const uint8_t* occupancy_dev, const int32_t* sources_host,
+                               int32_t n_sources, const int32_t* targets_host, int32_t n_targets,
+                               const omap_options* opts, void* stream) {
+    API_GUARD_BEGIN
+    if (!out) return fail(OMAP_ERR_INVALID_ARG, "out is NULL");
+    OK_TRY(validate_problem(height, width, occupancy_dev, sources_host, n_sources, targets_host, n_targets));
+    Options o;
+    OK_TRY(resolve_options(opts, &o));
+    std::unique_ptr<omap_plan_s> p(new omap_plan_s());
+    const Geometry g = make_geometry(height, width, o);
+    OK_TRY(p->solver.init(static_cast<hipStream_t>(stream), o, &p->mem, 1, g.tiles_x * g.tiles_y));
+    OK_TRY(p->solver.add(height, width, occupancy_dev, sources_host, n_sources, targets_host, n_targets, &p->slot));
+    *out = p.release();
+    return OMAP_OK;
+    API_GUARD_END
+}
+
+omap_status_t omap_plan_load(omap_plan_t plan, const uint8_t* occupancy_dev,
+                             const int32_t* sources_host, int32_t n_sources,
+                             const int32_t* targets_host, int32_t n_targets) {
+    API_GUARD_BEGIN
+    if (!plan) return fail(OMAP_ERR_INVALID_ARG, "plan is NULL");
+    plan->propagated = false;
+    return plan->solver.pack(plan->slot, occupancy_dev, sources_host, n_sources, targets_host, n_targets);
+    API_GUARD_END
+}
+
+static void fill_info_basic(omap_propagate_info* info) { std::memset(info, 0, sizeof *info); }
+
+omap_status_t omap_propagate(omap_plan_t plan, int64_t max_layers, omap_propagate_info* info) {
+    API_GUARD_BEGIN
+    if (!plan) return fail(OMAP_ERR_INVALID_ARG, "plan is NULL");
+    Solver& s = plan->solver;
+    plan->propagated = false;
+    OK_TRY(s.reset_schedule());
+    OK_TRY(s.start(plan->slot, max_layers));
+    OK_TRY(s.run_to_convergence());
+    plan->propagated = true;
+    if (info) {
+        fill_info_basic(info);
+        OK_TRY(s.info(plan->slot, info));
+    }
+    return OMAP_OK;
+    API_GUARD_END
+}
+
+omap_status_t omap_get_activity(omap_plan_t plan, int32_t* dst_dev, int64_t dst_pitch_elems) {
+    API_GUARD_BEGIN
+    if (!plan) return fail(OMAP_ERR_INVALID_ARG, "plan is NULL");
+    if (!plan->propagated) return fail(OMAP_ERR_NOT_PROPAGATED, "call omap_propagate first");
+    return plan->solver.activity(plan->slot, dst_dev, dst_pitch_elems);
+    API_GUARD_END
+}
+
+omap_status_t omap_extract_paths(omap_plan_t plan, int32_t* len_dev, int64_t* offsets_dev,
+                                 int32_t* cells_dev, int64_t cells_capacity,
+                                 int64_t* cells_needed_host) {
+    API_GUARD_BEGIN
+    if (!plan) return fail(OMAP_ERR_INVALID_ARG, "plan is NULL");
+    if (!plan->propagated) return fail(OMAP_ERR_NOT_PROPAGATED, "call omap_propagate first");
+    const int32_t nt = (int32_t)(plan->solver.slots[plan->slot].tgt.size() / 2);
+    if (!offsets_dev || (nt > 0 && !len_dev)) return fail(OMAP_ERR_INVALID_ARG, "len/offsets pointer is NULL");
+    std::vector<int32_t> one{plan->slot};
+    return plan->solver.extract(one, len_dev, offsets_dev, cells_dev, cells_capacity, cells_needed_host, false);
+    API_GUARD_END
+}
+
+omap_status_t omap_plan_destroy(omap_plan_t plan) {
+    API_GUARD_BEGIN
+    if (!plan) return OMAP_OK;
+    (void)hipStreamSynchronize(plan->solver.stream);
+    delete plan;
+    return OMAP_OK;
+    API_GUARD_END
+}
+
+// ---- batch -----------------------------------------------------------------
+
+omap_status_t omap_batch_create(omap_batch_t* out, const omap_maze_desc* mazes, int32_t n_mazes,
+                                const omap_options* opts, void* stream) {
+    API_GUARD_BEGIN
+    if (!out || !mazes || n_mazes < 1) return fail(OMAP_ERR_INVALID_ARG, "need out and n_mazes >= 1");
+    Options o;
+    OK_TRY(resolve_options(opts, &o));
+    int64_t tiles = 0;
+    for (int32_t i = 0; i < n_mazes; ++i) {
+        const omap_maze_desc& d = mazes[i];
+        omap_status_t st = validate_problem(d.height, d.width, d.occupancy_dev, d.sources_host,
+                                            d.n_sources, d.targets_host, d.n_targets);
+        if (st != OMAP_OK) {
+            g_last_error += " (maze " + std::to_string(i) + ")";
+            return st;
+        }
+        const Geometry g = make_geometry(d.height, d.width, o);
+        tiles += (int64_t)g.tiles_x * g.tiles_y;
+    }
+    if (tiles >= (int64_t(1) << 31)) return fail(OMAP_ERR_TOO_LARGE, "too many tiles");
+    std::unique_ptr<omap_batch_s> b(new omap_batch_s());
+    OK_TRY(b->solver.init(static_cast<hipStream_t>(stream), o, &b->mem, n_mazes, (int32_t)tiles));
+    for (int32_t i = 0; i < n_mazes; ++i) {
+        const omap_maze_desc& d = mazes[i];
+        int32_t slot = -1;
+        omap_status_t st = b->solver.add(d.height, d.width, d.occupancy_dev, d.sources_host, d.n_sources,
+                                         d.targets_host, d.n_targets, &slot);
+        if (st != OMAP_OK) {
+            g_last_error += " (maze " + std::to_string(i) + ")";
+            return st;
+        }
+        b->slots.push_back(slot);
+    }
+    *out = b.release();
+    return OMAP_OK;
+    API_GUARD_END
+}
+
+omap_status_t omap_batch_propagate(omap_batch_t batch, const int64_t* max_layers_host,
+                                   omap_propagate_info* infos_host) {
+    API_GUARD_BEGIN
+    if (!batch) return fail(OMAP_ERR_INVALID_ARG, "batch is NULL");
+    Solver& s = batch->solver;
+    batch->propagated = false;
+    OK_TRY(s.reset_schedule());
+    for (size_t i = 0; i < batch->slots.size(); ++i)
+        OK_TRY(s.start(batch->slots[i], max_layers_host ? max_layers_host[i] : OMAP_AUTO_LAYERS));
+    OK_TRY(s.run_to_convergence());
+    batch->propagated = true;
+    if (infos_host) {
+        OK_TRY(s.finalize(batch->slots));
+        for (size_t i = 0; i < batch->slots.size(); ++i) {
+            fill_info_basic(&infos_host[i]);
+            OK_TRY(s.info(batch->slots[i], &infos_host[i]));
+        }
+    }
+    return OMAP_OK;
+    API_GUARD_END
+}
+
+omap_status_t omap_batch_get_activity(omap_batch_t batch, int32_t index, int32_t* dst_dev,
+                                      int64_t dst_pitch_elems) {
+    API_GUARD_BEGIN
+    if (!batch) return fail(OMAP_ERR_INVALID_ARG, "batch is NULL");
+    if (index < 0 || index >= (int32_t)batch->slots.size())
+        return fail(OMAP_ERR_INVALID_ARG, "maze index %d out of range", index);
+    if (!batch->propagated) return fail(OMAP_ERR_NOT_PROPAGATED, "call omap_batch_propagate first");
+    return batch->solver.activity(batch->slots[index], dst_dev, dst_pitch_elems);
+    API_GUARD_END
+}
+
+omap_status_t omap_batch_extract_paths(omap_batch_t batch, int32_t* len_dev, int64_t* offsets_dev,
+                                       int32_t* cells_dev, int64_t cells_capacity,
+                                       int64_t* cells_needed_host) {
+    API_GUARD_BEGIN
+    if (!batch) return fail(OMAP_ERR_INVALID_ARG, "batch is NULL");
+    if (!batch->propagated) return fail(OMAP_ERR_NOT_PROPAGATED, "call omap_batch_propagate first");
+    if (!offsets_dev || !len_dev) return fail(OMAP_ERR_INVALID_ARG, "len/offsets pointer is NULL");
+    return batch->solver.extract(batch->slots, len_dev, offsets_dev, cells_dev, cells_capacity,
+                                 cells_needed_host, false);
+    API_GUARD_END
+}
+
+omap_status_t omap_batch_destroy(omap_batch_t batch) {
+    API_GUARD_BEGIN
+    if (!batch) return OMAP_OK;
+    (void)hipStreamSynchronize(batch->solver.stream);
+    delete batch;
+    return OMAP_OK;
+    API_GUARD_END
+}
+
+// ---- serving engine ----------------------------------------------------------
+
+omap_status_t omap_engine_create(omap_engine_t* out, int64_t memory_budget_bytes, int32_t max_slots,
+                                 const omap_options* opts, void* stream) {
+    API_GUARD_BEGIN
+    if (!out || memory_budget_bytes < (1 << 20) || max_slots < 1)
+        return fail(OMAP_ERR_INVALID_ARG, "need out, budget >= 1 MiB and max_slots >= 1");
+    Options o;
+    OK_TRY(resolve_options(opts, &o));
+    std::unique_ptr<omap_engine_s> e(new omap_engine_s());
+    if (!e->mem.init((size_t)memory_budget_bytes))
+        return fail(OMAP_ERR_OUT_OF_MEMORY, "engine budget of %lld bytes", (long long)memory_budget_bytes);
+    e->budget = memory_budget_bytes;
+    e->max_slots = max_slots;
+    // tile ids: enough for the whole budget filled with the smallest mazes
+    const int64_t per_tile = (int64_t)o.TH * o.TW * 8;
+    int64_t cap_tiles = memory_budget_bytes / per_tile + 4 * (int64_t)max_slots + 64;
+    if (cap_tiles > (int64_t(1) << 28)) cap_tiles = int64_t(1) << 28;
+    OK_TRY(e->solver.init(static_cast<hipStream_t>(stream), o, &e->mem, max_slots, (int32_t)cap_tiles));
+    *out = e.release();
+    return OMAP_OK;
+    API_GUARD_END
+}
+
+omap_status_t omap_engine_submit(omap_engine_t engine, int32_t height, int32_t width,
+                                 const uint8_t* occupancy_host, const int32_t* sources_host,
+                                 int32_t n_sources, const int32_t* targets_host, int32_t n_targets,
+                                 int64_t max_layers, int64_t* query_id) {
+    API_GUARD_BEGIN
+    if (!engine || !query_id) return fail(OMAP_ERR_INVALID_ARG, "engine/query_id is NULL");
+    OK_TRY(validate_problem(height, width, occupancy_host, sources_host, n_sources, targets_host, n_targets));
+    if (max_layers < -1) return fail(OMAP_ERR_INVALID_ARG, "max_layers must be >= 0 or OMAP_AUTO_LAYERS");
+    if (max_layers >= 0 && max_layers + 1 > 0x7fffffffLL) return fail(OMAP_ERR_TOO_LARGE, "L + 1 >= 2^31");
+    Query q;
+    q.id = engine->next_id++;
+    q.H = height;
+    q.W = width;
+    q.occ.assign(occupancy_host, occupancy_host + (size_t)height * width);
+    q.src.assign(sources_host, sources_host + 2 * n_sources);
+    if (n_targets > 0) q.tgt.assign(targets_host, targets_host + 2 * n_targets);
+    q.L = max_layers;
+    q.bytes = query_bytes(q, engine->solver.opt);
+    if (q.bytes > (int64_t)engine->mem.size())
+        return fail(OMAP_ERR_OUT_OF_MEMORY, "query needs %lld bytes, budget is %lld", (long long)q.bytes,
+                    (long long)engine->mem.size());
+    const Geometry g = make_geometry(height, width, engine->solver.opt);
+    if ((int64_t)g.tiles_x * g.tiles_y > engine->solver.cap_tiles)
+        return fail(OMAP_ERR_OUT_OF_MEMORY, "query has more tiles than the engine's tile table");
+    *query_id = q.id;
+    engine->waiting.push_back(q.id);
+    engine->queries.emplace(q.id, std::move(q));
+    return OMAP_OK;
+    API_GUARD_END
+}
+
+omap_status_t omap_engine_step(omap_engine_t engine, int32_t rounds, int32_t* n_resident,
+                               int64_t* n_done_total) {
+    API_GUARD_BEGIN
+    if (!engine || rounds < 0) return fail(OMAP_ERR_INVALID_ARG, "engine is NULL or rounds < 0");
+    OK_TRY(engine_admit(engine));
+    if (!engine->resident.empty())
+        for (int32_t i = 0; i < rounds; ++i) OK_TRY(engine->solver.round());
+    OK_TRY(engine_retire(engine));
+    OK_TRY(engine_admit(engine));
+    if (n_resident) *n_resident = (int32_t)engine->resident.size();
+    if (n_done_total) *n_done_total = engine->done_total;
+    return OMAP_OK;
+    API_GUARD_END
+}
+
+omap_status_t omap_engine_poll(omap_engine_t engine, int64_t query_id, int32_t* state) {
+    API_GUARD_BEGIN
+    if (!engine || !state) return fail(OMAP_ERR_INVALID_ARG, "engine/state is NULL");
+    auto it = engine->queries.find(query_id);
+    if (it == engine->queries.end()) return fail(OMAP_ERR_NOT_FOUND, "query %lld", (long long)query_id);
+    *state = it->second.state;
+    return OMAP_OK;
+    API_GUARD_END
+}
+
+omap_status_t omap_engine_fetch(omap_engine_t engine, int64_t query_id, int32_t* len_host,
+                                int64_t* offsets_host, int32_t* cells_host, int64_t cells_capacity,
+                                int64_t* cells_needed_host, omap_propagate_info* info_host) {
+    API_GUARD_BEGIN
+    if (!engine) return fail(OMAP_ERR_INVALID_ARG, "engine is NULL");
+    auto it = engine->queries.find(query_id);
+    if (it == engine->queries.end()) return fail(OMAP_ERR_NOT_FOUND, "query %lld", (long long)query_id);
+    Query& q = it->second;
+    if (q.state == OMAP_QUERY_FAILED) {
+        const std::string msg = q.error;
+        engine->queries.erase(it);
+        g_last_error = msg;
+        return OMAP_ERR_SOURCE_ON_OBSTACLE;
+    }
+    if (q.state != OMAP_QUERY_DONE) return fail(OMAP_ERR_BUSY, "query %lld not finished", (long long)query_id);
+    const int64_t total = q.off.empty() ? 0 : q.off.back();
+    if (cells_needed_host) *cells_needed_host = total;
+    if (cells_capacity < total || (total > 0 && !cells_host))
+        return fail(OMAP_ERR_BUFFER_TOO_SMALL, "paths need %lld cells", (long long)total);
+    const size_t nt = q.tgt.size() / 2;
+    if ((nt > 0 && !len_host) || !offsets_host) return fail(OMAP_ERR_INVALID_ARG, "len/offsets pointer is NULL");
+    if (nt) std::memcpy(len_host, q.len.data(), nt * sizeof(int32_t));
+    std::memcpy(offsets_host, q.off.data(), (nt + 1) * sizeof(int64_t));
+    if (total) std::memcpy(cells_host, q.cells.data(), total * sizeof(int32_t));
+    if (info_host) *info_host = q.info;
+    engine->queries.erase(it);
+    return OMAP_OK;
+    API_GUARD_END
+}
+
+omap_status_t omap_engine_destroy(omap_engine_t engine) {
+    API_GUARD_BEGIN
+    if (!engine) return OMAP_OK;
+    (void)hipStreamSynchronize(engine->solver.stream);
+    engine->solver.destroy();
+    delete engine;
+    return OMAP_OK;
+    API_GUARD_END
+}
+
+// ---- diagnostics -----------------------------------------------------------------
+
+static Solver* solver_of(void* handle, int32_t kind) {
+    if (!handle) return nullptr;
+    if (kind == 0) return &static_cast<omap_plan_s*>(handle)->solver;
+    if (kind == 1) return &static_cast<omap_batch_s*>(handle)->solver;
+    if (kind == 2) return &static_cast<omap_engine_s*>(handle)->solver;
+    return nullptr;
+}
+
+omap_status_t omap_profile_enable(void* handle, int32_t kind, int32_t enable) {
+    API_GUARD_BEGIN
+    Solver* s = solver_of(handle, kind);
+    if (!s) return fail(OMAP_ERR_INVALID_ARG, "bad handle or kind");
+    return s->profile(enable != 0);
+    API_GUARD_END
+}
+
+omap_status_t omap_profile_read(void* handle, int32_t kind, int64_t* launches, double* milliseconds,
+                                int64_t* cell_updates) {
+    API_GUARD_BEGIN
+    Solver* s = solver_of(handle, kind);
+    if (!s) return fail(OMAP_ERR_INVALID_ARG, "bad handle or kind");
+    return s->profile_read(launches, milliseconds, cell_updates);
+    API_GUARD_END
+}
+
+omap_status_t omap_selftest(void* stream) {
+    API_GUARD_BEGIN
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int32_t* d = nullptr;
+    HIP_TRY(hipMalloc(&d, 256 * sizeof(int32_t)));
+    std::vector<int32_t> h(256, 0);
+    hipError_t e = launch_selftest(d, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(h.data(), d, 256 * sizeof(int32_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(d);
+    if (e != hipSuccess) return fail(OMAP_ERR_HIP, "selftest: %s", hipGetErrorString(e));
+    for (int l = 0; l < 64; ++l) {
+        const int want_left = l == 0 ? 0 : l - 1 + 100;     // lane without a source reads 0
+        const int want_right = l == 63 ? 0 : l + 1 + 100;
+        if (h[l] != want_left) return fail(OMAP_ERR_HIP, "lane move from left: lane %d got %d want %d", l, h[l], want_left);
+        if (h[64 + l] != want_right)
+            return fail(OMAP_ERR_HIP, "lane move from right: lane %d got %d want %d", l, h[64 + l], want_right);
+    }
+    if (h[128] != 0 || h[129] != 4 || (uint32_t)h[130] != 0x7fffffffu || (uint32_t)h[131] != 0x80000000u ||
+        h[132] != 3)
+        return fail(OMAP_ERR_HIP, "saturating arithmetic: %d %d %d %d %d", h[128], h[129], h[130], h[131], h[132]);
+    return OMAP_OK;
+    API_GUARD_END
+}
+
+}  // extern "C"
