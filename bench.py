@@ -88,6 +88,20 @@ def cpu_baseline(m, budget_s: float = 12.0):
     }
 
 
+def copy_probe(args):
+    """A plain device-to-device copy of 1 GiB (torch's copy kernel), run under
+    the same hardware counters as the sweep to calibrate the HBM byte counters."""
+    import torch
+    n = 1 << 28
+    src = torch.ones(n, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(max(1, args.steps)):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    return {"metric": "copy_bytes", "value": 2 * 4 * n, "unit": "B", "read_bytes": 4 * n,
+            "write_bytes": 4 * n, "launches": max(1, args.steps)}
+
+
 def bench_plain(args):
     import torch
     import paper_2004_00540_amd as omap
@@ -196,18 +210,25 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "batch", "serve"])
+    ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "batch", "serve", "copy"])
     ap.add_argument("--depth", type=int, default=0)
     ap.add_argument("--tile-rows", type=int, default=0)
     ap.add_argument("--schedule", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--serve-pool", type=int, default=48)
+    ap.add_argument("--serve-requests", type=int, default=200)
+    ap.add_argument("--serve-budget-gb", type=float, default=64.0)
+    ap.add_argument("--serve-slots", type=int, default=64)
+    ap.add_argument("--serve-rounds", type=int, default=4)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the path runs on a single MI355X "
               "(multi-GPU sharding is a design note, not part of this build)", file=sys.stderr)
         sys.exit(2)
-    if args.workload in ("c1", "c2", "c3"):
+    if args.workload == "copy":
+        out = copy_probe(args)
+    elif args.workload in ("c1", "c2", "c3"):
         out = bench_plain(args)
     elif args.workload == "batch":
         from bench_forms import bench_batch

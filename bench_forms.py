@@ -1,0 +1,184 @@
+"""Benchmarks of the batched and serving forms (used by bench.py --workload).
+
+batch: 512 mazes (sides log-uniform in [128, 2048], Bernoulli(p), p ~ U[0.2,
+       0.45], 1-8 sources, 16-512 targets; seeded).  One batched step =
+       omap_batch_create + propagate (run-time L per maze) + extract paths +
+       destroy.  Baseline: the plain per-maze loop (plan create + propagate +
+       extract + destroy for each maze, one after another) on the same GPU.
+serve: maze queries (side log-uniform in [256, 8192], DFS maze with 2% removals
+       or Bernoulli(0.35), 1-16 sources, 8-2048 targets; seeded) arriving as a
+       Poisson process at 0.7 x the engine's measured closed-loop capacity;
+       latency = completion - arrival.  Baseline: the plain per-maze loop.
+"""
+from __future__ import annotations
+
+import concurrent.futures as cf
+import time
+
+import numpy as np
+
+
+def _log(*a):
+    import sys
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _gen_config4(n):
+    import workloads
+    params = workloads.config4_params()
+    return [workloads.config4_maze(i, params) for i in range(n)]
+
+
+def bench_batch(args):
+    import torch
+    import paper_2004_00540_amd as omap
+    import workloads
+
+    n = 512
+    t0 = time.perf_counter()
+    params = workloads.config4_params()
+    with cf.ProcessPoolExecutor(max_workers=8) as ex:
+        mazes = list(ex.map(workloads.config4_maze, range(n), [params] * n, chunksize=16))
+    _log(f"generated {n} mazes in {time.perf_counter() - t0:.1f} s")
+    dev = torch.device("cuda:0")
+    occs = [torch.from_numpy(m.occ).to(dev) for m in mazes]
+    cells = sum(m.H * m.W for m in mazes)
+    n_tgt = sum(len(m.targets) for m in mazes)
+    opts = dict(temporal_depth=args.depth, tile_rows=args.tile_rows, schedule=args.schedule)
+
+    def batched():
+        with omap.Batch([(occs[i], m.sources, m.targets) for i, m in enumerate(mazes)], **opts) as b:
+            b.propagate(sync=False)
+            out = b.paths()
+        return out
+
+    def plain():
+        res = []
+        for i, m in enumerate(mazes):
+            with omap.Plan(occs[i], m.sources, m.targets, **opts) as p:
+                p.propagate(sync=False)
+                res.append(p.paths())
+        return res
+
+    batched()
+    torch.cuda.synchronize()
+    reps = max(1, args.steps)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        batched()
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / reps
+    with omap.Batch([(occs[i], m.sources, m.targets) for i, m in enumerate(mazes)], **opts) as b:
+        infos = b.propagate()
+        b.profile(True)
+        b.propagate(sync=False)
+        prof = b.profile_read()
+    plain()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plain()
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    eff = sum(m.H * m.W * (i["layers"] + 1) for m, i in zip(mazes, infos))
+    return {
+        "metric": "mazes/s", "value": round(n / t_batch, 2), "unit": "mazes/s", "n_gpus": 1,
+        "steps": reps, "warmup": 1, "ms_per_step": round(t_batch * 1e3, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": "config4_512_mazes_loguniform_128_2048", "mazes": n, "cells": cells,
+                   "targets": n_tgt, "max_layers_run_time": max(i["layers"] for i in infos)},
+        "plain_loop_mazes_per_s": round(n / t_plain, 2),
+        "speedup_vs_plain_loop": round(t_plain / t_batch, 2),
+        "effective_gcell_updates_per_s": round(eff / t_batch / 1e9, 1),
+        "paths_per_s": round(n_tgt / t_batch, 1),
+        "sweep_kernel": {"launches": prof["launches"], "ms_total": round(prof["ms"], 3),
+                         "cell_updates": prof["cell_updates"]},
+    }
+
+
+def _gen_query(i):
+    import workloads
+    return workloads.serve_query(i)
+
+
+def bench_serve(args):
+    import torch
+    import paper_2004_00540_amd as omap
+    import workloads
+
+    n_pool = args.serve_pool
+    n_req = args.serve_requests
+    t0 = time.perf_counter()
+    with cf.ProcessPoolExecutor(max_workers=12) as ex:
+        pool = list(ex.map(_gen_query, range(n_pool)))
+    _log(f"generated {n_pool} queries in {time.perf_counter() - t0:.1f} s; "
+         f"mean cells {np.mean([q.H * q.W for q in pool]) / 1e6:.1f} M")
+    dev = torch.device("cuda:0")
+    opts = dict(temporal_depth=args.depth, tile_rows=args.tile_rows, schedule=args.schedule)
+    budget = int(args.serve_budget_gb * (1 << 30))
+    seq = [pool[k % n_pool] for k in range(n_req)]
+
+    # plain per-maze loop (device-resident occupancy uploaded per query, as the engine does)
+    def plain_one(q):
+        occ = torch.from_numpy(q.occ).to(dev)
+        with omap.Plan(occ, q.sources, q.targets, **opts) as p:
+            p.propagate(sync=False)
+            ln, off, cells = p.paths()
+            cells.cpu()
+    plain_one(pool[0])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    n_plain = min(n_req, 2 * n_pool)
+    for q in seq[:n_plain]:
+        plain_one(q)
+    torch.cuda.synchronize()
+    plain_rate = n_plain / (time.perf_counter() - t0)
+    _log(f"plain loop {plain_rate:.2f} mazes/s")
+
+    def run(arrivals, rounds):
+        eng = omap.Engine(budget, max_slots=args.serve_slots, **opts)
+        done = {}
+        ids = {}
+        k = 0
+        start = time.perf_counter()
+        while len(done) < len(arrivals):
+            now = time.perf_counter() - start
+            while k < len(arrivals) and arrivals[k] <= now:
+                q = seq[k]
+                ids[eng.submit(q.occ, q.sources, q.targets)] = k
+                k += 1
+            res, _ = eng.step(rounds=rounds)
+            now = time.perf_counter() - start
+            for qid, j in list(ids.items()):
+                if eng.poll(qid) in (omap.QUERY_DONE, omap.QUERY_FAILED):
+                    eng.fetch(qid)
+                    done[j] = now - arrivals[j]
+                    del ids[qid]
+            if res == 0 and not ids and k < len(arrivals):
+                time.sleep(max(0.0, arrivals[k] - (time.perf_counter() - start)))
+        total = time.perf_counter() - start
+        eng.close()
+        lat = np.array([done[j] for j in range(len(arrivals))])
+        return total, lat
+
+    # closed loop: everything queued at t = 0 -> capacity
+    closed = np.zeros(n_req)
+    t_closed, _ = run(closed, args.serve_rounds)
+    capacity = n_req / t_closed
+    rate = 0.7 * capacity
+    arrivals = workloads.serve_arrivals(n_req, rate)
+    t_open, lat = run(arrivals, args.serve_rounds)
+    return {
+        "metric": "mazes/s", "value": round(n_req / t_open, 2), "unit": "mazes/s", "n_gpus": 1,
+        "steps": n_req, "warmup": 0, "ms_per_step": round(t_open / n_req * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": f"serve_poisson_{n_req}_requests_pool_{n_pool}", "arrival_rate_per_s": round(rate, 2),
+                   "budget_gb": args.serve_budget_gb, "slots": args.serve_slots,
+                   "rounds_per_step": args.serve_rounds},
+        "latency_ms": {"p50": round(float(np.percentile(lat, 50)) * 1e3, 2),
+                       "p99": round(float(np.percentile(lat, 99)) * 1e3, 2),
+                       "mean": round(float(lat.mean()) * 1e3, 2)},
+        "closed_loop_capacity_mazes_per_s": round(capacity, 2),
+        "plain_loop_mazes_per_s": round(plain_rate, 2),
+        "capacity_vs_plain_loop": round(capacity / plain_rate, 2),
+    }

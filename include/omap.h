@@ -79,11 +79,15 @@ typedef enum omap_status {
 /* Execution options.  Zero-initialised = tuned defaults.  No option changes a
  * result: activity maps and paths are identical bit for bit for every value. */
 typedef struct omap_options {
-    int32_t temporal_depth;  /* layers applied per tile visit: 4, 8, 12 or 16; 0 = default */
-    int32_t tile_rows;       /* interior rows per tile, even, 2..4096; 0 = default          */
+    int32_t temporal_depth;  /* layers applied per tile visit: 4, 8, 12, 16 (and 24, 32    */
+                             /* with lane_columns = 2); 0 = default (16)                   */
+    int32_t tile_rows;       /* interior rows per tile, even, 2..4096, >= temporal_depth;  */
+                             /* 0 = default (max(16, temporal_depth))                      */
     int32_t schedule;        /* OMAP_SCHEDULE_ACTIVE or OMAP_SCHEDULE_DENSE                 */
     int32_t check_interval;  /* rounds between host reads of the convergence count;        */
                              /* 0 = adaptive                                                */
+    int32_t lane_columns;    /* columns each lane owns (tile strip = 64 x this): 2 or 4;   */
+                             /* 0 = default (4)                                            */
 } omap_options;
 
 /* Per-maze report of a propagation. */
@@ -143,8 +147,9 @@ omap_status_t omap_get_activity(omap_plan_t plan, int32_t *dst_dev, int64_t dst_
  *   cells_dev    linear cell indices r*width + c, target first, source last
  *   cells_capacity  size of cells_dev in elements
  *   cells_needed_host  always written (on OK and on BUFFER_TOO_SMALL)
- * With cells_dev == NULL or too small a capacity, only cells_needed is
- * written and BUFFER_TOO_SMALL returned.  Synchronous.
+ * When cells_capacity < cells_needed (or cells_dev is NULL and cells_needed
+ * > 0), only cells_needed is written and BUFFER_TOO_SMALL returned; a NULL
+ * cells_dev is accepted when no target has a path.  Synchronous.
  * Errors: INVALID_ARG, NOT_PROPAGATED, BUFFER_TOO_SMALL, HIP. */
 omap_status_t omap_extract_paths(omap_plan_t plan, int32_t *len_dev, int64_t *offsets_dev,
                                  int32_t *cells_dev, int64_t cells_capacity,

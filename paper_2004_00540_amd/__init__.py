@@ -46,7 +46,8 @@ class OmapError(RuntimeError):
 
 class Options(ctypes.Structure):
     _fields_ = [("temporal_depth", ctypes.c_int32), ("tile_rows", ctypes.c_int32),
-                ("schedule", ctypes.c_int32), ("check_interval", ctypes.c_int32)]
+                ("schedule", ctypes.c_int32), ("check_interval", ctypes.c_int32),
+                ("lane_columns", ctypes.c_int32)]
 
 
 class PropagateInfo(ctypes.Structure):
@@ -134,8 +135,9 @@ def _stream(stream=None) -> int:
     return int(stream.cuda_stream) if hasattr(stream, "cuda_stream") else int(stream)
 
 
-def _options(temporal_depth=0, tile_rows=0, schedule=SCHEDULE_ACTIVE, check_interval=0):
-    return Options(temporal_depth, tile_rows, schedule, check_interval)
+def _options(temporal_depth=0, tile_rows=0, schedule=SCHEDULE_ACTIVE, check_interval=0,
+             lane_columns=0):
+    return Options(temporal_depth, tile_rows, schedule, check_interval, lane_columns)
 
 
 def _device_u8(occ):
@@ -376,6 +378,9 @@ class Engine:
         st = lib().omap_engine_fetch(self.handle, int(qid), ln.ctypes.data_as(ctypes.c_void_p),
                                      off.ctypes.data_as(ctypes.c_void_p), None, 0,
                                      ctypes.byref(needed), ctypes.byref(info))
+        if st == OK:     # no target has a path: the query is complete already
+            del self._nt[qid]
+            return QueryResult(ln[:nt], off, np.zeros(0, np.int32), info.as_dict())
         if st != ERR_BUFFER_TOO_SMALL:
             _check(st)
         cells = np.empty(max(int(needed.value), 1), np.int32)

@@ -7,8 +7,6 @@
 namespace omap {
 
 constexpr int kLanes = 64;                          // CDNA wavefront
-constexpr int kColsPerLane = 4;                     // one int4 per lane per row
-constexpr int kStripCols = kLanes * kColsPerLane;   // columns one wave streams
 constexpr int kWavesPerBlock = 4;
 constexpr int kBlockThreads = kLanes * kWavesPerBlock;
 constexpr uint32_t kObstacleBit = 0x80000000u;      // in-register obstacle marker
@@ -31,19 +29,23 @@ struct MazeDev {
 // Per-maze progress states.
 enum : int32_t { kMazeIdle = 0, kMazeRunning = 1, kMazeDone = 2 };
 
-// Arguments of one round of the tile schedule.
+// Arguments of one round of the tile schedule.  Round r reads the tile list
+// and flags of parity r&1 and appends the tiles to visit in round r+1 to the
+// other parity; a tile is appended at most once per round (its flag is set by
+// an atomic exchange).
 struct RoundArgs {
     const MazeDev* mazes;
     const int32_t* tile_maze;     // global tile id -> maze slot (-1 = unused id)
     int32_t n_tile_ids;           // size of the tile id space
     const int32_t* list_in;       // tiles visited this round
-    const int32_t* count_in;
+    int32_t* count_in;            // reset to 0 when the round finishes
+    int32_t* flags_in;            // cleared as the tiles of this round are visited
     int32_t* list_out;            // tiles scheduled for the next round
     int32_t* count_out;
-    uint8_t* flags;               // per tile id: 1 = visit next round (active schedule)
+    int32_t* flags_out;           // 1 = already scheduled for the next round
     int32_t* maze_changed;        // per slot: some tile changed this round
-    int32_t* maze_active;         // per slot: tiles scheduled for the next round
-    int64_t* maze_cells;          // per slot: interior cells scheduled for the next round
+    int32_t* maze_sched;          // per slot: tiles scheduled for the next round
+    unsigned long long* maze_sched_cells;  // per slot: their interior cells
     int32_t* maze_state;          // per slot: kMaze*
     int64_t* maze_rounds;         // per slot: rounds with at least one tile visited
     int64_t* maze_visits;         // per slot: tile visits
@@ -52,7 +54,7 @@ struct RoundArgs {
     int32_t n_slots;
     int32_t parity;               // activity buffer read this round
     int32_t tile_rows;            // interior rows per tile
-    int32_t tile_cols;            // interior columns per tile (kStripCols - 2T)
+    int32_t tile_cols;            // interior columns per tile (64*C - 2T)
     int32_t dense;                // 1 = dense schedule
 };
 
@@ -60,14 +62,18 @@ struct RoundArgs {
 hipError_t launch_pack_mask(const uint8_t* occ, int32_t H, int32_t W, uint32_t* mask,
                             int32_t mpitch, hipStream_t s);
 hipError_t launch_fill(int32_t* p, int64_t n_elems, int32_t value, hipStream_t s);
-hipError_t launch_seed(const MazeDev* mazes, int32_t slot, const int32_t* src_rc, int32_t n_src,
-                       int32_t tile_rows, int32_t tile_cols, uint8_t* flags, int32_t* maze_changed,
+// Seed slot's sources (V := K) and schedule their tiles for the round that
+// reads parity a.parity (a.list_in / a.count_in / a.flags_in).
+hipError_t launch_seed(const RoundArgs& a, int32_t slot, const int32_t* src_rc, int32_t n_src,
                        int32_t* bad_count, hipStream_t s);
+// Schedule every tile of `slot` for the round that reads parity a.parity.
+hipError_t launch_schedule_all(const RoundArgs& a, int32_t slot, int32_t n_tiles, hipStream_t s);
 hipError_t launch_check_sources(const uint32_t* mask, int32_t mpitch, const int32_t* src_rc,
                                 int32_t n_src, int32_t* bad_count, hipStream_t s);
-hipError_t launch_sweep(int T, const RoundArgs& a, int32_t grid, hipStream_t s);
-hipError_t launch_build(const RoundArgs& a, hipStream_t s);
-hipError_t launch_update(const RoundArgs& a, hipStream_t s);
+bool sweep_supported(int T, int C);
+hipError_t launch_sweep(int T, int C, const RoundArgs& a, int32_t grid, hipStream_t s);
+hipError_t launch_finish(const RoundArgs& a, hipStream_t s);
+hipError_t launch_slot_reset(const RoundArgs& a, int32_t slot, hipStream_t s);
 hipError_t launch_reduce(const MazeDev* mazes, const int32_t* tile_maze, int32_t tile_begin,
                          int32_t tile_end, const int32_t* slot_select, int32_t tile_rows,
                          int32_t tile_cols, int32_t parity, int32_t* maze_min,
@@ -82,6 +88,6 @@ hipError_t launch_activity(const MazeDev* mazes, int32_t slot, int32_t H, int32_
                            int32_t parity, int32_t offset, int32_t* dst, int64_t dpitch,
                            hipStream_t s);
 hipError_t launch_selftest(int32_t* out, hipStream_t s);
-int sweep_max_waves_per_cu(int T);
+int sweep_max_waves_per_cu(int T, int C);
 
 }  // namespace omap

@@ -94,14 +94,33 @@ __global__ void k_check_sources(const uint32_t* __restrict__ mask, int32_t mpitc
     if ((w >> (c & 31)) & 1u) atomicAdd(bad, 1);
 }
 
-// Seed V := K at the sources (both buffers) and schedule the tiles whose
-// interior or halo holds a source.
-__global__ void k_seed(const MazeDev* __restrict__ mazes, int32_t slot, const int32_t* __restrict__ src,
-                       int32_t n, int32_t tile_rows, int32_t tile_cols, uint8_t* __restrict__ flags,
-                       int32_t* __restrict__ maze_changed, int32_t* __restrict__ bad) {
+__device__ __forceinline__ int64_t tile_cells(const MazeDev& md, int ty, int tx, int tile_rows,
+                                              int tile_cols) {
+    return (int64_t)min(tile_rows, md.H - ty * tile_rows) * min(tile_cols, md.W - tx * tile_cols);
+}
+
+// Append tile (ty, tx) of `slot` to the list of the round that reads
+// a.list_out (the round about to run) and count it as visited in that round.
+__device__ __forceinline__ void seed_tile(const RoundArgs& a, const MazeDev& md, int slot, int ty,
+                                          int tx) {
+    const int g = md.tile_base + ty * md.tiles_x + tx;
+    if (atomicExch(&a.flags_out[g], 1) == 0) {
+        a.list_out[atomicAdd(a.count_out, 1)] = g;
+        const unsigned long long cells = (unsigned long long)tile_cells(md, ty, tx, a.tile_rows, a.tile_cols);
+        atomicAdd(reinterpret_cast<unsigned long long*>(&a.maze_visits[slot]), 1ull);
+        atomicAdd(reinterpret_cast<unsigned long long*>(&a.maze_cell_visits[slot]), cells);
+        atomicAdd(a.total_cells, cells);
+        a.maze_rounds[slot] = 1;
+    }
+}
+
+// Seed V := K at the sources (both buffers) and, when `schedule` is set,
+// schedule the tiles whose interior or halo holds a source.
+__global__ void k_seed(RoundArgs a, int32_t slot, const int32_t* __restrict__ src, int32_t n,
+                       int32_t schedule, int32_t* __restrict__ bad) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const MazeDev md = mazes[slot];
+    const MazeDev md = a.mazes[slot];
     const int32_t r = src[2 * i], c = src[2 * i + 1];
     const uint32_t w = md.mask[(int64_t)r * md.mpitch + (c >> 5)];
     if ((w >> (c & 31)) & 1u) {
@@ -111,14 +130,31 @@ __global__ void k_seed(const MazeDev* __restrict__ mazes, int32_t slot, const in
     const int64_t x = (int64_t)r * md.pitch + c;
     md.V[0][x] = md.K;
     md.V[1][x] = md.K;
-    const int ty = r / tile_rows, tx = c / tile_cols;
+    if (!schedule) return;
+    const int ty = r / a.tile_rows, tx = c / a.tile_cols;
     for (int dy = -1; dy <= 1; ++dy)
         for (int dx = -1; dx <= 1; ++dx) {
             const int ny = ty + dy, nx = tx + dx;
-            if (ny >= 0 && ny < md.tiles_y && nx >= 0 && nx < md.tiles_x)
-                flags[md.tile_base + ny * md.tiles_x + nx] = 1;
+            if (ny >= 0 && ny < md.tiles_y && nx >= 0 && nx < md.tiles_x) seed_tile(a, md, slot, ny, nx);
         }
-    maze_changed[slot] = 1;
+}
+
+// Append every tile of `slot` to a.list_out (dense schedule, first round).
+__global__ void k_schedule_all(RoundArgs a, int32_t slot, int32_t n_tiles) {
+    __shared__ int base;
+    const MazeDev md = a.mazes[slot];
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int cnt = min((int)blockDim.x, n_tiles - (int)(blockIdx.x * blockDim.x));
+    if (threadIdx.x == 0) base = atomicAdd(a.count_out, cnt);
+    __syncthreads();
+    if (t < n_tiles) a.list_out[base + threadIdx.x] = md.tile_base + t;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        const unsigned long long cells = (unsigned long long)md.H * md.W;
+        a.maze_rounds[slot] = 1;
+        a.maze_visits[slot] += n_tiles;
+        a.maze_cell_visits[slot] += (int64_t)cells;
+        atomicAdd(a.total_cells, cells);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -135,195 +171,241 @@ __global__ void k_seed(const MazeDev* __restrict__ mazes, int32_t slot, const in
 // after T layers (trapezoidal temporal blocking).  Out-of-grid positions load
 // as obstacles, which is the zero padding of the paper's pooling.
 
-// One row step of the pipeline.  Stage s keeps its last three input rows in
-// st[s][0..2]; on the step with P = i mod 3 the newest row (i) sits in slot P,
-// row i-1 in slot (P+2) mod 3 and row i-2 in slot (P+1) mod 3.  Stage s writes
-// its output row straight into stage s+1's slot P, whose previous content
-// (row i-3 of that stage) is dead, so no register copies are needed.
-template <int T, int P>
-__device__ __forceinline__ void sweep_row(uint32_t (&st)[T][3][4], uint32_t (&out)[4]) {
+// One row step of the pipeline (C columns per lane).  Stage s keeps its last
+// three input rows in st[s][0..2]; on the step with P = i mod 3 the newest row
+// (i) sits in slot P, row i-1 in slot (P+2) mod 3 and row i-2 in slot
+// (P+1) mod 3.  Stage s writes its output row straight into stage s+1's slot
+// P, whose previous content (row i-3 of that stage) is dead, so no register
+// copies are needed.
+template <int T, int P, int C>
+__device__ __forceinline__ void sweep_row(uint32_t (&st)[T][3][C], uint32_t (&out)[C]) {
     constexpr int PA = (P + 1) % 3, PB = (P + 2) % 3;
 #pragma unroll
     for (int s = 0; s < T; ++s) {
         const uint32_t* a = st[s][PA];   // row above the centre
         const uint32_t* b = st[s][PB];   // centre row
         const uint32_t* c = st[s][P];    // row below the centre
-        const int v0 = max3i((int)a[0], (int)b[0], (int)c[0]);
-        const int v1 = max3i((int)a[1], (int)b[1], (int)c[1]);
-        const int v2 = max3i((int)a[2], (int)b[2], (int)c[2]);
-        const int v3 = max3i((int)a[3], (int)b[3], (int)c[3]);
-        const int left = from_left_lane(v3);
-        const int right = from_right_lane(v0);
-        const uint32_t h0 = (uint32_t)max3i(left, v0, v1);
-        const uint32_t h1 = (uint32_t)max3i(v0, v1, v2);
-        const uint32_t h2 = (uint32_t)max3i(v1, v2, v3);
-        const uint32_t h3 = (uint32_t)max3i(v2, v3, right);
+        int v[C];
+#pragma unroll
+        for (int j = 0; j < C; ++j) v[j] = max3i((int)a[j], (int)b[j], (int)c[j]);
+        const int left = from_left_lane(v[C - 1]);
+        const int right = from_right_lane(v[0]);
         uint32_t* o = (s + 1 < T) ? st[s + 1 < T ? s + 1 : s][P] : out;
-        o[0] = max(b[0], sat_dec(h0));
-        o[1] = max(b[1], sat_dec(h1));
-        o[2] = max(b[2], sat_dec(h2));
-        o[3] = max(b[3], sat_dec(h3));
+#pragma unroll
+        for (int j = 0; j < C; ++j) {
+            const int l = j == 0 ? left : v[j - 1];
+            const int r = j == C - 1 ? right : v[j + 1];
+            o[j] = max(b[j], sat_dec((uint32_t)max3i(l, v[j], r)));
+        }
     }
 }
 
-template <int T, int P>
-__device__ __forceinline__ void sweep_iter(uint32_t (&st)[T][3][4], const MazeDev& md,
+// Global-memory views of the activity and mask buffers (lets the compiler use
+// global_load / global_store instead of flat accesses).
+typedef int v4i32 __attribute__((ext_vector_type(4)));
+typedef int v2i32 __attribute__((ext_vector_type(2)));
+template <int C> struct LaneVec;
+template <> struct LaneVec<4> { typedef v4i32 type; };
+template <> struct LaneVec<2> { typedef v2i32 type; };
+typedef const __attribute__((address_space(1))) uint32_t gconst_u32;
+
+template <int C>
+__device__ __forceinline__ typename LaneVec<C>::type gload(const int32_t* p) {
+    typedef typename LaneVec<C>::type V;
+    return *(const __attribute__((address_space(1))) V*)p;
+}
+
+template <int C>
+__device__ __forceinline__ void gstore(int32_t* p, typename LaneVec<C>::type v) {
+    typedef typename LaneVec<C>::type V;
+    *(__attribute__((address_space(1))) V*)p = v;
+}
+
+// Issues the loads of row R of the strip: C activity values and the mask word
+// holding their bits.  Rows and columns outside the grid are clamped to a valid
+// address (the loads are unconditional, so they can stay in flight); the decode
+// in sweep_iter turns them into obstacles.
+template <int C>
+__device__ __forceinline__ void load_row(const MazeDev& md, const int32_t* __restrict__ Vin, int R,
+                                         int col, bool col_ok, typename LaneVec<C>::type& v,
+                                         uint32_t& w) {
+    const int Rc = min(max(R, 0), md.H - 1);
+    const int cc = col_ok ? col : 0;
+    v = gload<C>(Vin + (int64_t)Rc * md.pitch + cc);
+    w = *(gconst_u32*)(md.mask + (int64_t)Rc * md.mpitch + (cc >> 5));
+}
+
+// One row of the tile.  (v, w) holds row R, loaded one group (three rows)
+// earlier; it is decoded into stage 0's slot P (cells outside the grid become
+// exactly 0x80000000) and the same registers then receive the load of row
+// R + 3, whose latency overlaps the T-stage arithmetic of the next rows.
+template <int T, int P, int C>
+__device__ __forceinline__ void sweep_iter(uint32_t (&st)[T][3][C], typename LaneVec<C>::type& v,
+                                           uint32_t& w, const MazeDev& md,
                                            const int32_t* __restrict__ Vin,
                                            int32_t* __restrict__ Vout, int R, int r0, int r_end,
                                            int col, bool col_ok, bool inner,
                                            uint64_t& sum_in, uint64_t& sum_out) {
+    const bool ok = R >= 0 && R < md.H && col_ok;
+    const uint32_t keep = ok ? 0xffffffffu : 0u;
+    const uint32_t bits = ok ? (w >> (col & 31)) : 0xFu;   // outside the grid: obstacle
     uint32_t* c = st[0][P];
-    if (R >= 0 && R < md.H && col_ok) {
-        const int4 v = *reinterpret_cast<const int4*>(Vin + (int64_t)R * md.pitch + col);
-        const uint32_t w = md.mask[(int64_t)R * md.mpitch + (col >> 5)] >> (col & 31);
-        c[0] = (uint32_t)v.x | ((w & 1u) << 31);
-        c[1] = (uint32_t)v.y | ((w & 2u) << 30);
-        c[2] = (uint32_t)v.z | ((w & 4u) << 29);
-        c[3] = (uint32_t)v.w | ((w & 8u) << 28);
-    } else {
-        c[0] = c[1] = c[2] = c[3] = kObstacleBit;
+#pragma unroll
+    for (int j = 0; j < C; ++j) c[j] = ((uint32_t)v[j] & keep) | (((bits >> j) & 1u) << 31);
+    load_row<C>(md, Vin, R + 3, col, col_ok, v, w);
+    if (inner && R >= r0 && R < r_end) {
+        uint64_t t = 0;
+#pragma unroll
+        for (int j = 0; j < C; ++j) t += c[j] & 0x7fffffffu;
+        sum_in += t;
     }
-    if (inner && R >= r0 && R < r_end)
-        sum_in += (uint64_t)(c[0] & 0x7fffffffu) + (c[1] & 0x7fffffffu) + (c[2] & 0x7fffffffu) +
-                  (c[3] & 0x7fffffffu);
-    uint32_t out[4];
-    sweep_row<T, P>(st, out);
+    uint32_t out[C];
+    sweep_row<T, P, C>(st, out);
     const int Ro = R - T;
     if (inner && Ro >= r0 && Ro < r_end) {
-        int4 o;
-        o.x = (int)(out[0] & 0x7fffffffu);
-        o.y = (int)(out[1] & 0x7fffffffu);
-        o.z = (int)(out[2] & 0x7fffffffu);
-        o.w = (int)(out[3] & 0x7fffffffu);
-        *reinterpret_cast<int4*>(Vout + (int64_t)Ro * md.pitch + col) = o;
-        sum_out += (uint64_t)(uint32_t)o.x + (uint32_t)o.y + (uint32_t)o.z + (uint32_t)o.w;
+        typename LaneVec<C>::type o;
+        uint64_t t = 0;
+#pragma unroll
+        for (int j = 0; j < C; ++j) {
+            o[j] = (int)(out[j] & 0x7fffffffu);
+            t += (uint32_t)o[j];
+        }
+        gstore<C>(Vout + (int64_t)Ro * md.pitch + col, o);
+        sum_out += t;
     }
 }
 
-// Returns true (wave-uniform) if any interior cell of the tile changed.
-template <int T>
+// Returns true (wave-uniform) if any interior cell of the tile changed.  The
+// wave streams the strip of 64*C columns starting T columns left of the tile.
+template <int T, int C>
 __device__ bool sweep_tile(const MazeDev& md, int ty, int tx, int tile_rows, int parity) {
-    constexpr int TW = kStripCols - 2 * T;
+    constexpr int TW = kLanes * C - 2 * T;
+    constexpr int HALO_LANES = T / C;
     const int lane = lane_id();
     const int r0 = ty * tile_rows;
     const int r_end = min(r0 + tile_rows, md.H);
-    const int col = tx * TW - T + kColsPerLane * lane;
+    const int col = tx * TW - T + C * lane;
     const bool col_ok = col >= 0 && col < md.pitch;
-    const bool inner = lane >= T / 4 && lane < kLanes - T / 4 && col < md.W;
+    const bool inner = lane >= HALO_LANES && lane < kLanes - HALO_LANES && col < md.W;
     const int32_t* __restrict__ Vin = md.V[parity];
     int32_t* __restrict__ Vout = md.V[parity ^ 1];
 
-    uint32_t st[T][3][4];
+    uint32_t st[T][3][C];
 #pragma unroll
     for (int s = 0; s < T; ++s)
 #pragma unroll
         for (int k = 0; k < 3; ++k)
 #pragma unroll
-            for (int j = 0; j < 4; ++j) st[s][k][j] = kObstacleBit;
+            for (int j = 0; j < C; ++j) st[s][k][j] = kObstacleBit;
 
     uint64_t sum_in = 0, sum_out = 0;
     const int n_iter = (r_end - r0) + 2 * T;   // rows r0-T .. r_end+T-1
+    typename LaneVec<C>::type v0, v1, v2;
+    uint32_t w0, w1, w2;
+    load_row<C>(md, Vin, r0 - T, col, col_ok, v0, w0);
+    load_row<C>(md, Vin, r0 - T + 1, col, col_ok, v1, w1);
+    load_row<C>(md, Vin, r0 - T + 2, col, col_ok, v2, w2);
     for (int i = 0; i < n_iter; i += 3) {
         const int R = r0 - T + i;
-        sweep_iter<T, 0>(st, md, Vin, Vout, R, r0, r_end, col, col_ok, inner, sum_in, sum_out);
-        sweep_iter<T, 1>(st, md, Vin, Vout, R + 1, r0, r_end, col, col_ok, inner, sum_in, sum_out);
-        sweep_iter<T, 2>(st, md, Vin, Vout, R + 2, r0, r_end, col, col_ok, inner, sum_in, sum_out);
+        sweep_iter<T, 0, C>(st, v0, w0, md, Vin, Vout, R, r0, r_end, col, col_ok, inner, sum_in, sum_out);
+        sweep_iter<T, 1, C>(st, v1, w1, md, Vin, Vout, R + 1, r0, r_end, col, col_ok, inner, sum_in, sum_out);
+        sweep_iter<T, 2, C>(st, v2, w2, md, Vin, Vout, R + 2, r0, r_end, col, col_ok, inner, sum_in, sum_out);
     }
     return __ballot(sum_in != sum_out) != 0;
 }
 
-template <int T>
+// Append tile (ty, tx) of `slot` to the next round's list unless it is already
+// there.
+__device__ __forceinline__ void schedule_tile(const RoundArgs& a, const MazeDev& md, int slot,
+                                              int ty, int tx) {
+    const int g = md.tile_base + ty * md.tiles_x + tx;
+    if (atomicExch(&a.flags_out[g], 1) == 0) {
+        a.list_out[atomicAdd(a.count_out, 1)] = g;
+        atomicAdd(&a.maze_sched[slot], 1);
+        atomicAdd(&a.maze_sched_cells[slot],
+                  (unsigned long long)tile_cells(md, ty, tx, a.tile_rows, a.tile_cols));
+    }
+}
+
+// End of a round (one block, after the sweep): the dense schedule's
+// next-round list, per-maze counters and convergence, and the reset of this
+// round's input count.
+__global__ __launch_bounds__(kBlockThreads) void k_finish(RoundArgs a) {
+    __shared__ int s_base[kBlockThreads], s_n[kBlockThreads], s_tb[kBlockThreads];
+    if (a.dense) {
+        for (int m0 = 0; m0 < a.n_slots; m0 += blockDim.x) {
+            const int m = m0 + threadIdx.x;
+            int base = -1, nt = 0, tb = 0;
+            if (m < a.n_slots && a.maze_state[m] == kMazeRunning && atomicExch(&a.maze_changed[m], 0)) {
+                const MazeDev md = a.mazes[m];
+                nt = md.tiles_x * md.tiles_y;
+                tb = md.tile_base;
+                base = atomicAdd(a.count_out, nt);
+                atomicAdd(&a.maze_sched[m], nt);
+                atomicAdd(&a.maze_sched_cells[m], (unsigned long long)md.H * md.W);
+            }
+            s_base[threadIdx.x] = base;
+            s_n[threadIdx.x] = nt;
+            s_tb[threadIdx.x] = tb;
+            __syncthreads();
+            for (int k = 0; k < (int)blockDim.x; ++k) {
+                if (s_base[k] < 0) continue;
+                for (int t = threadIdx.x; t < s_n[k]; t += blockDim.x) a.list_out[s_base[k] + t] = s_tb[k] + t;
+            }
+            __syncthreads();
+        }
+    }
+    for (int m = threadIdx.x; m < a.n_slots; m += blockDim.x) {
+        const int sched = atomicExch(&a.maze_sched[m], 0);
+        const unsigned long long cells = atomicExch(&a.maze_sched_cells[m], 0ull);
+        if (a.maze_state[m] == kMazeRunning) {
+            if (sched > 0) {
+                a.maze_rounds[m] += 1;
+                a.maze_visits[m] += sched;
+                a.maze_cell_visits[m] += (int64_t)cells;
+                atomicAdd(a.total_cells, cells);
+            } else {
+                a.maze_state[m] = kMazeDone;
+            }
+        }
+    }
+    if (threadIdx.x == 0) *a.count_in = 0;
+}
+
+// Marks `slot` running and clears its counters (before its seeds).
+__global__ void k_slot_reset(RoundArgs a, int32_t slot) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    a.maze_state[slot] = kMazeRunning;
+    a.maze_rounds[slot] = 0;
+    a.maze_visits[slot] = 0;
+    a.maze_cell_visits[slot] = 0;
+    a.maze_changed[slot] = 0;
+}
+
+template <int T, int C>
 __global__ __launch_bounds__(kBlockThreads) void k_sweep(RoundArgs a) {
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = lane_id();
-    if (blockIdx.x == 0 && threadIdx.x == 0) *a.count_out = 0;
     const int n = __builtin_amdgcn_readfirstlane(*a.count_in);
     const int stride = gridDim.x * kWavesPerBlock;
     for (int i = blockIdx.x * kWavesPerBlock + wave; i < n; i += stride) {
         const int g = a.list_in[i];
+        if (lane == 0) a.flags_in[g] = 0;
         const int slot = a.tile_maze[g];
         const MazeDev md = a.mazes[slot];
         const int lt = g - md.tile_base;
         const int ty = lt / md.tiles_x;
         const int tx = lt - ty * md.tiles_x;
-        if (sweep_tile<T>(md, ty, tx, a.tile_rows, a.parity)) {
-            if (lane < 9) {
+        if (sweep_tile<T, C>(md, ty, tx, a.tile_rows, a.parity)) {
+            if (a.dense) {
+                if (lane == 0) a.maze_changed[slot] = 1;
+            } else if (lane < 9) {
                 const int ny = ty + lane / 3 - 1, nx = tx + lane % 3 - 1;
                 if (ny >= 0 && ny < md.tiles_y && nx >= 0 && nx < md.tiles_x)
-                    a.flags[md.tile_base + ny * md.tiles_x + nx] = 1;
-            }
-            if (lane == 0) a.maze_changed[slot] = 1;
-        }
-    }
-}
-
-// ---------------------------------------------------------------------------
-// schedule: next round's tile list from the change flags
-// ---------------------------------------------------------------------------
-
-__global__ __launch_bounds__(256) void k_build(RoundArgs a) {
-    const int g = blockIdx.x * blockDim.x + threadIdx.x;
-    const int lane = lane_id();
-    bool act = false;
-    int slot = -1;
-    int64_t cells = 0;
-    if (g < a.n_tile_ids) {
-        slot = a.tile_maze[g];
-        const bool flagged = a.flags[g] != 0;
-        if (flagged) a.flags[g] = 0;
-        if (slot >= 0 && a.maze_state[slot] == kMazeRunning) {
-            act = a.dense ? (a.maze_changed[slot] != 0) : flagged;
-            if (act) {
-                const MazeDev md = a.mazes[slot];
-                const int lt = g - md.tile_base;
-                const int ty = lt / md.tiles_x, tx = lt - ty * md.tiles_x;
-                const int rows = min(a.tile_rows, md.H - ty * a.tile_rows);
-                const int cols = min(a.tile_cols, md.W - tx * a.tile_cols);
-                cells = (int64_t)rows * cols;
+                    schedule_tile(a, md, slot, ny, nx);
             }
         }
     }
-    const unsigned long long bal = __ballot(act);
-    if (bal == 0) return;
-    const int leader = __ffsll(bal) - 1;
-    int base = 0;
-    if (lane == leader) base = atomicAdd(a.count_out, __popcll(bal));
-    base = __shfl(base, leader);
-    if (act) a.list_out[base + __popcll(bal & ((1ull << lane) - 1ull))] = g;
-    // per-maze counts, aggregated over lanes of the leader's maze
-    const int lead_slot = __shfl(slot, leader);
-    const bool same = act && slot == lead_slot;
-    const unsigned long long bs = __ballot(same);
-    int64_t csum = same ? cells : 0;
-    for (int off = 32; off > 0; off >>= 1) csum += __shfl_xor(csum, off);
-    if (lane == leader) {
-        atomicAdd(&a.maze_active[lead_slot], (int)__popcll(bs));
-        atomicAdd((unsigned long long*)&a.maze_cells[lead_slot], (unsigned long long)csum);
-    }
-    if (act && !same) {
-        atomicAdd(&a.maze_active[slot], 1);
-        atomicAdd((unsigned long long*)&a.maze_cells[slot], (unsigned long long)cells);
-    }
-}
-
-__global__ void k_update(RoundArgs a) {
-    const int m = blockIdx.x * blockDim.x + threadIdx.x;
-    if (m >= a.n_slots) return;
-    const int act = a.maze_active[m];
-    const int64_t cells = a.maze_cells[m];
-    if (a.maze_state[m] == kMazeRunning) {
-        if (act > 0) {
-            a.maze_rounds[m] += 1;
-            a.maze_visits[m] += act;
-            a.maze_cell_visits[m] += cells;
-            atomicAdd(a.total_cells, (unsigned long long)cells);
-        } else {
-            a.maze_state[m] = kMazeDone;
-        }
-    }
-    a.maze_active[m] = 0;
-    a.maze_cells[m] = 0;
-    a.maze_changed[m] = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -519,33 +601,48 @@ hipError_t launch_check_sources(const uint32_t* mask, int32_t mpitch, const int3
     return hipGetLastError();
 }
 
-hipError_t launch_seed(const MazeDev* mazes, int32_t slot, const int32_t* src_rc, int32_t n_src,
-                       int32_t tile_rows, int32_t tile_cols, uint8_t* flags, int32_t* maze_changed,
+hipError_t launch_seed(const RoundArgs& a, int32_t slot, const int32_t* src_rc, int32_t n_src,
                        int32_t* bad_count, hipStream_t s) {
-    hipLaunchKernelGGL(k_seed, dim3(grid_for(n_src, 256)), dim3(256), 0, s, mazes, slot, src_rc,
-                       n_src, tile_rows, tile_cols, flags, maze_changed, bad_count);
+    hipLaunchKernelGGL(k_seed, dim3(grid_for(n_src, 256)), dim3(256), 0, s, a, slot, src_rc, n_src,
+                       a.dense ? 0 : 1, bad_count);
     return hipGetLastError();
 }
 
-hipError_t launch_sweep(int T, const RoundArgs& a, int32_t grid, hipStream_t s) {
-    switch (T) {
-        case 4: hipLaunchKernelGGL(k_sweep<4>, dim3(grid), dim3(kBlockThreads), 0, s, a); break;
-        case 8: hipLaunchKernelGGL(k_sweep<8>, dim3(grid), dim3(kBlockThreads), 0, s, a); break;
-        case 12: hipLaunchKernelGGL(k_sweep<12>, dim3(grid), dim3(kBlockThreads), 0, s, a); break;
-        case 16: hipLaunchKernelGGL(k_sweep<16>, dim3(grid), dim3(kBlockThreads), 0, s, a); break;
-        default: return hipErrorInvalidValue;
+hipError_t launch_schedule_all(const RoundArgs& a, int32_t slot, int32_t n_tiles, hipStream_t s) {
+    hipLaunchKernelGGL(k_schedule_all, dim3(grid_for(n_tiles, 256)), dim3(256), 0, s, a, slot, n_tiles);
+    return hipGetLastError();
+}
+
+hipError_t launch_slot_reset(const RoundArgs& a, int32_t slot, hipStream_t s) {
+    hipLaunchKernelGGL(k_slot_reset, dim3(1), dim3(64), 0, s, a, slot);
+    return hipGetLastError();
+}
+
+hipError_t launch_finish(const RoundArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(kBlockThreads), 0, s, a);
+    return hipGetLastError();
+}
+
+// Sweep kernels instantiated for (layers per visit, columns per lane).
+#define OMAP_SWEEP_VARIANTS(X) \
+    X(4, 4) X(8, 4) X(12, 4) X(16, 4) X(4, 2) X(8, 2) X(12, 2) X(16, 2) X(24, 2) X(32, 2)
+
+bool sweep_supported(int T, int C) {
+#define X(t, c) if (T == t && C == c) return true;
+    OMAP_SWEEP_VARIANTS(X)
+#undef X
+    return false;
+}
+
+hipError_t launch_sweep(int T, int C, const RoundArgs& a, int32_t grid, hipStream_t s) {
+#define X(t, c)                                                                             \
+    if (T == t && C == c) {                                                                 \
+        hipLaunchKernelGGL((k_sweep<t, c>), dim3(grid), dim3(kBlockThreads), 0, s, a);     \
+        return hipGetLastError();                                                           \
     }
-    return hipGetLastError();
-}
-
-hipError_t launch_build(const RoundArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL(k_build, dim3(grid_for(a.n_tile_ids, 256)), dim3(256), 0, s, a);
-    return hipGetLastError();
-}
-
-hipError_t launch_update(const RoundArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL(k_update, dim3(grid_for(a.n_slots, 256)), dim3(256), 0, s, a);
-    return hipGetLastError();
+    OMAP_SWEEP_VARIANTS(X)
+#undef X
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_reduce(const MazeDev* mazes, const int32_t* tile_maze, int32_t tile_begin,
@@ -596,16 +693,14 @@ hipError_t launch_selftest(int32_t* out, hipStream_t s) {
     return hipGetLastError();
 }
 
-int sweep_max_waves_per_cu(int T) {
+int sweep_max_waves_per_cu(int T, int C) {
     int blocks = 0;
     hipError_t e = hipErrorInvalidValue;
-    switch (T) {
-        case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_sweep<4>, kBlockThreads, 0); break;
-        case 8: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_sweep<8>, kBlockThreads, 0); break;
-        case 12: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_sweep<12>, kBlockThreads, 0); break;
-        case 16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_sweep<16>, kBlockThreads, 0); break;
-        default: break;
-    }
+#define X(t, c)                                                                                  \
+    if (T == t && C == c)                                                                        \
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_sweep<t, c>, kBlockThreads, 0);
+    OMAP_SWEEP_VARIANTS(X)
+#undef X
     if (e != hipSuccess || blocks < 1) blocks = 1;
     return blocks * kWavesPerBlock;
 }

@@ -63,8 +63,9 @@ static omap_status_t fail(omap_status_t st, const char* fmt, ...) {
 
 struct Options {
     int T = 16;          // layers per tile visit
-    int TH = 64;         // interior rows per tile
-    int TW = kStripCols - 2 * 16;
+    int C = 4;           // columns per lane (strip = 64*C columns)
+    int TH = 16;         // interior rows per tile
+    int TW = 64 * 4 - 2 * 16;
     int dense = 0;
     int check = 0;       // 0 = adaptive
 };
@@ -72,18 +73,23 @@ struct Options {
 static omap_status_t resolve_options(const omap_options* o, Options* out) {
     Options r;
     if (o) {
-        if (o->temporal_depth != 0) {
-            if (o->temporal_depth != 4 && o->temporal_depth != 8 && o->temporal_depth != 12 &&
-                o->temporal_depth != 16)
-                return fail(OMAP_ERR_INVALID_ARG, "temporal_depth must be 4, 8, 12 or 16 (got %d)",
-                            o->temporal_depth);
-            r.T = o->temporal_depth;
+        if (o->lane_columns != 0) {
+            if (o->lane_columns != 2 && o->lane_columns != 4)
+                return fail(OMAP_ERR_INVALID_ARG, "lane_columns must be 2 or 4 (got %d)", o->lane_columns);
+            r.C = o->lane_columns;
         }
+        if (o->temporal_depth != 0) r.T = o->temporal_depth;
+        if (!sweep_supported(r.T, r.C))
+            return fail(OMAP_ERR_INVALID_ARG,
+                        "temporal_depth %d is not available with %d columns per lane "
+                        "(4, 8, 12, 16; with 2 columns also 24, 32)", r.T, r.C);
         if (o->tile_rows != 0) {
             if (o->tile_rows < 2 || o->tile_rows > 4096 || (o->tile_rows & 1))
                 return fail(OMAP_ERR_INVALID_ARG, "tile_rows must be even in [2, 4096] (got %d)",
                             o->tile_rows);
             r.TH = o->tile_rows;
+        } else {
+            r.TH = std::max(16, r.T);
         }
         if (o->schedule != OMAP_SCHEDULE_ACTIVE && o->schedule != OMAP_SCHEDULE_DENSE)
             return fail(OMAP_ERR_INVALID_ARG, "schedule must be ACTIVE or DENSE (got %d)", o->schedule);
@@ -93,7 +99,7 @@ static omap_status_t resolve_options(const omap_options* o, Options* out) {
     }
     if (r.TH < r.T)
         return fail(OMAP_ERR_INVALID_ARG, "tile_rows (%d) must be >= temporal_depth (%d)", r.TH, r.T);
-    r.TW = kStripCols - 2 * r.T;
+    r.TW = 64 * r.C - 2 * r.T;
     *out = r;
     return OMAP_OK;
 }
@@ -272,10 +278,15 @@ class Solver {
     int32_t* d_tile_maze = nullptr;
     int32_t* d_list[2] = {nullptr, nullptr};
     int32_t* d_count = nullptr;               // [2]
-    uint8_t* d_flags = nullptr;
-    int32_t *d_changed = nullptr, *d_active = nullptr, *d_state = nullptr;
-    int64_t *d_cells = nullptr, *d_rounds = nullptr, *d_visits = nullptr, *d_cell_visits = nullptr;
+    int32_t* d_flags[2] = {nullptr, nullptr};
+    int32_t *d_changed = nullptr, *d_sched = nullptr, *d_state = nullptr;
+    unsigned long long* d_sched_cells = nullptr;
+    int64_t *d_rounds = nullptr, *d_visits = nullptr, *d_cell_visits = nullptr;
     unsigned long long* d_total_cells = nullptr;
+    int32_t* d_bad_slot = nullptr;            // per slot: sources found on obstacles
+    int32_t* h_bad = nullptr;                 // pinned mirror of d_bad_slot
+    std::vector<MazeDev> h_mazes;             // host mirror of d_mazes
+    std::vector<int32_t> h_tile_maze;         // host mirror of d_tile_maze
     int32_t* d_min = nullptr;
     unsigned long long* d_reached = nullptr;
     int32_t* d_bad = nullptr;
@@ -308,6 +319,8 @@ class Solver {
         scratch_bytes = 0;
         if (h_pinned) (void)hipHostFree(h_pinned);
         h_pinned = nullptr;
+        if (h_bad) (void)hipHostFree(h_bad);
+        h_bad = nullptr;
         for (auto& e : prof_events) {
             (void)hipEventDestroy(e.first);
             (void)hipEventDestroy(e.second);
@@ -339,11 +352,16 @@ class Solver {
         OK_TRY(dalloc(&d_list[0], cap_tiles));
         OK_TRY(dalloc(&d_list[1], cap_tiles));
         OK_TRY(dalloc(&d_count, 2));
-        OK_TRY(dalloc(&d_flags, cap_tiles));
+        OK_TRY(dalloc(&d_flags[0], cap_tiles));
+        OK_TRY(dalloc(&d_flags[1], cap_tiles));
         OK_TRY(dalloc(&d_changed, cap_slots));
-        OK_TRY(dalloc(&d_active, cap_slots));
+        OK_TRY(dalloc(&d_sched, cap_slots));
         OK_TRY(dalloc(&d_state, cap_slots));
-        OK_TRY(dalloc(&d_cells, cap_slots));
+        OK_TRY(dalloc(&d_sched_cells, cap_slots));
+        OK_TRY(dalloc(&d_bad_slot, cap_slots));
+        HIP_TRY(hipHostMalloc((void**)&h_bad, sizeof(int32_t) * cap_slots, hipHostMallocDefault));
+        h_mazes.assign(cap_slots, MazeDev());
+        h_tile_maze.assign(cap_tiles, -1);
         OK_TRY(dalloc(&d_rounds, cap_slots));
         OK_TRY(dalloc(&d_visits, cap_slots));
         OK_TRY(dalloc(&d_cell_visits, cap_slots));
@@ -354,12 +372,14 @@ class Solver {
         OK_TRY(dalloc(&d_sel, cap_slots));
         HIP_TRY(hipHostMalloc((void**)&h_pinned, 64 * sizeof(int32_t), hipHostMallocDefault));
         HIP_TRY(hipMemsetAsync(d_tile_maze, 0xff, sizeof(int32_t) * cap_tiles, stream));
-        HIP_TRY(hipMemsetAsync(d_flags, 0, cap_tiles, stream));
+        HIP_TRY(hipMemsetAsync(d_flags[0], 0, sizeof(int32_t) * cap_tiles, stream));
+        HIP_TRY(hipMemsetAsync(d_flags[1], 0, sizeof(int32_t) * cap_tiles, stream));
         HIP_TRY(hipMemsetAsync(d_count, 0, 2 * sizeof(int32_t), stream));
         HIP_TRY(hipMemsetAsync(d_changed, 0, sizeof(int32_t) * cap_slots, stream));
-        HIP_TRY(hipMemsetAsync(d_active, 0, sizeof(int32_t) * cap_slots, stream));
+        HIP_TRY(hipMemsetAsync(d_sched, 0, sizeof(int32_t) * cap_slots, stream));
         HIP_TRY(hipMemsetAsync(d_state, 0, sizeof(int32_t) * cap_slots, stream));
-        HIP_TRY(hipMemsetAsync(d_cells, 0, sizeof(int64_t) * cap_slots, stream));
+        HIP_TRY(hipMemsetAsync(d_sched_cells, 0, sizeof(unsigned long long) * cap_slots, stream));
+        HIP_TRY(hipMemsetAsync(d_bad_slot, 0, sizeof(int32_t) * cap_slots, stream));
         HIP_TRY(hipMemsetAsync(d_rounds, 0, sizeof(int64_t) * cap_slots, stream));
         HIP_TRY(hipMemsetAsync(d_visits, 0, sizeof(int64_t) * cap_slots, stream));
         HIP_TRY(hipMemsetAsync(d_cell_visits, 0, sizeof(int64_t) * cap_slots, stream));
@@ -368,7 +388,7 @@ class Solver {
         HIP_TRY(hipGetDevice(&dev));
         int cus = 0;
         HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-        const int waves = sweep_max_waves_per_cu(opt.T);
+        const int waves = sweep_max_waves_per_cu(opt.T, opt.C);
         grid = std::max(1, cus * std::max(1, waves / kWavesPerBlock));
         const int need = (cap_tiles + kWavesPerBlock - 1) / kWavesPerBlock;
         grid = std::max(1, std::min(grid, need));
@@ -376,19 +396,24 @@ class Solver {
         return OMAP_OK;
     }
 
-    RoundArgs round_args() const {
+    // Arguments of the round that reads parity `parity`.  With `seeding` the
+    // "out" list is the one that round itself reads (seeds schedule tiles for
+    // the round about to run).
+    RoundArgs round_args(bool seeding = false) const {
         RoundArgs a;
+        const int pin = parity, pout = seeding ? parity : parity ^ 1;
         a.mazes = d_mazes;
         a.tile_maze = d_tile_maze;
         a.n_tile_ids = tile_hwm;
-        a.list_in = d_list[parity];
-        a.count_in = d_count + parity;
-        a.list_out = d_list[parity ^ 1];
-        a.count_out = d_count + (parity ^ 1);
-        a.flags = d_flags;
+        a.list_in = d_list[pin];
+        a.count_in = d_count + pin;
+        a.flags_in = d_flags[pin];
+        a.list_out = d_list[pout];
+        a.count_out = d_count + pout;
+        a.flags_out = d_flags[pout];
         a.maze_changed = d_changed;
-        a.maze_active = d_active;
-        a.maze_cells = d_cells;
+        a.maze_sched = d_sched;
+        a.maze_sched_cells = d_sched_cells;
         a.maze_state = d_state;
         a.maze_rounds = d_rounds;
         a.maze_visits = d_visits;
@@ -412,9 +437,11 @@ class Solver {
         s.d_src = nullptr;
     }
 
+    // Copies slot k's descriptor to the device (stream-ordered; the host
+    // mirror outlives the copy).
     omap_status_t upload_desc(int32_t k) {
         const Slot& s = slots[k];
-        MazeDev md;
+        MazeDev& md = h_mazes[k];
         md.H = s.g.H;
         md.W = s.g.W;
         md.pitch = s.g.pitch;
@@ -427,7 +454,14 @@ class Solver {
         md.V[1] = s.V[1];
         md.mask = s.mask;
         HIP_TRY(hipMemcpyAsync(d_mazes + k, &md, sizeof md, hipMemcpyHostToDevice, stream));
-        HIP_TRY(hipStreamSynchronize(stream));   // md lives on this stack frame
+        return OMAP_OK;
+    }
+
+    omap_status_t upload_tile_range(int32_t base, int32_t n, int32_t value) {
+        if (n <= 0) return OMAP_OK;
+        std::fill(h_tile_maze.begin() + base, h_tile_maze.begin() + base + n, value);
+        HIP_TRY(hipMemcpyAsync(d_tile_maze + base, h_tile_maze.data() + base, sizeof(int32_t) * n,
+                               hipMemcpyHostToDevice, stream));
         return OMAP_OK;
     }
 
@@ -469,33 +503,54 @@ class Solver {
         return -1;
     }
 
-    // Pack and validate one maze into slot k (synchronous).
-    omap_status_t pack(int32_t k, const uint8_t* occ_dev, const int32_t* src, int32_t n_src,
-                       const int32_t* tgt, int32_t n_tgt) {
+    // Pack one maze into slot k and check its sources on the device; the
+    // verdict is read by commit() (stream-ordered, no host wait).
+    omap_status_t pack_async(int32_t k, const uint8_t* occ_dev, const int32_t* src, int32_t n_src,
+                             const int32_t* tgt, int32_t n_tgt) {
         Slot& s = slots[k];
         OK_TRY(validate_problem(s.g.H, s.g.W, occ_dev, src, n_src, tgt, n_tgt));
+        s.src.assign(src, src + 2 * n_src);
+        if (tgt && n_tgt > 0) s.tgt.assign(tgt, tgt + 2 * n_tgt);
+        else s.tgt.clear();
         mem->release(s.d_src);
         s.d_src = static_cast<int32_t*>(mem->alloc(sizeof(int32_t) * 2 * n_src));
         if (!s.d_src) return fail(OMAP_ERR_OUT_OF_MEMORY, "source list (%d sources)", n_src);
         HIP_TRY(launch_pack_mask(occ_dev, s.g.H, s.g.W, s.mask, s.g.mpitch, stream));
-        HIP_TRY(hipMemcpyAsync(s.d_src, src, sizeof(int32_t) * 2 * n_src, hipMemcpyHostToDevice, stream));
-        HIP_TRY(hipMemsetAsync(d_bad, 0, sizeof(int32_t), stream));
-        HIP_TRY(launch_check_sources(s.mask, s.g.mpitch, s.d_src, n_src, d_bad, stream));
-        HIP_TRY(hipMemcpyAsync(h_pinned, d_bad, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
-        HIP_TRY(hipStreamSynchronize(stream));
-        if (h_pinned[0] != 0)
-            return fail(OMAP_ERR_SOURCE_ON_OBSTACLE, "%d source(s) lie on obstacles", h_pinned[0]);
-        s.src.assign(src, src + 2 * n_src);
-        s.tgt.assign(tgt ? tgt : src, tgt ? tgt + 2 * n_tgt : src);
-        if (!tgt) s.tgt.clear();
+        HIP_TRY(hipMemcpyAsync(s.d_src, s.src.data(), sizeof(int32_t) * 2 * n_src, hipMemcpyHostToDevice, stream));
+        HIP_TRY(hipMemsetAsync(d_bad_slot + k, 0, sizeof(int32_t), stream));
+        HIP_TRY(launch_check_sources(s.mask, s.g.mpitch, s.d_src, n_src, d_bad_slot + k, stream));
         s.started = s.finalized = false;
         s.layers = -1;
         return OMAP_OK;
     }
 
-    // Allocate slot buffers and a tile id range, then pack (synchronous).
+    // Waits for the device and reports the first slot of `which` that has a
+    // source on an obstacle (*bad_index = its position in `which`).
+    omap_status_t commit(const std::vector<int32_t>& which, int32_t* bad_index) {
+        HIP_TRY(hipMemcpyAsync(h_bad, d_bad_slot, sizeof(int32_t) * cap_slots, hipMemcpyDeviceToHost, stream));
+        HIP_TRY(hipStreamSynchronize(stream));
+        for (size_t i = 0; i < which.size(); ++i)
+            if (h_bad[which[i]] != 0) {
+                if (bad_index) *bad_index = (int32_t)i;
+                return fail(OMAP_ERR_SOURCE_ON_OBSTACLE, "%d source(s) lie on obstacles", h_bad[which[i]]);
+            }
+        return OMAP_OK;
+    }
+
+    // Re-pack slot k with a new problem of the same size (synchronous).
+    omap_status_t pack(int32_t k, const uint8_t* occ_dev, const int32_t* src, int32_t n_src,
+                       const int32_t* tgt, int32_t n_tgt) {
+        OK_TRY(pack_async(k, occ_dev, src, n_src, tgt, n_tgt));
+        std::vector<int32_t> one{k};
+        return commit(one, nullptr);
+    }
+
+    // Allocate slot buffers and a tile id range, then pack.  With defer the
+    // source check is left to a later commit(); otherwise it is synchronous and
+    // a failing maze is removed again.
     omap_status_t add(int32_t H, int32_t W, const uint8_t* occ_dev, const int32_t* src,
-                      int32_t n_src, const int32_t* tgt, int32_t n_tgt, int32_t* slot_out) {
+                      int32_t n_src, const int32_t* tgt, int32_t n_tgt, int32_t* slot_out,
+                      bool defer = false) {
         OK_TRY(validate_problem(H, W, occ_dev, src, n_src, tgt, n_tgt));
         const int32_t k = free_slot_index();
         if (k < 0) return fail(OMAP_ERR_OUT_OF_MEMORY, "no free maze slot (capacity %d)", cap_slots);
@@ -506,39 +561,39 @@ class Solver {
         if (nt > cap_tiles || !take_tiles((int32_t)nt, &s.tile_base))
             return fail(OMAP_ERR_OUT_OF_MEMORY, "no tile ids left for %lld tiles", (long long)nt);
         s.n_tiles = (int32_t)nt;
+        s.used = true;
         s.V[0] = static_cast<int32_t*>(mem->alloc(s.g.v_bytes));
         s.V[1] = static_cast<int32_t*>(mem->alloc(s.g.v_bytes));
         s.mask = static_cast<uint32_t*>(mem->alloc(s.g.m_bytes));
-        s.used = true;
         if (!s.V[0] || !s.V[1] || !s.mask) {
             remove(k);
             return fail(OMAP_ERR_OUT_OF_MEMORY, "activity and mask buffers for %d x %d", H, W);
         }
-        omap_status_t st = pack(k, occ_dev, src, n_src, tgt, n_tgt);
+        omap_status_t st = pack_async(k, occ_dev, src, n_src, tgt, n_tgt);
+        if (st == OMAP_OK) st = upload_tile_range(s.tile_base, s.n_tiles, k);
+        if (st == OMAP_OK) st = upload_desc(k);
+        if (st == OMAP_OK && !defer) {
+            std::vector<int32_t> one{k};
+            st = commit(one, nullptr);
+        }
         if (st != OMAP_OK) {
             const std::string msg = g_last_error;
             remove(k);
             g_last_error = msg;
             return st;
         }
-        std::vector<int32_t> ids(s.n_tiles, k);
-        HIP_TRY(hipMemcpyAsync(d_tile_maze + s.tile_base, ids.data(), sizeof(int32_t) * ids.size(),
-                               hipMemcpyHostToDevice, stream));
-        OK_TRY(upload_desc(k));
         *slot_out = k;
         return OMAP_OK;
     }
 
+    // Forget slot k: its tile ids and buffers go back to the pools
+    // (stream-ordered).
     omap_status_t remove(int32_t k) {
         Slot& s = slots[k];
         if (!s.used) return OMAP_OK;
         if (s.n_tiles > 0) {
-            std::vector<int32_t> ids(s.n_tiles, -1);
-            HIP_TRY(hipMemcpyAsync(d_tile_maze + s.tile_base, ids.data(),
-                                   sizeof(int32_t) * ids.size(), hipMemcpyHostToDevice, stream));
-            const int32_t idle = kMazeIdle;
-            HIP_TRY(hipMemcpyAsync(d_state + k, &idle, sizeof idle, hipMemcpyHostToDevice, stream));
-            HIP_TRY(hipStreamSynchronize(stream));
+            OK_TRY(upload_tile_range(s.tile_base, s.n_tiles, -1));
+            HIP_TRY(hipMemsetAsync(d_state + k, 0, sizeof(int32_t), stream));   // kMazeIdle
             give_tiles(s.tile_base, s.n_tiles);
         }
         free_slot_buffers(s);
@@ -547,7 +602,7 @@ class Solver {
     }
 
     // Reset slot k's activity and seed it for L layers (L < 0: run-time L).
-    // Stream-ordered; the maze joins the schedule at the next round's build.
+    // Stream-ordered: the maze's tiles join the next round.
     omap_status_t start(int32_t k, int64_t L) {
         Slot& s = slots[k];
         if (L < -1) return fail(OMAP_ERR_INVALID_ARG, "max_layers must be >= 0 or OMAP_AUTO_LAYERS");
@@ -558,27 +613,28 @@ class Solver {
         OK_TRY(upload_desc(k));
         HIP_TRY(launch_fill(s.V[0], s.g.v_bytes / 4, 0, stream));
         HIP_TRY(launch_fill(s.V[1], s.g.v_bytes / 4, 0, stream));
-        HIP_TRY(hipMemsetAsync(d_bad, 0, sizeof(int32_t), stream));
-        HIP_TRY(launch_seed(d_mazes, k, s.d_src, (int32_t)(s.src.size() / 2), opt.TH, opt.TW, d_flags,
-                            d_changed, d_bad, stream));
-        const int32_t running = kMazeRunning;
-        const int64_t zero = 0;
-        HIP_TRY(hipMemcpyAsync(d_state + k, &running, sizeof(int32_t), hipMemcpyHostToDevice, stream));
-        HIP_TRY(hipMemcpyAsync(d_rounds + k, &zero, sizeof zero, hipMemcpyHostToDevice, stream));
-        HIP_TRY(hipMemcpyAsync(d_visits + k, &zero, sizeof zero, hipMemcpyHostToDevice, stream));
-        HIP_TRY(hipMemcpyAsync(d_cell_visits + k, &zero, sizeof zero, hipMemcpyHostToDevice, stream));
-        HIP_TRY(hipStreamSynchronize(stream));   // host sources of the copies above
+        const RoundArgs a = round_args(true);
+        HIP_TRY(launch_slot_reset(a, k, stream));
+        HIP_TRY(launch_seed(a, k, s.d_src, (int32_t)(s.src.size() / 2), d_bad, stream));
+        if (opt.dense) HIP_TRY(launch_schedule_all(a, k, s.n_tiles, stream));
         s.started = true;
         s.finalized = false;
         s.layers = -1;
         return OMAP_OK;
     }
 
+    // Empty schedule (before starting every resident maze afresh).
     omap_status_t reset_schedule() {
-        HIP_TRY(hipMemsetAsync(d_count + parity, 0, sizeof(int32_t), stream));
+        HIP_TRY(hipMemsetAsync(d_count, 0, 2 * sizeof(int32_t), stream));
+        HIP_TRY(hipMemsetAsync(d_flags[0], 0, sizeof(int32_t) * std::max(tile_hwm, 1), stream));
+        HIP_TRY(hipMemsetAsync(d_flags[1], 0, sizeof(int32_t) * std::max(tile_hwm, 1), stream));
+        HIP_TRY(hipMemsetAsync(d_sched, 0, sizeof(int32_t) * cap_slots, stream));
+        HIP_TRY(hipMemsetAsync(d_sched_cells, 0, sizeof(unsigned long long) * cap_slots, stream));
+        HIP_TRY(hipMemsetAsync(d_changed, 0, sizeof(int32_t) * cap_slots, stream));
         return OMAP_OK;
     }
 
+    // One round: the sweep over this round's tiles, then the one-block finish.
     omap_status_t round() {
         const RoundArgs a = round_args();
         if (prof) {
@@ -586,14 +642,13 @@ class Solver {
             HIP_TRY(hipEventCreate(&ev.first));
             HIP_TRY(hipEventCreate(&ev.second));
             HIP_TRY(hipEventRecord(ev.first, stream));
-            HIP_TRY(launch_sweep(opt.T, a, grid, stream));
+            HIP_TRY(launch_sweep(opt.T, opt.C, a, grid, stream));
             HIP_TRY(hipEventRecord(ev.second, stream));
             prof_events.push_back(ev);
         } else {
-            HIP_TRY(launch_sweep(opt.T, a, grid, stream));
+            HIP_TRY(launch_sweep(opt.T, opt.C, a, grid, stream));
         }
-        HIP_TRY(launch_build(a, stream));
-        HIP_TRY(launch_update(a, stream));
+        HIP_TRY(launch_finish(a, stream));
         parity ^= 1;
         return OMAP_OK;
     }
@@ -719,7 +774,7 @@ class Solver {
         int64_t total = 0;
         std::memcpy(&total, h_pinned, sizeof total);
         if (needed) *needed = total;
-        if (cells_out == nullptr || capacity < total)
+        if (capacity < total || (total > 0 && cells_out == nullptr))
             return fail(OMAP_ERR_BUFFER_TOO_SMALL, "paths need %lld cells, capacity %lld",
                         (long long)total, (long long)capacity);
         int32_t* walk_dst = cells_out;
@@ -814,7 +869,7 @@ struct omap_plan_s {
 };
 
 struct omap_batch_s {
-    omap::DirectMemory mem;
+    omap::ArenaMemory mem;   // one device allocation holding every maze's buffers
     omap::Solver solver;
     std::vector<int32_t> slots;
     bool propagated = false;
@@ -1089,18 +1144,29 @@ omap_status_t omap_batch_create(omap_batch_t* out, const omap_maze_desc* mazes, 
         tiles += (int64_t)g.tiles_x * g.tiles_y;
     }
     if (tiles >= (int64_t(1) << 31)) return fail(OMAP_ERR_TOO_LARGE, "too many tiles");
+    int64_t bytes = 0;
+    for (int32_t i = 0; i < n_mazes; ++i)
+        bytes += maze_device_bytes(mazes[i].height, mazes[i].width, o) + 8 * (int64_t)mazes[i].n_sources + 1024;
     std::unique_ptr<omap_batch_s> b(new omap_batch_s());
+    if (!b->mem.init((size_t)bytes))
+        return fail(OMAP_ERR_OUT_OF_MEMORY, "batch buffers (%lld bytes)", (long long)bytes);
     OK_TRY(b->solver.init(static_cast<hipStream_t>(stream), o, &b->mem, n_mazes, (int32_t)tiles));
     for (int32_t i = 0; i < n_mazes; ++i) {
         const omap_maze_desc& d = mazes[i];
         int32_t slot = -1;
         omap_status_t st = b->solver.add(d.height, d.width, d.occupancy_dev, d.sources_host, d.n_sources,
-                                         d.targets_host, d.n_targets, &slot);
+                                         d.targets_host, d.n_targets, &slot, true);
         if (st != OMAP_OK) {
             g_last_error += " (maze " + std::to_string(i) + ")";
             return st;
         }
         b->slots.push_back(slot);
+    }
+    int32_t bad = -1;
+    omap_status_t st = b->solver.commit(b->slots, &bad);
+    if (st != OMAP_OK) {
+        g_last_error += " (maze " + std::to_string(bad) + ")";
+        return st;
     }
     *out = b.release();
     return OMAP_OK;

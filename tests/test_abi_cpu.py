@@ -74,8 +74,9 @@ def test_plan_create_validation(args, status):
 
 def test_plan_create_null_out_and_bad_options():
     assert omap.STATUS[_create(5, 5, FAKE, [[0, 0]], [], out=False)] == "OMAP_ERR_INVALID_ARG"
-    for bad in (omap.Options(3, 0, 0, 0), omap.Options(0, 3, 0, 0), omap.Options(0, 0, 7, 0),
-                omap.Options(16, 8, 0, 0), omap.Options(0, 0, 0, -1)):
+    for bad in (omap.Options(3, 0, 0, 0, 0), omap.Options(0, 3, 0, 0, 0), omap.Options(0, 0, 7, 0, 0),
+                omap.Options(16, 8, 0, 0, 0), omap.Options(0, 0, 0, -1, 0), omap.Options(0, 0, 0, 0, 3),
+                omap.Options(24, 0, 0, 0, 4), omap.Options(32, 16, 0, 0, 2)):
         assert omap.STATUS[_create(5, 5, FAKE, [[0, 0]], [], opts=bad)] == "OMAP_ERR_INVALID_ARG"
 
 

@@ -27,19 +27,28 @@ def test_selftest():
     omap.selftest()
 
 
-@pytest.mark.parametrize("T", ALL_T)
-@pytest.mark.parametrize("tile_rows", [16, 64])
-def test_random_mazes_all_depths(T, tile_rows):
-    rng = np.random.default_rng(100 + T + tile_rows)
-    for i in range(12):
+VARIANTS = [(T, 4) for T in ALL_T] + [(T, 2) for T in (4, 8, 12, 16, 24, 32)]
+
+
+@pytest.mark.parametrize("T,C", VARIANTS)
+@pytest.mark.parametrize("tile_rows", [32, 64])
+def test_random_mazes_all_variants(T, C, tile_rows):
+    rng = np.random.default_rng(100 + T + tile_rows + C)
+    for i in range(10):
         H, W = int(rng.integers(1, 300)), int(rng.integers(1, 700))
-        if tile_rows < T:
-            continue
         m = workloads.random_maze(H, W, float(rng.uniform(0, 0.45)), int(rng.integers(1, 6)),
-                                  int(rng.integers(0, 40)), 7000 + 31 * T + i)
+                                  int(rng.integers(0, 40)), 7000 + 31 * T + 7 * C + i)
         for L in (-1, int(rng.integers(0, 50))):
-            got = run_plan(m, L, temporal_depth=T, tile_rows=tile_rows)
-            assert_same(m, got, oracle_solution(m, L), f"{m.name} L={L} T={T} TH={tile_rows}")
+            got = run_plan(m, L, temporal_depth=T, tile_rows=tile_rows, lane_columns=C)
+            assert_same(m, got, oracle_solution(m, L), f"{m.name} L={L} T={T} C={C} TH={tile_rows}")
+
+
+@pytest.mark.parametrize("T,C", VARIANTS)
+def test_minimum_tile_rows(T, C):
+    m = workloads.random_maze(211, 389, 0.3, 3, 25, 555 + T + C)
+    for L in (-1, 17):
+        got = run_plan(m, L, temporal_depth=T, tile_rows=T, lane_columns=C)
+        assert_same(m, got, oracle_solution(m, L), f"T={T} C={C} TH=T L={L}")
 
 
 @pytest.mark.parametrize("shape", [(1, 1), (1, 2), (2, 1), (1, 1000), (1000, 1), (3, 257), (257, 3),
@@ -49,9 +58,9 @@ def test_edge_shapes(shape):
     for seed in range(3):
         m = workloads.random_maze(H, W, 0.25, 2, 10, 9000 + seed * 7 + H)
         for L in (-1, 0, 1, 5):
-            for T in (4, 16):
-                got = run_plan(m, L, temporal_depth=T, tile_rows=max(T, 8))
-                assert_same(m, got, oracle_solution(m, L), f"{shape} L={L} T={T}")
+            for T, C in ((4, 4), (16, 4), (8, 2), (32, 2)):
+                got = run_plan(m, L, temporal_depth=T, tile_rows=max(T, 8), lane_columns=C)
+                assert_same(m, got, oracle_solution(m, L), f"{shape} L={L} T={T} C={C}")
 
 
 def test_sources_on_borders_and_corners():
@@ -80,9 +89,9 @@ def test_pockets_duplicates_and_special_targets():
     tgt = np.array([[30, 40], [65, 15], [5, 5], [70, 80], [0, 0], [79, 89], [30, 40]], np.int32)
     m = workloads.Maze(occ, src, tgt, "pockets")
     for L in (-1, 0, 1, 2, 30, 200):
-        for T in ALL_T:
-            assert_same(m, run_plan(m, L, temporal_depth=T, tile_rows=16), oracle_solution(m, L),
-                        f"pockets L={L} T={T}")
+        for T, C in VARIANTS:
+            assert_same(m, run_plan(m, L, temporal_depth=T, tile_rows=max(16, T), lane_columns=C),
+                        oracle_solution(m, L), f"pockets L={L} T={T} C={C}")
 
 
 def test_isolated_source_and_all_obstacles():
@@ -108,12 +117,13 @@ def test_large_layer_count():
 def test_schedules_and_options_identical_bits():
     m = workloads.random_maze(333, 517, 0.35, 3, 50, 31337)
     ref = oracle_solution(m, -1)
-    for T in ALL_T:
-        for th in (T, 2 * T + 2, 64, 256):
+    for T, C in VARIANTS:
+        for th in sorted({T, 2 * T + 2, 64, 256}):
             for sched in (0, 1):
                 for chk in (0, 1, 5):
-                    got = run_plan(m, -1, temporal_depth=T, tile_rows=th, schedule=sched, check_interval=chk)
-                    assert_same(m, got, ref, f"T={T} th={th} sched={sched} chk={chk}")
+                    got = run_plan(m, -1, temporal_depth=T, tile_rows=th, schedule=sched, check_interval=chk,
+                                   lane_columns=C)
+                    assert_same(m, got, ref, f"T={T} C={C} th={th} sched={sched} chk={chk}")
 
 
 def test_config1():
