@@ -60,6 +60,10 @@ class Oracle:
         for fn in (L.oracle_walk, L.oracle_walk_euclidean):
             fn.argtypes = [i32, i32, P, P, i32, P, i32, P, P, P, i64]
             fn.restype = i64
+        L.oracle_walk_random.argtypes = [i32, i32, P, P, i32, P, i32, ctypes.c_uint64, P, P, P, i64]
+        L.oracle_walk_random.restype = i64
+        L.oracle_tie_hash.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64]
+        L.oracle_tie_hash.restype = ctypes.c_uint64
         self.lib = L
         self.path = path
 
@@ -121,6 +125,15 @@ class Oracle:
         """Euclidean path reconstruction on activity map O. Returns (len, offsets, cells)."""
         return self._walk(self.lib.oracle_walk_euclidean, O, sources, targets, capacity)
 
+    def walk_random(self, O, sources, targets, seed: int, capacity=None):
+        """Simple path reconstruction with seeded random ties. Returns (len, offsets, cells)."""
+        fn = lambda H, W, o, s, ns, t, nt, ln, off, cells, cap: self.lib.oracle_walk_random(  # noqa: E731
+            H, W, o, s, ns, t, nt, int(seed) & 0xFFFFFFFFFFFFFFFF, ln, off, cells, cap)
+        return self._walk(fn, O, sources, targets, capacity)
+
+    def tie_hash(self, seed: int, target: int, step: int) -> int:
+        return int(self.lib.oracle_tie_hash(seed & 0xFFFFFFFFFFFFFFFF, target, step))
+
 
 _default = None
 
@@ -152,3 +165,7 @@ def walk(O, sources, targets, capacity=None):
 
 def walk_euclidean(O, sources, targets, capacity=None):
     return default().walk_euclidean(O, sources, targets, capacity)
+
+
+def walk_random(O, sources, targets, seed: int, capacity=None):
+    return default().walk_random(O, sources, targets, seed, capacity)

@@ -30,6 +30,9 @@
  *   oracle_walk_euclidean  Euclidean path reconstruction; parity unpinned by the
  *                          paper (no printed path); checked for validity and
  *                          cost against octile-distance bounds only.
+ *   oracle_walk_random     simple reconstruction with the paper's random ties
+ *                          (counter-based hash); pinned by path validity, step
+ *                          count = BFS distance and the spread of choices.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -240,16 +243,19 @@ int64_t oracle_walk(int32_t H, int32_t W, const int64_t *O, const int32_t *src_r
  * (2) straighten: remove an intermediate point P(t) when P(t-1) and P(t+1) are
  *     sqrt(2) apart, i.e. diagonal neighbours.
  * READING (ties): first maximum in the order up, left, right, down.
- * READING (dead ends): step (1) can cycle when the only way up the activity
- *     gradient is a diagonal step between two obstacles.  The walk never
- *     revisits a cell and, if every unvisited 4-neighbour has lower activity
- *     than the current cell, takes the simple-reconstruction step (8
- *     neighbours).
+ * READING (cycles): the literal rule can step sideways forever (two cells of
+ *     equal activity choosing each other, e.g. when the only way up is a
+ *     diagonal step between two obstacles).  Here a sideways move (to a
+ *     4-neighbour of equal activity) is allowed only if the previous move was
+ *     not sideways; when no 4-neighbour is higher and a sideways move is not
+ *     allowed, the walk takes the simple-reconstruction step (first maximal
+ *     8-neighbour), which always climbs.  Activity never decreases along the
+ *     walk, so no cell is visited twice and at most 2 d(t) moves are made.
  * READING (straightening order): one left-to-right pass over the current list;
  *     a removed point is gone before the next triple is examined.
  * Output layout as oracle_walk; len = number of segments of the final path.
  * Returns the total number of cells, -1 if the capacity is too small, -2 if a
- * walk does not end. */
+ * walk does not end, -3 on allocation failure. */
 int64_t oracle_walk_euclidean(int32_t H, int32_t W, const int64_t *O, const int32_t *src_rc,
                               int32_t n_src, const int32_t *tgt_rc, int32_t n_tgt, int32_t *len,
                               int64_t *offsets, int32_t *cells, int64_t cells_capacity)
@@ -257,9 +263,8 @@ int64_t oracle_walk_euclidean(int32_t H, int32_t W, const int64_t *O, const int3
     static const int M_DR[4] = {-1, 0, 0, 1};
     static const int M_DC[4] = {0, -1, 1, 0};
     const int64_t N = (int64_t)H * W;
-    uint8_t *seen = (uint8_t *)calloc((size_t)(N > 0 ? N : 1), 1);
-    int32_t *buf = (int32_t *)malloc(sizeof(int32_t) * (size_t)(N + 1));
-    if (!seen || !buf) { free(seen); free(buf); return -3; }
+    int32_t *buf = (int32_t *)malloc(sizeof(int32_t) * (size_t)(2 * N + 2));
+    if (!buf) return -3;
     int64_t total = 0;
     int64_t rc = 0;
     for (int32_t t = 0; t < n_tgt; ++t) {
@@ -267,18 +272,22 @@ int64_t oracle_walk_euclidean(int32_t H, int32_t W, const int64_t *O, const int3
         int64_t p = (int64_t)tgt_rc[2 * t] * W + tgt_rc[2 * t + 1];
         if (O[p] <= 0) { len[t] = -1; continue; }
         int64_t k = 0;
+        int sideways_before = 0;
         buf[k++] = (int32_t)p;
-        seen[p] = 1;
         while (!is_source(p, W, src_rc, n_src)) {
             const int32_t r = (int32_t)(p / W), c = (int32_t)(p % W);
-            int64_t best = -1, best_v = O[p] - 1;   /* accept equal or higher */
+            int64_t best = -1, best_v = INT64_MIN;
             for (int m = 0; m < 4; ++m) {
                 const int32_t rr = r + M_DR[m], cc = c + M_DC[m];
                 if (rr < 0 || rr >= H || cc < 0 || cc >= W) continue;
                 const int64_t y = (int64_t)rr * W + cc;
-                if (!seen[y] && O[y] > best_v) { best_v = O[y]; best = y; }
+                if (O[y] > best_v) { best_v = O[y]; best = y; }
             }
-            if (best < 0) {   /* every unvisited 4-neighbour is lower: 8-neighbour step */
+            if (best >= 0 && best_v > O[p]) {
+                sideways_before = 0;                       /* climb */
+            } else if (best >= 0 && best_v == O[p] && !sideways_before) {
+                sideways_before = 1;                       /* sideways */
+            } else {                                       /* 8-neighbour step */
                 best_v = INT64_MIN;
                 for (int m = 0; m < 8; ++m) {
                     const int32_t rr = r + NB_DR[m], cc = c + NB_DC[m];
@@ -286,11 +295,11 @@ int64_t oracle_walk_euclidean(int32_t H, int32_t W, const int64_t *O, const int3
                     const int64_t y = (int64_t)rr * W + cc;
                     if (O[y] > best_v) { best_v = O[y]; best = y; }
                 }
+                sideways_before = 0;
             }
             p = best;
-            if (k > N) { rc = -2; goto done; }
+            if (k > 2 * N) { rc = -2; goto done; }
             buf[k++] = (int32_t)p;
-            seen[p] = 1;
         }
         /* straightening pass over triples (last kept point, buf[i], buf[i+1]) */
         int64_t out_n = 0;
@@ -307,14 +316,65 @@ int64_t oracle_walk_euclidean(int32_t H, int32_t W, const int64_t *O, const int3
             cells[total + out_n] = buf[i];
             ++out_n;
         }
-        for (int64_t i = 0; i < k; ++i) seen[buf[i]] = 0;
         len[t] = (int32_t)(out_n - 1);
         total += out_n;
     }
     offsets[n_tgt] = total;
     rc = total;
 done:
-    free(seen);
     free(buf);
     return rc;
+}
+
+/* Counter-based random numbers for the random tie-break: the SplitMix64 output
+ * function (Steele, Lea, Flood 2014) applied to seed ^ (target << 32) ^ step. */
+uint64_t oracle_tie_hash(uint64_t seed, uint64_t target, uint64_t step)
+{
+    uint64_t z = seed ^ (target << 32) ^ step;
+    z += 0x9e3779b97f4a7c15ULL;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+    return z ^ (z >> 31);
+}
+
+/* Simple path reconstruction with the paper's random choice among maximal
+ * neighbours (Sec. "Path Reconstruction"): at move s from target t, the
+ * maximal 8-neighbours are listed in the fixed order and the one at position
+ * oracle_tie_hash(seed, t, s) mod (their number) is taken.  Output as
+ * oracle_walk. */
+int64_t oracle_walk_random(int32_t H, int32_t W, const int64_t *O, const int32_t *src_rc,
+                           int32_t n_src, const int32_t *tgt_rc, int32_t n_tgt, uint64_t seed,
+                           int32_t *len, int64_t *offsets, int32_t *cells, int64_t cells_capacity)
+{
+    const int64_t N = (int64_t)H * W;
+    int64_t total = 0;
+    for (int32_t t = 0; t < n_tgt; ++t) {
+        offsets[t] = total;
+        int64_t p = (int64_t)tgt_rc[2 * t] * W + tgt_rc[2 * t + 1];
+        if (O[p] <= 0) { len[t] = -1; continue; }
+        int64_t steps = 0;
+        if (total >= cells_capacity) return -1;
+        cells[total++] = (int32_t)p;
+        while (!is_source(p, W, src_rc, n_src)) {
+            const int32_t r = (int32_t)(p / W), c = (int32_t)(p % W);
+            int64_t cand[8];
+            int n_cand = 0;
+            int64_t best_v = INT64_MIN;
+            for (int k = 0; k < 8; ++k) {
+                const int32_t rr = r + NB_DR[k], cc = c + NB_DC[k];
+                if (rr < 0 || rr >= H || cc < 0 || cc >= W) continue;
+                const int64_t y = (int64_t)rr * W + cc;
+                if (O[y] > best_v) { best_v = O[y]; n_cand = 0; }
+                if (O[y] == best_v) cand[n_cand++] = y;
+            }
+            p = cand[oracle_tie_hash(seed, (uint64_t)t, (uint64_t)steps) % (uint64_t)n_cand];
+            ++steps;
+            if (steps > N) return -2;
+            if (total >= cells_capacity) return -1;
+            cells[total++] = (int32_t)p;
+        }
+        len[t] = (int32_t)steps;
+    }
+    offsets[n_tgt] = total;
+    return total;
 }

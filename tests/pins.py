@@ -433,6 +433,53 @@ def check_euclidean_walk(o, n_cases=40):
             assert cost >= min(_octile(tuple(t), s) for s in srcset) - 1e-9
 
 
+def check_tie_hash_vectors(o):
+    """The tie-break hash is SplitMix64's output function: from state 0 the
+    published generator yields the three reference values."""
+    with open(os.path.join(GOLDEN, "splitmix64.json")) as f:
+        g = json.load(f)
+    outs = [int(x, 16) for x in g["state0_outputs_hex"]]
+    inc = int(g["increment_hex"], 16)
+    state = 0
+    for want in outs:
+        assert o.tie_hash(state, 0, 0) == want          # output after one increment from `state`
+        state = (state + inc) & 0xFFFFFFFFFFFFFFFF
+    # target and step enter as (target << 32) ^ step
+    assert o.tie_hash(5, 3, 7) == o.tie_hash(5 ^ (3 << 32) ^ 7, 0, 0)
+
+
+def check_walk_random(o, n_cases=40):
+    """Random ties (Sec. 'Path Reconstruction'): every path is a shortest path
+    (valid, climbs by one per step, steps = BFS distance), the same seed gives
+    the same path, and where three neighbours tie the choice is spread evenly."""
+    for m in maze_cases(n_cases, 41, hmax=28, pmax=0.45):
+        d, _ = o.bfs(m.occ, m.sources)
+        A, _ = o.layers(m.occ, m.sources, -1)
+        for seed in (0, 1, 12345):
+            ln, off, cells = o.walk_random(A, m.sources, m.targets, seed)
+            l2, o2, c2 = o.walk_random(A, m.sources, m.targets, seed)
+            assert np.array_equal(cells, c2) and np.array_equal(ln, l2)
+            for k, t in enumerate(m.targets):
+                tr, tc = int(t[0]), int(t[1])
+                if d[tr, tc] < 0:
+                    assert ln[k] == -1
+                    continue
+                path = [divmod(int(x), m.W) for x in cells[off[k]:off[k + 1]]]
+                assert path[0] == (tr, tc) and ln[k] == d[tr, tc]
+                _check_path_valid(m.occ, m.sources, path, int(ln[k]))
+                vals = [A[p] for p in path]
+                assert all(b == a + 1 for a, b in zip(vals, vals[1:]))
+    occ = np.zeros((9, 9), np.uint8)
+    A, _ = o.layers(occ, [(0, 0)], -1)
+    counts = {}
+    for seed in range(300):
+        ln, off, cells = o.walk_random(A, [(0, 0)], [(4, 8)], seed)
+        first = divmod(int(cells[1]), 9)
+        counts[first] = counts.get(first, 0) + 1
+    assert set(counts) == {(3, 7), (4, 7), (5, 7)}
+    assert all(60 <= c <= 140 for c in counts.values()), counts
+
+
 ALL_CHECKS = [
     check_layer_one_facts,
     check_source_value,
@@ -447,4 +494,6 @@ ALL_CHECKS = [
     check_source_on_obstacle_plateau,
     check_comb_bound,
     check_euclidean_walk,
+    check_tie_hash_vectors,
+    check_walk_random,
 ]

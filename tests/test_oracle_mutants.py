@@ -37,6 +37,10 @@ MUTANTS = [
      "        while", 1),
     ("walk_zero_activity_allowed", "if (O[p] <= 0) { len[t] = -1; continue; }",
      "if (O[p] < 0) { len[t] = -1; continue; }", 1),
+    ("random_ties_always_first", "p = cand[oracle_tie_hash(seed, (uint64_t)t, (uint64_t)steps) % (uint64_t)n_cand];",
+     "p = cand[0];", 1),
+    ("tie_hash_wrong_shift", "z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;", "z = (z ^ (z >> 26)) * 0x94d049bb133111ebULL;", 1),
+    ("euclid_no_straightening", "if (dr == 1 && dc == 1) continue;   /* drop buf[i] */", "if (0) continue;", 1),
 ]
 
 
