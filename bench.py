@@ -210,7 +210,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "batch", "serve", "copy"])
+    ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "batch", "serve", "copy", "paper"])
     ap.add_argument("--depth", type=int, default=0)
     ap.add_argument("--tile-rows", type=int, default=0)
     ap.add_argument("--schedule", type=int, default=0)
@@ -233,6 +233,9 @@ def main():
     elif args.workload == "batch":
         from bench_forms import bench_batch
         out = bench_batch(args)
+    elif args.workload == "paper":
+        from bench_forms import bench_paper
+        out = bench_paper(args)
     else:
         from bench_forms import bench_serve
         out = bench_serve(args)

@@ -182,3 +182,63 @@ def bench_serve(args):
         "plain_loop_mazes_per_s": round(plain_rate, 2),
         "capacity_vs_plain_loop": round(capacity / plain_rate, 2),
     }
+
+
+# The paper's own run-time workloads (empty maps, fixed L), with the times the
+# paper reports on its hardware (context only, other GPUs):
+#   Table gpu_comp: 2000x2000, 2000 layers, one pass: 2.370 s (GTX 1080 Ti), 0.871 s (Titan V)
+#   Sec. "Run-time": t_r(n, L) ~ 3.0751e-10 * L * n^2 s (GTX 1080 Ti), n in 500..4000
+#   Sec. "Limitations": n = 26,000, L = 3,450: 692.3 s; 5,000 sources, L = 650: 147.4 s
+PAPER_CASES = [
+    # (name, n, L, n_sources, paper_seconds, paper_hw)
+    ("gpu_comp_2000_L2000", 2000, 2000, 1, 2.370, "GTX 1080 Ti"),
+    ("time_pro_1000_L1000", 1000, 1000, 1, 3.0751e-10 * 1000 * 1000 ** 2, "GTX 1080 Ti (fit)"),
+    ("time_pro_2000_L4000", 2000, 4000, 1, 3.0751e-10 * 4000 * 2000 ** 2, "GTX 1080 Ti (fit)"),
+    ("time_pro_4000_L8000", 4000, 8000, 1, 3.0751e-10 * 8000 * 4000 ** 2, "GTX 1080 Ti (fit)"),
+    ("big_26000_L3450", 26000, 3450, 1, 692.3, "GTX 1080 Ti"),
+    ("big_26000_5000src_L650", 26000, 650, 5000, 147.4, "GTX 1080 Ti"),
+]
+
+
+def bench_paper(args):
+    """Empty n x n maps run for exactly L layers (the paper's output A_L), one
+    source in the corner (the paper's worst case) or k seeded random sources;
+    timed with the dense and the active schedule."""
+    import torch
+    import paper_2004_00540_amd as omap
+    import workloads
+
+    dev = torch.device("cuda:0")
+    rows = []
+    for name, n, L, k, paper_s, hw in PAPER_CASES:
+        occ = torch.zeros((n, n), dtype=torch.uint8, device=dev)
+        if k == 1:
+            src = np.array([[0, 0]], np.int32)
+        else:
+            rc = workloads.below(5, 11, n * n, k)
+            src = np.unique(np.stack([rc // n, rc % n], 1).astype(np.int32), axis=0)
+        row = {"case": name, "n": n, "layers": L, "sources": int(len(src)),
+               "paper_s": round(paper_s, 4), "paper_hw": hw}
+        for sched, label in ((omap.SCHEDULE_DENSE, "dense"), (omap.SCHEDULE_ACTIVE, "active")):
+            with omap.Plan(occ, src, None, schedule=sched, temporal_depth=args.depth,
+                           tile_rows=args.tile_rows) as plan:
+                plan.propagate(L)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                plan.propagate(L, sync=False)
+                torch.cuda.synchronize()
+                t = time.perf_counter() - t0
+            row[f"{label}_s"] = round(t, 5)
+            row[f"{label}_gcell_updates_per_s"] = round(n * n * L / t / 1e9, 1)
+            row[f"{label}_speedup_vs_paper"] = round(paper_s / t, 1)
+        _log(row)
+        rows.append(row)
+        del occ
+        torch.cuda.empty_cache()
+    best = rows[0]
+    return {
+        "metric": "Gcell-updates/s", "value": best["active_gcell_updates_per_s"], "unit": "Gcell-updates/s",
+        "n_gpus": 1, "steps": 1, "warmup": 1, "ms_per_step": round(best["active_s"] * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
+        "data": "synthetic", "config": {"workload": "paper_empty_maps_fixed_L"}, "cases": rows,
+    }

@@ -82,12 +82,12 @@ typedef struct omap_options {
     int32_t temporal_depth;  /* layers applied per tile visit: 4, 8, 12, 16 (and 24, 32    */
                              /* with lane_columns = 2); 0 = default (16)                   */
     int32_t tile_rows;       /* interior rows per tile, even, 2..4096, >= temporal_depth;  */
-                             /* 0 = default (max(16, temporal_depth))                      */
+                             /* 0 = default (active: max(16, depth); dense: 256)           */
     int32_t schedule;        /* OMAP_SCHEDULE_ACTIVE or OMAP_SCHEDULE_DENSE                 */
     int32_t check_interval;  /* rounds between host reads of the convergence count;        */
                              /* 0 = adaptive                                                */
     int32_t lane_columns;    /* columns each lane owns (tile strip = 64 x this): 2 or 4;   */
-                             /* 0 = default (4)                                            */
+                             /* 0 = default (active: 2; dense: 4)                          */
 } omap_options;
 
 /* Per-maze report of a propagation. */
@@ -155,6 +155,36 @@ omap_status_t omap_extract_paths(omap_plan_t plan, int32_t *len_dev, int64_t *of
                                  int32_t *cells_dev, int64_t cells_capacity,
                                  int64_t *cells_needed_host);
 
+/* Path reconstruction variants (Sec. "Path Reconstruction"). */
+#define OMAP_WALK_FIRST_MAX 0     /* simple reconstruction, ties by the fixed neighbour order  */
+#define OMAP_WALK_RANDOM_TIES 1   /* simple reconstruction, the paper's random choice among     */
+                                  /* maximal neighbours, made reproducible: at move s of target */
+                                  /* t the choice is SplitMix64out(seed ^ (t << 32) ^ s) mod the */
+                                  /* number of maxima, maxima listed in the fixed order         */
+#define OMAP_WALK_EUCLIDEAN 2     /* Euclidean reconstruction (Eq. 1): climb through 4-neighbours */
+                                  /* (first maximum in the order up, left, right, down), at most */
+                                  /* one sideways move to an equal 4-neighbour per activity      */
+                                  /* level, else the first maximal 8-neighbour; then remove each */
+                                  /* point whose neighbours on the path are diagonal neighbours */
+                                  /* (one left-to-right pass).  len = segments of the result.    */
+
+typedef struct omap_walk_options {
+    int32_t mode;      /* OMAP_WALK_* */
+    int32_t reserved;  /* 0 */
+    uint64_t seed;     /* OMAP_WALK_RANDOM_TIES only */
+} omap_walk_options;
+
+/* omap_extract_paths with a reconstruction variant (walk NULL = FIRST_MAX)
+ * and, when source_index_dev is not NULL, n_targets int32 receiving the index
+ * in the source list of the source each path ends on (its closest source,
+ * first listed if repeated; -1 for no path) -- the paper's taxi assignment
+ * (Sec. "Multi-source Multi-target Path Planning").  Same synchrony and
+ * errors as omap_extract_paths. */
+omap_status_t omap_extract_paths_ex(omap_plan_t plan, const omap_walk_options *walk,
+                                    int32_t *len_dev, int64_t *offsets_dev, int32_t *cells_dev,
+                                    int64_t cells_capacity, int64_t *cells_needed_host,
+                                    int32_t *source_index_dev);
+
 /* Release the plan and its device buffers.  NULL is a no-op. */
 omap_status_t omap_plan_destroy(omap_plan_t plan);
 
@@ -195,6 +225,13 @@ omap_status_t omap_batch_get_activity(omap_batch_t batch, int32_t index, int32_t
 omap_status_t omap_batch_extract_paths(omap_batch_t batch, int32_t *len_dev, int64_t *offsets_dev,
                                        int32_t *cells_dev, int64_t cells_capacity,
                                        int64_t *cells_needed_host);
+
+/* omap_batch_extract_paths with a reconstruction variant and source indices
+ * (per maze: t and the source list are those of the target's own maze). */
+omap_status_t omap_batch_extract_paths_ex(omap_batch_t batch, const omap_walk_options *walk,
+                                          int32_t *len_dev, int64_t *offsets_dev, int32_t *cells_dev,
+                                          int64_t cells_capacity, int64_t *cells_needed_host,
+                                          int32_t *source_index_dev);
 
 omap_status_t omap_batch_destroy(omap_batch_t batch);
 

@@ -59,6 +59,13 @@ class PropagateInfo(ctypes.Structure):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
 
 
+WALK_FIRST_MAX, WALK_RANDOM_TIES, WALK_EUCLIDEAN = 0, 1, 2
+
+
+class WalkOptions(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("reserved", ctypes.c_int32), ("seed", ctypes.c_uint64)]
+
+
 class MazeDesc(ctypes.Structure):
     _fields_ = [("height", ctypes.c_int32), ("width", ctypes.c_int32),
                 ("occupancy_dev", ctypes.c_void_p),
@@ -86,6 +93,8 @@ def lib() -> ctypes.CDLL:
         "omap_propagate": [P, i64, P],
         "omap_get_activity": [P, P, i64],
         "omap_extract_paths": [P, P, P, P, i64, P],
+        "omap_extract_paths_ex": [P, P, P, P, P, i64, P, P],
+        "omap_batch_extract_paths_ex": [P, P, P, P, P, i64, P, P],
         "omap_plan_destroy": [P],
         "omap_batch_create": [PP, P, i32, P, P],
         "omap_batch_propagate": [P, P, P],
@@ -158,19 +167,32 @@ def selftest(stream=None) -> None:
     _check(lib().omap_selftest(ctypes.c_void_p(_stream(stream))))
 
 
-def _paths(extract, n_targets: int, device):
-    """Two-phase path extraction through an omap_*_extract_paths entry point."""
+def _paths(extract, n_targets: int, device, walk=None, source_index=False):
+    """Two-phase path extraction through an omap_*_extract_paths_ex entry point.
+    Returns (lengths, offsets, cells) or, with source_index, also the index of
+    the source each path ends on."""
     import torch
     lengths = torch.empty(max(n_targets, 1), dtype=torch.int32, device=device)
     offsets = torch.empty(n_targets + 1, dtype=torch.int64, device=device)
+    src = torch.empty(max(n_targets, 1), dtype=torch.int32, device=device) if source_index else None
+    wopt = ctypes.byref(walk) if walk is not None else None
+    sptr = src.data_ptr() if src is not None else None
     needed = ctypes.c_int64(0)
-    st = extract(lengths.data_ptr(), offsets.data_ptr(), None, 0, ctypes.byref(needed))
+    st = extract(wopt, lengths.data_ptr(), offsets.data_ptr(), None, 0, ctypes.byref(needed), sptr)
     if st not in (OK, ERR_BUFFER_TOO_SMALL):
         _check(st)
     cells = torch.empty(max(int(needed.value), 1), dtype=torch.int32, device=device)
-    _check(extract(lengths.data_ptr(), offsets.data_ptr(), cells.data_ptr(), cells.numel(),
-                   ctypes.byref(needed)))
-    return lengths[:n_targets], offsets, cells[: int(needed.value)]
+    _check(extract(wopt, lengths.data_ptr(), offsets.data_ptr(), cells.data_ptr(), cells.numel(),
+                   ctypes.byref(needed), sptr))
+    out = (lengths[:n_targets], offsets, cells[: int(needed.value)])
+    return out + (src[:n_targets],) if source_index else out
+
+
+def _walk_options(mode, seed):
+    if mode is None:
+        return None
+    m = {"first_max": WALK_FIRST_MAX, "random": WALK_RANDOM_TIES, "euclidean": WALK_EUCLIDEAN}.get(mode, mode)
+    return WalkOptions(int(m), 0, int(seed) & 0xFFFFFFFFFFFFFFFF)
 
 
 class Plan:
@@ -217,10 +239,12 @@ class Plan:
         _check(lib().omap_get_activity(self.handle, out.data_ptr(), int(out.stride(0))))
         return out
 
-    def paths(self):
-        """(lengths int32 [t], offsets int64 [t+1], cells int32) on the GPU."""
-        ex = lambda a, b, c, d, e: lib().omap_extract_paths(self.handle, a, b, c, d, e)  # noqa: E731
-        return _paths(ex, self.n_targets, self.device)
+    def paths(self, mode=None, seed: int = 0, source_index: bool = False):
+        """(lengths int32 [t], offsets int64 [t+1], cells int32) on the GPU
+        (+ source index per target).  mode: None / "first_max", "random",
+        "euclidean"."""
+        ex = lambda *a: lib().omap_extract_paths_ex(self.handle, *a)  # noqa: E731
+        return _paths(ex, self.n_targets, self.device, _walk_options(mode, seed), source_index)
 
     def extract_into(self, lengths, offsets, cells):
         needed = ctypes.c_int64(0)
@@ -303,9 +327,9 @@ class Batch:
         _check(lib().omap_batch_get_activity(self.handle, int(index), out.data_ptr(), int(out.stride(0))))
         return out
 
-    def paths(self):
-        ex = lambda a, b, c, d, e: lib().omap_batch_extract_paths(self.handle, a, b, c, d, e)  # noqa: E731
-        return _paths(ex, sum(self.n_targets), self.device)
+    def paths(self, mode=None, seed: int = 0, source_index: bool = False):
+        ex = lambda *a: lib().omap_batch_extract_paths_ex(self.handle, *a)  # noqa: E731
+        return _paths(ex, sum(self.n_targets), self.device, _walk_options(mode, seed), source_index)
 
     def profile(self, enable: bool):
         _check(lib().omap_profile_enable(self.handle, 1, int(enable)))

@@ -26,33 +26,35 @@ struct MazeDev {
     const uint32_t* mask;
 };
 
-// Per-maze progress states.
-enum : int32_t { kMazeIdle = 0, kMazeRunning = 1, kMazeDone = 2 };
-
-// Arguments of one round of the tile schedule.  Round r reads the tile list
-// and flags of parity r&1 and appends the tiles to visit in round r+1 to the
-// other parity; a tile is appended at most once per round (its flag is set by
-// an atomic exchange).
+// Arguments of round r of the tile schedule.  The tile lists and their dedup
+// flags alternate by r mod 2; the list counts, the per-maze scheduled counts
+// and the dense schedule's "changed" flags rotate over three buffers by r mod
+// 3, so that round r can clear the buffer round r+1 will fill without racing
+// with anything that reads or writes during round r.
 struct RoundArgs {
     const MazeDev* mazes;
     const int32_t* tile_maze;     // global tile id -> maze slot (-1 = unused id)
     int32_t n_tile_ids;           // size of the tile id space
-    const int32_t* list_in;       // tiles visited this round
-    int32_t* count_in;            // reset to 0 when the round finishes
-    int32_t* flags_in;            // cleared as the tiles of this round are visited
-    int32_t* list_out;            // tiles scheduled for the next round
-    int32_t* count_out;
-    int32_t* flags_out;           // 1 = already scheduled for the next round
-    int32_t* maze_changed;        // per slot: some tile changed this round
-    int32_t* maze_sched;          // per slot: tiles scheduled for the next round
-    unsigned long long* maze_sched_cells;  // per slot: their interior cells
-    int32_t* maze_state;          // per slot: kMaze*
-    int64_t* maze_rounds;         // per slot: rounds with at least one tile visited
+    const int32_t* list_in;       // tiles of round r (active schedule)
+    const int32_t* count_in;      // their number
+    int32_t* flags_in;            // cleared as the tiles of round r are visited
+    int32_t* list_out;            // tiles scheduled for round r+1
+    int32_t* count_out;           // their number (dense: 1 = some tile changed)
+    int32_t* flags_out;           // 1 = already scheduled for round r+1
+    int32_t* count_clear;         // count of round r+2, zeroed by round r
+    int32_t* sched_out;           // per slot: tiles scheduled for round r+1
+    int32_t* sched_clear;         // per slot: scheduled counts of round r+2, zeroed by round r
+    int32_t* dchg_prev;           // dense, per slot: changed in round r-1 (visit in round r)
+    int32_t* dchg_cur;            // dense, per slot: changed in round r
+    int32_t* dchg_clear;          // dense, per slot: flags of round r+1, zeroed by round r
+    int32_t* maze_last_round;     // per slot: last round with a tile visited
+    uint8_t* touched;             // per tile id: written since its maze's buffers were last cleared
     int64_t* maze_visits;         // per slot: tile visits
     int64_t* maze_cell_visits;    // per slot: interior cells of visited tiles
     unsigned long long* total_cells;  // all slots: interior cells of visited tiles
     int32_t n_slots;
-    int32_t parity;               // activity buffer read this round
+    int32_t round_id;             // r (wraps; only differences are used)
+    int32_t parity;               // activity buffer read in round r (r mod 2)
     int32_t tile_rows;            // interior rows per tile
     int32_t tile_cols;            // interior columns per tile (64*C - 2T)
     int32_t dense;                // 1 = dense schedule
@@ -62,17 +64,17 @@ struct RoundArgs {
 hipError_t launch_pack_mask(const uint8_t* occ, int32_t H, int32_t W, uint32_t* mask,
                             int32_t mpitch, hipStream_t s);
 hipError_t launch_fill(int32_t* p, int64_t n_elems, int32_t value, hipStream_t s);
-// Seed slot's sources (V := K) and schedule their tiles for the round that
-// reads parity a.parity (a.list_in / a.count_in / a.flags_in).
+// Seed slot's sources (V := K) and schedule their tiles into a.list_out /
+// a.count_out / a.flags_out / a.sched_out (the runtime points these at the
+// round about to run).
 hipError_t launch_seed(const RoundArgs& a, int32_t slot, const int32_t* src_rc, int32_t n_src,
                        int32_t* bad_count, hipStream_t s);
-// Schedule every tile of `slot` for the round that reads parity a.parity.
-hipError_t launch_schedule_all(const RoundArgs& a, int32_t slot, int32_t n_tiles, hipStream_t s);
 hipError_t launch_check_sources(const uint32_t* mask, int32_t mpitch, const int32_t* src_rc,
                                 int32_t n_src, int32_t* bad_count, hipStream_t s);
 bool sweep_supported(int T, int C);
 hipError_t launch_sweep(int T, int C, const RoundArgs& a, int32_t grid, hipStream_t s);
-hipError_t launch_finish(const RoundArgs& a, hipStream_t s);
+// Clears slot's counters before its seeds (last round = r-1; dense: marks the
+// maze for a visit in the round about to run through a.dchg_prev).
 hipError_t launch_slot_reset(const RoundArgs& a, int32_t slot, hipStream_t s);
 hipError_t launch_reduce(const MazeDev* mazes, const int32_t* tile_maze, int32_t tile_begin,
                          int32_t tile_end, const int32_t* slot_select, int32_t tile_rows,
@@ -84,10 +86,23 @@ hipError_t launch_scan_offsets(const int32_t* len, int32_t n, int64_t* offsets, 
 hipError_t launch_walk(const MazeDev* mazes, const int32_t* tgt_slot, const int32_t* tgt_rc,
                        int32_t n_tgt, int32_t parity, const int32_t* len, const int64_t* offsets,
                        int32_t* cells, hipStream_t s);
+hipError_t launch_walk_random(const MazeDev* mazes, const int32_t* tgt_slot, const int32_t* tgt_rc,
+                              const int32_t* tgt_local, int32_t n_tgt, int32_t parity, uint64_t seed,
+                              const int32_t* len, const int64_t* offsets, int32_t* cells, hipStream_t s);
+hipError_t launch_walk_euclid(bool write, const MazeDev* mazes, const int32_t* tgt_slot,
+                              const int32_t* tgt_rc, int32_t n_tgt, int32_t parity, int32_t* len,
+                              const int64_t* offsets, int32_t* cells, hipStream_t s);
+hipError_t launch_source_index(const MazeDev* mazes, const int32_t* tgt_slot, int32_t n_tgt,
+                               const int32_t* len, const int64_t* offsets, const int32_t* cells,
+                               const int32_t* src_sorted, const int32_t* src_base, const int32_t* src_n,
+                               int32_t* out, hipStream_t s);
 hipError_t launch_activity(const MazeDev* mazes, int32_t slot, int32_t H, int32_t W,
                            int32_t parity, int32_t offset, int32_t* dst, int64_t dpitch,
                            hipStream_t s);
 hipError_t launch_selftest(int32_t* out, hipStream_t s);
+// Zeroes both activity buffers over the interiors of slot's touched tiles and
+// clears their touched flags.
+hipError_t launch_clear_touched(const RoundArgs& a, int32_t slot, int32_t n_tiles, hipStream_t s);
 int sweep_max_waves_per_cu(int T, int C);
 
 }  // namespace omap

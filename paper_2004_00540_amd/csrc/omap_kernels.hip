@@ -99,18 +99,14 @@ __device__ __forceinline__ int64_t tile_cells(const MazeDev& md, int ty, int tx,
     return (int64_t)min(tile_rows, md.H - ty * tile_rows) * min(tile_cols, md.W - tx * tile_cols);
 }
 
-// Append tile (ty, tx) of `slot` to the list of the round that reads
-// a.list_out (the round about to run) and count it as visited in that round.
-__device__ __forceinline__ void seed_tile(const RoundArgs& a, const MazeDev& md, int slot, int ty,
-                                          int tx) {
+// Append tile (ty, tx) of `slot` to a.list_out unless it is already there
+// (flag exchange) and count it in the slot's scheduled tiles.
+__device__ __forceinline__ void schedule_tile(const RoundArgs& a, const MazeDev& md, int slot, int ty,
+                                              int tx) {
     const int g = md.tile_base + ty * md.tiles_x + tx;
     if (atomicExch(&a.flags_out[g], 1) == 0) {
         a.list_out[atomicAdd(a.count_out, 1)] = g;
-        const unsigned long long cells = (unsigned long long)tile_cells(md, ty, tx, a.tile_rows, a.tile_cols);
-        atomicAdd(reinterpret_cast<unsigned long long*>(&a.maze_visits[slot]), 1ull);
-        atomicAdd(reinterpret_cast<unsigned long long*>(&a.maze_cell_visits[slot]), cells);
-        atomicAdd(a.total_cells, cells);
-        a.maze_rounds[slot] = 1;
+        atomicAdd(&a.sched_out[slot], 1);
     }
 }
 
@@ -135,26 +131,8 @@ __global__ void k_seed(RoundArgs a, int32_t slot, const int32_t* __restrict__ sr
     for (int dy = -1; dy <= 1; ++dy)
         for (int dx = -1; dx <= 1; ++dx) {
             const int ny = ty + dy, nx = tx + dx;
-            if (ny >= 0 && ny < md.tiles_y && nx >= 0 && nx < md.tiles_x) seed_tile(a, md, slot, ny, nx);
+            if (ny >= 0 && ny < md.tiles_y && nx >= 0 && nx < md.tiles_x) schedule_tile(a, md, slot, ny, nx);
         }
-}
-
-// Append every tile of `slot` to a.list_out (dense schedule, first round).
-__global__ void k_schedule_all(RoundArgs a, int32_t slot, int32_t n_tiles) {
-    __shared__ int base;
-    const MazeDev md = a.mazes[slot];
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    const int cnt = min((int)blockDim.x, n_tiles - (int)(blockIdx.x * blockDim.x));
-    if (threadIdx.x == 0) base = atomicAdd(a.count_out, cnt);
-    __syncthreads();
-    if (t < n_tiles) a.list_out[base + threadIdx.x] = md.tile_base + t;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        const unsigned long long cells = (unsigned long long)md.H * md.W;
-        a.maze_rounds[slot] = 1;
-        a.maze_visits[slot] += n_tiles;
-        a.maze_cell_visits[slot] += (int64_t)cells;
-        atomicAdd(a.total_cells, cells);
-    }
 }
 
 // ---------------------------------------------------------------------------
@@ -287,8 +265,8 @@ __device__ bool sweep_tile(const MazeDev& md, int ty, int tx, int tile_rows, int
     const int col = tx * TW - T + C * lane;
     const bool col_ok = col >= 0 && col < md.pitch;
     const bool inner = lane >= HALO_LANES && lane < kLanes - HALO_LANES && col < md.W;
-    const int32_t* __restrict__ Vin = md.V[parity];
-    int32_t* __restrict__ Vout = md.V[parity ^ 1];
+    const int32_t* __restrict__ Vin = parity ? md.V[1] : md.V[0];
+    int32_t* __restrict__ Vout = parity ? md.V[0] : md.V[1];
 
     uint32_t st[T][3][C];
 #pragma unroll
@@ -314,91 +292,64 @@ __device__ bool sweep_tile(const MazeDev& md, int ty, int tx, int tile_rows, int
     return __ballot(sum_in != sum_out) != 0;
 }
 
-// Append tile (ty, tx) of `slot` to the next round's list unless it is already
-// there.
-__device__ __forceinline__ void schedule_tile(const RoundArgs& a, const MazeDev& md, int slot,
-                                              int ty, int tx) {
-    const int g = md.tile_base + ty * md.tiles_x + tx;
-    if (atomicExch(&a.flags_out[g], 1) == 0) {
-        a.list_out[atomicAdd(a.count_out, 1)] = g;
-        atomicAdd(&a.maze_sched[slot], 1);
-        atomicAdd(&a.maze_sched_cells[slot],
-                  (unsigned long long)tile_cells(md, ty, tx, a.tile_rows, a.tile_cols));
-    }
-}
-
-// End of a round (one block, after the sweep): the dense schedule's
-// next-round list, per-maze counters and convergence, and the reset of this
-// round's input count.
-__global__ __launch_bounds__(kBlockThreads) void k_finish(RoundArgs a) {
-    __shared__ int s_base[kBlockThreads], s_n[kBlockThreads], s_tb[kBlockThreads];
-    if (a.dense) {
-        for (int m0 = 0; m0 < a.n_slots; m0 += blockDim.x) {
-            const int m = m0 + threadIdx.x;
-            int base = -1, nt = 0, tb = 0;
-            if (m < a.n_slots && a.maze_state[m] == kMazeRunning && atomicExch(&a.maze_changed[m], 0)) {
-                const MazeDev md = a.mazes[m];
-                nt = md.tiles_x * md.tiles_y;
-                tb = md.tile_base;
-                base = atomicAdd(a.count_out, nt);
-                atomicAdd(&a.maze_sched[m], nt);
-                atomicAdd(&a.maze_sched_cells[m], (unsigned long long)md.H * md.W);
-            }
-            s_base[threadIdx.x] = base;
-            s_n[threadIdx.x] = nt;
-            s_tb[threadIdx.x] = tb;
-            __syncthreads();
-            for (int k = 0; k < (int)blockDim.x; ++k) {
-                if (s_base[k] < 0) continue;
-                for (int t = threadIdx.x; t < s_n[k]; t += blockDim.x) a.list_out[s_base[k] + t] = s_tb[k] + t;
-            }
-            __syncthreads();
-        }
-    }
-    for (int m = threadIdx.x; m < a.n_slots; m += blockDim.x) {
-        const int sched = atomicExch(&a.maze_sched[m], 0);
-        const unsigned long long cells = atomicExch(&a.maze_sched_cells[m], 0ull);
-        if (a.maze_state[m] == kMazeRunning) {
-            if (sched > 0) {
-                a.maze_rounds[m] += 1;
-                a.maze_visits[m] += sched;
-                a.maze_cell_visits[m] += (int64_t)cells;
-                atomicAdd(a.total_cells, cells);
-            } else {
-                a.maze_state[m] = kMazeDone;
-            }
-        }
-    }
-    if (threadIdx.x == 0) *a.count_in = 0;
-}
-
-// Marks `slot` running and clears its counters (before its seeds).
+// Marks `slot` for its first round: counters cleared, last round = r - 1; in
+// the dense schedule the maze is flagged as changed so round r visits it.
 __global__ void k_slot_reset(RoundArgs a, int32_t slot) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    a.maze_state[slot] = kMazeRunning;
-    a.maze_rounds[slot] = 0;
+    a.maze_last_round[slot] = a.round_id - 1;
     a.maze_visits[slot] = 0;
     a.maze_cell_visits[slot] = 0;
-    a.maze_changed[slot] = 0;
+    if (a.dense) a.dchg_prev[slot] = 1;
 }
 
+// Round r: every scheduled tile gets T layers.  Active schedule: the tiles of
+// a.list_in; a changed tile schedules itself and its 8 neighbour tiles for
+// round r+1.  Dense schedule: every tile of each maze that changed in round
+// r-1; a changed tile flags its maze for round r+1.  Block 0 also clears the
+// buffers round r+1 will fill.
 template <int T, int C>
 __global__ __launch_bounds__(kBlockThreads) void k_sweep(RoundArgs a) {
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = lane_id();
-    const int n = __builtin_amdgcn_readfirstlane(*a.count_in);
+    if (blockIdx.x == 0) {
+        if (threadIdx.x == 0) *a.count_clear = 0;
+        for (int m = threadIdx.x; m < a.n_slots; m += blockDim.x) {
+            a.sched_clear[m] = 0;
+            a.dchg_clear[m] = 0;
+        }
+    }
+    const int n = a.dense ? a.n_tile_ids : __builtin_amdgcn_readfirstlane(*a.count_in);
     const int stride = gridDim.x * kWavesPerBlock;
     for (int i = blockIdx.x * kWavesPerBlock + wave; i < n; i += stride) {
-        const int g = a.list_in[i];
-        if (lane == 0) a.flags_in[g] = 0;
-        const int slot = a.tile_maze[g];
+        int g, slot;
+        if (a.dense) {
+            g = i;
+            slot = a.tile_maze[g];
+            if (slot < 0 || a.dchg_prev[slot] == 0) continue;
+        } else {
+            g = a.list_in[i];
+            if (lane == 0) a.flags_in[g] = 0;
+            slot = a.tile_maze[g];
+        }
         const MazeDev md = a.mazes[slot];
         const int lt = g - md.tile_base;
         const int ty = lt / md.tiles_x;
         const int tx = lt - ty * md.tiles_x;
+        if (lane == 0) {
+            const unsigned long long cells =
+                (unsigned long long)tile_cells(md, ty, tx, a.tile_rows, a.tile_cols);
+            atomicAdd(reinterpret_cast<unsigned long long*>(&a.maze_visits[slot]), 1ull);
+            atomicAdd(reinterpret_cast<unsigned long long*>(&a.maze_cell_visits[slot]), cells);
+            atomicAdd(a.total_cells, cells);
+            if (a.maze_last_round[slot] != a.round_id) a.maze_last_round[slot] = a.round_id;
+            a.touched[g] = 1;
+        }
         if (sweep_tile<T, C>(md, ty, tx, a.tile_rows, a.parity)) {
             if (a.dense) {
-                if (lane == 0) a.maze_changed[slot] = 1;
+                if (lane == 0) {
+                    a.dchg_cur[slot] = 1;
+                    *a.count_out = 1;
+                }
             } else if (lane < 9) {
                 const int ny = ty + lane / 3 - 1, nx = tx + lane % 3 - 1;
                 if (ny >= 0 && ny < md.tiles_y && nx >= 0 && nx < md.tiles_x)
@@ -406,6 +357,27 @@ __global__ __launch_bounds__(kBlockThreads) void k_sweep(RoundArgs a) {
             }
         }
     }
+}
+
+// One wave per tile of `slot`: zero the interior of touched tiles in both
+// activity buffers (everything else is still 0 from the last full clear).
+__global__ __launch_bounds__(kBlockThreads) void k_clear_touched(RoundArgs a, int32_t slot,
+                                                                 int32_t n_tiles) {
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int t = blockIdx.x * kWavesPerBlock + wave;
+    if (t >= n_tiles) return;
+    const MazeDev md = a.mazes[slot];
+    const int g = md.tile_base + t;
+    if (!a.touched[g]) return;
+    const int ty = t / md.tiles_x, tx = t - ty * md.tiles_x;
+    const int r0 = ty * a.tile_rows, c0 = tx * a.tile_cols;
+    const int rows = min(a.tile_rows, md.H - r0), cols = min(a.tile_cols, md.W - c0);
+    for (int k = lane_id(); k < rows * cols; k += kLanes) {
+        const int64_t x = (int64_t)(r0 + k / cols) * md.pitch + c0 + k % cols;
+        md.V[0][x] = 0;
+        md.V[1][x] = 0;
+    }
+    if (lane_id() == 0) a.touched[g] = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -426,7 +398,7 @@ __global__ __launch_bounds__(256) void k_reduce(const MazeDev* __restrict__ maze
     const int ty = lt / md.tiles_x, tx = lt - ty * md.tiles_x;
     const int r0 = ty * tile_rows, c0 = tx * tile_cols;
     const int rows = min(tile_rows, md.H - r0), cols = min(tile_cols, md.W - c0);
-    const int32_t* V = md.V[parity];
+    const int32_t* V = parity ? md.V[1] : md.V[0];
     int vmin = 0x7fffffff;
     int cnt = 0;
     for (int k = threadIdx.x; k < rows * cols; k += blockDim.x) {
@@ -472,7 +444,7 @@ __global__ void k_path_lengths(const MazeDev* __restrict__ mazes, const int32_t*
     if (i >= n) return;
     const MazeDev md = mazes[tslot[i]];
     const int32_t r = trc[2 * i], c = trc[2 * i + 1];
-    const int v = md.V[parity][(int64_t)r * md.pitch + c];
+    const int v = (parity ? md.V[1] : md.V[0])[(int64_t)r * md.pitch + c];
     len[i] = v > 0 ? md.K - v : -1;
 }
 
@@ -500,6 +472,54 @@ __global__ __launch_bounds__(1024) void k_scan(const int32_t* __restrict__ len, 
     }
 }
 
+// The walk is bound by dependent-load latency, so each lane loads the 7x7
+// window around its current cell once and resolves up to three steps from
+// registers: after each step the window is re-centred (5x5, then 3x3) by
+// selects, with no dynamic register indexing.  Window cells outside the grid
+// read as -1, below every in-grid value.
+constexpr int kWalkSteps = 3;
+constexpr int kWalkWin = 2 * kWalkSteps + 1;
+
+// Index (0..7, fixed order) of the first maximal 8-neighbour of the window centre.
+template <int N>
+__device__ __forceinline__ int first_max_neighbour(const int (&w)[N][N]) {
+    constexpr int m = N / 2;
+    const int nv[8] = {w[m - 1][m - 1], w[m - 1][m], w[m - 1][m + 1], w[m][m - 1],
+                       w[m][m + 1],     w[m + 1][m - 1], w[m + 1][m], w[m + 1][m + 1]};
+    int best = 0, bv = nv[0];
+#pragma unroll
+    for (int k = 1; k < 8; ++k)
+        if (nv[k] > bv) {
+            bv = nv[k];
+            best = k;
+        }
+    return best;
+}
+
+__device__ __forceinline__ int dir_dr(int k) { return k < 3 ? -1 : (k < 5 ? 0 : 1); }
+__device__ __forceinline__ int dir_dc(int k) {
+    return (k == 0 || k == 3 || k == 5) ? -1 : ((k == 1 || k == 6) ? 0 : 1);
+}
+
+// Window of size N-2 centred on the neighbour (dr, dc) of the centre of w.
+// The choice between the three candidate cells is a mask blend rather than a
+// conditional expression, which keeps the windows in registers (a select
+// between two array elements would become a load from a selected address).
+template <int N>
+__device__ __forceinline__ void recentre(const int (&w)[N][N], int dr, int dc, int (&o)[N - 2][N - 2]) {
+    const int rm = -(int)(dr < 0), r0 = -(int)(dr == 0), rp = -(int)(dr > 0);
+    const int cm = -(int)(dc < 0), c0 = -(int)(dc == 0), cp = -(int)(dc > 0);
+    int t[N - 2][N];
+#pragma unroll
+    for (int i = 0; i < N - 2; ++i)
+#pragma unroll
+        for (int j = 0; j < N; ++j) t[i][j] = (w[i][j] & rm) | (w[i + 1][j] & r0) | (w[i + 2][j] & rp);
+#pragma unroll
+    for (int i = 0; i < N - 2; ++i)
+#pragma unroll
+        for (int j = 0; j < N - 2; ++j) o[i][j] = (t[i][j] & cm) | (t[i][j + 1] & c0) | (t[i][j + 2] & cp);
+}
+
 __global__ void k_walk(const MazeDev* __restrict__ mazes, const int32_t* __restrict__ tslot,
                        const int32_t* __restrict__ trc, int32_t n, int32_t parity,
                        const int32_t* __restrict__ len, const int64_t* __restrict__ off,
@@ -509,36 +529,215 @@ __global__ void k_walk(const MazeDev* __restrict__ mazes, const int32_t* __restr
     const int steps = len[i];
     if (steps < 0) return;
     const MazeDev md = mazes[tslot[i]];
-    const int32_t* __restrict__ V = md.V[parity];
+    const int32_t* __restrict__ V = parity ? md.V[1] : md.V[0];
     int r = trc[2 * i], c = trc[2 * i + 1];
     int64_t o = off[i];
     cells[o++] = r * md.W + c;
-    for (int s = 0; s < steps; ++s) {
-        // the 8 neighbours in the fixed order; first maximum wins
-        const bool up = r > 0, dn = r + 1 < md.H, lf = c > 0, rt = c + 1 < md.W;
-        const int32_t* row_u = V + (int64_t)(r - 1) * md.pitch;
-        const int32_t* row_m = V + (int64_t)r * md.pitch;
-        const int32_t* row_d = V + (int64_t)(r + 1) * md.pitch;
-        int nv[8];
-        nv[0] = (up && lf) ? row_u[c - 1] : -1;
-        nv[1] = up ? row_u[c] : -1;
-        nv[2] = (up && rt) ? row_u[c + 1] : -1;
-        nv[3] = lf ? row_m[c - 1] : -1;
-        nv[4] = rt ? row_m[c + 1] : -1;
-        nv[5] = (dn && lf) ? row_d[c - 1] : -1;
-        nv[6] = dn ? row_d[c] : -1;
-        nv[7] = (dn && rt) ? row_d[c + 1] : -1;
-        int best = 0, bv = nv[0];
+    int s = 0;
+    while (s < steps) {
+        int w7[kWalkWin][kWalkWin];
 #pragma unroll
-        for (int k = 1; k < 8; ++k)
-            if (nv[k] > bv) {
-                bv = nv[k];
-                best = k;
+        for (int a = 0; a < kWalkWin; ++a) {
+            const int rr = r - kWalkSteps + a;
+            const int rc = min(max(rr, 0), md.H - 1);
+            const int32_t* row = V + (int64_t)rc * md.pitch;
+#pragma unroll
+            for (int b = 0; b < kWalkWin; ++b) {
+                const int cc = c - kWalkSteps + b;
+                const int v = row[min(max(cc, 0), md.W - 1)];
+                w7[a][b] = (rr >= 0 && rr < md.H && cc >= 0 && cc < md.W) ? v : -1;
             }
-        r += (best < 3) ? -1 : (best < 5 ? 0 : 1);
-        c += (best == 0 || best == 3 || best == 5) ? -1 : ((best == 1 || best == 6) ? 0 : 1);
+        }
+        int k = first_max_neighbour<7>(w7);
+        int dr = dir_dr(k), dc = dir_dc(k);
+        r += dr;
+        c += dc;
+        cells[o++] = r * md.W + c;
+        if (++s >= steps) break;
+        int w5[5][5];
+        recentre<7>(w7, dr, dc, w5);
+        k = first_max_neighbour<5>(w5);
+        dr = dir_dr(k);
+        dc = dir_dc(k);
+        r += dr;
+        c += dc;
+        cells[o++] = r * md.W + c;
+        if (++s >= steps) break;
+        int w3[3][3];
+        recentre<5>(w5, dr, dc, w3);
+        k = first_max_neighbour<3>(w3);
+        r += dir_dr(k);
+        c += dir_dc(k);
+        cells[o++] = r * md.W + c;
+        ++s;
+    }
+}
+
+// ---- random ties and Euclidean reconstruction ------------------------------
+
+// SplitMix64 output function on seed ^ (target << 32) ^ step: the counter-based
+// random number of the random tie-break (Steele, Lea, Flood 2014).
+__device__ __forceinline__ uint64_t tie_hash(uint64_t seed, uint64_t target, uint64_t step) {
+    uint64_t z = seed ^ (target << 32) ^ step;
+    z += 0x9e3779b97f4a7c15ull;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ int read_or(const int32_t* V, const MazeDev& md, int r, int c, int outside) {
+    return (r >= 0 && r < md.H && c >= 0 && c < md.W) ? V[(int64_t)r * md.pitch + c] : outside;
+}
+
+// Simple reconstruction with random ties: at move s of target t (t = index in
+// its maze's target list) the maximal 8-neighbours are counted in the fixed
+// order and the one at position tie_hash(seed, t, s) mod count is taken.
+__global__ void k_walk_random(const MazeDev* __restrict__ mazes, const int32_t* __restrict__ tslot,
+                              const int32_t* __restrict__ trc, const int32_t* __restrict__ tlocal,
+                              int32_t n, int32_t parity, uint64_t seed, const int32_t* __restrict__ len,
+                              const int64_t* __restrict__ off, int32_t* __restrict__ cells) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int steps = len[i];
+    if (steps < 0) return;
+    const MazeDev md = mazes[tslot[i]];
+    const int32_t* __restrict__ V = parity ? md.V[1] : md.V[0];
+    int r = trc[2 * i], c = trc[2 * i + 1];
+    int64_t o = off[i];
+    cells[o++] = r * md.W + c;
+    const uint64_t t = (uint64_t)tlocal[i];
+    for (int s = 0; s < steps; ++s) {
+        int nv[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) nv[k] = read_or(V, md, r + dir_dr(k), c + dir_dc(k), -1);
+        int bv = nv[0];
+#pragma unroll
+        for (int k = 1; k < 8; ++k) bv = max(bv, nv[k]);
+        int cnt = 0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) cnt += nv[k] == bv;
+        int j = (int)(tie_hash(seed, t, (uint64_t)s) % (uint64_t)cnt);
+        int pick = 0;
+#pragma unroll
+        for (int k = 7; k >= 0; --k)
+            if (nv[k] == bv) {      // walk maxima from the last: ends on the j-th in order
+                if (--cnt == j) pick = k;
+            }
+        r += dir_dr(pick);
+        c += dir_dc(pick);
         cells[o++] = r * md.W + c;
     }
+}
+
+// Euclidean reconstruction (Eq. 1 and straightening).  The walk climbs through
+// 4-neighbours (first maximum in the order up, left, right, down), allows one
+// sideways move to an equal 4-neighbour per activity level, and otherwise
+// takes the first maximal 8-neighbour; the straightening pass (drop a point
+// whose predecessor and successor are diagonal neighbours) runs on the fly.
+// WRITE = false counts the final points (len = points - 1, -1 if no path);
+// WRITE = true writes them at off[i].
+template <bool WRITE>
+__global__ void k_walk_euclid(const MazeDev* __restrict__ mazes, const int32_t* __restrict__ tslot,
+                              const int32_t* __restrict__ trc, int32_t n, int32_t parity,
+                              int32_t* __restrict__ len, const int64_t* __restrict__ off,
+                              int32_t* __restrict__ cells) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const MazeDev md = mazes[tslot[i]];
+    const int32_t* __restrict__ V = parity ? md.V[1] : md.V[0];
+    int r = trc[2 * i], c = trc[2 * i + 1];
+    int v = V[(int64_t)r * md.pitch + c];
+    if (v <= 0) {
+        if (!WRITE) len[i] = -1;
+        return;
+    }
+    if (WRITE && len[i] < 0) return;
+    int64_t o = WRITE ? off[i] : 0;
+    int32_t count = 1;
+    if (WRITE) cells[o++] = r * md.W + c;
+    int kr = r, kc = c;            // last kept point
+    int pr = -1, pc = -1;          // pending point (not yet decided)
+    bool sideways_before = false;
+    while (v != md.K) {
+        // 4-neighbours: up, left, right, down
+        const int u = read_or(V, md, r - 1, c, -1), l = read_or(V, md, r, c - 1, -1);
+        const int rt = read_or(V, md, r, c + 1, -1), dn = read_or(V, md, r + 1, c, -1);
+        int b4 = u, dr = -1, dc = 0;
+        if (l > b4) { b4 = l; dr = 0; dc = -1; }
+        if (rt > b4) { b4 = rt; dr = 0; dc = 1; }
+        if (dn > b4) { b4 = dn; dr = 1; dc = 0; }
+        if (b4 > v) {
+            sideways_before = false;
+        } else if (b4 == v && !sideways_before) {
+            sideways_before = true;
+        } else {
+            int nv[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) nv[k] = read_or(V, md, r + dir_dr(k), c + dir_dc(k), -1);
+            int best = 0, bv = nv[0];
+#pragma unroll
+            for (int k = 1; k < 8; ++k)
+                if (nv[k] > bv) {
+                    bv = nv[k];
+                    best = k;
+                }
+            b4 = bv;
+            dr = dir_dr(best);
+            dc = dir_dc(best);
+            sideways_before = false;
+        }
+        r += dr;
+        c += dc;
+        v = b4;
+        // straightening: the pending point is dropped when the last kept point
+        // and the new point are diagonal neighbours
+        if (pr >= 0) {
+            const int ar = kr > r ? kr - r : r - kr, ac = kc > c ? kc - c : c - kc;
+            if (!(ar == 1 && ac == 1)) {
+                if (WRITE) cells[o++] = pr * md.W + pc;
+                ++count;
+                kr = pr;
+                kc = pc;
+            }
+        }
+        pr = r;
+        pc = c;
+    }
+    if (pr >= 0) {
+        if (WRITE) cells[o++] = pr * md.W + pc;
+        ++count;
+    }
+    if (!WRITE) len[i] = count - 1;
+}
+
+// Index (in its maze's source list) of the source each path ends on; -1 if no
+// path.  src_sorted holds per-maze (linear cell, first list index) pairs sorted
+// by cell, src_base[t] / src_n[t] the target's maze's range.
+__global__ void k_source_index(const MazeDev* __restrict__ mazes, const int32_t* __restrict__ tslot,
+                               int32_t n, const int32_t* __restrict__ len,
+                               const int64_t* __restrict__ off, const int32_t* __restrict__ cells,
+                               const int32_t* __restrict__ src_sorted,
+                               const int32_t* __restrict__ src_base,
+                               const int32_t* __restrict__ src_n, int32_t* __restrict__ out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (len[i] < 0) {
+        out[i] = -1;
+        return;
+    }
+    const int32_t end = cells[off[i + 1] - 1];
+    const int32_t* p = src_sorted + 2 * (int64_t)src_base[i];
+    int lo = 0, hi = src_n[i] - 1, found = -1;
+    while (lo <= hi) {
+        const int mid = (lo + hi) >> 1;
+        const int32_t key = p[2 * mid];
+        if (key == end) {
+            found = p[2 * mid + 1];
+            break;
+        }
+        if (key < end) lo = mid + 1; else hi = mid - 1;
+    }
+    out[i] = found;
 }
 
 // O = V - offset where V > 0, else 0 (offset = K - L - 1 maps the encoding back
@@ -551,7 +750,7 @@ __global__ void k_activity(const MazeDev* __restrict__ mazes, int32_t slot, int3
     const int32_t r = (int32_t)(b / col_blocks);
     const int32_t c = (int32_t)(b - (int64_t)r * col_blocks) * blockDim.x + threadIdx.x;
     if (r >= md.H || c >= md.W) return;
-    const int v = md.V[parity][(int64_t)r * md.pitch + c];
+    const int v = (parity ? md.V[1] : md.V[0])[(int64_t)r * md.pitch + c];
     dst[(int64_t)r * dpitch + c] = v > 0 ? v - offset : 0;
 }
 
@@ -608,18 +807,8 @@ hipError_t launch_seed(const RoundArgs& a, int32_t slot, const int32_t* src_rc, 
     return hipGetLastError();
 }
 
-hipError_t launch_schedule_all(const RoundArgs& a, int32_t slot, int32_t n_tiles, hipStream_t s) {
-    hipLaunchKernelGGL(k_schedule_all, dim3(grid_for(n_tiles, 256)), dim3(256), 0, s, a, slot, n_tiles);
-    return hipGetLastError();
-}
-
 hipError_t launch_slot_reset(const RoundArgs& a, int32_t slot, hipStream_t s) {
     hipLaunchKernelGGL(k_slot_reset, dim3(1), dim3(64), 0, s, a, slot);
-    return hipGetLastError();
-}
-
-hipError_t launch_finish(const RoundArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL(k_finish, dim3(1), dim3(kBlockThreads), 0, s, a);
     return hipGetLastError();
 }
 
@@ -678,6 +867,38 @@ hipError_t launch_walk(const MazeDev* mazes, const int32_t* tgt_slot, const int3
     return hipGetLastError();
 }
 
+hipError_t launch_walk_random(const MazeDev* mazes, const int32_t* tgt_slot, const int32_t* tgt_rc,
+                              const int32_t* tgt_local, int32_t n_tgt, int32_t parity, uint64_t seed,
+                              const int32_t* len, const int64_t* offsets, int32_t* cells, hipStream_t s) {
+    if (n_tgt <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_walk_random, dim3(grid_for(n_tgt, 64)), dim3(64), 0, s, mazes, tgt_slot, tgt_rc,
+                       tgt_local, n_tgt, parity, seed, len, offsets, cells);
+    return hipGetLastError();
+}
+
+hipError_t launch_walk_euclid(bool write, const MazeDev* mazes, const int32_t* tgt_slot,
+                              const int32_t* tgt_rc, int32_t n_tgt, int32_t parity, int32_t* len,
+                              const int64_t* offsets, int32_t* cells, hipStream_t s) {
+    if (n_tgt <= 0) return hipSuccess;
+    if (write)
+        hipLaunchKernelGGL(k_walk_euclid<true>, dim3(grid_for(n_tgt, 64)), dim3(64), 0, s, mazes, tgt_slot,
+                           tgt_rc, n_tgt, parity, len, offsets, cells);
+    else
+        hipLaunchKernelGGL(k_walk_euclid<false>, dim3(grid_for(n_tgt, 64)), dim3(64), 0, s, mazes, tgt_slot,
+                           tgt_rc, n_tgt, parity, len, offsets, cells);
+    return hipGetLastError();
+}
+
+hipError_t launch_source_index(const MazeDev* mazes, const int32_t* tgt_slot, int32_t n_tgt,
+                               const int32_t* len, const int64_t* offsets, const int32_t* cells,
+                               const int32_t* src_sorted, const int32_t* src_base, const int32_t* src_n,
+                               int32_t* out, hipStream_t s) {
+    if (n_tgt <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_source_index, dim3(grid_for(n_tgt, 256)), dim3(256), 0, s, mazes, tgt_slot, n_tgt,
+                       len, offsets, cells, src_sorted, src_base, src_n, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_activity(const MazeDev* mazes, int32_t slot, int32_t H, int32_t W,
                            int32_t parity, int32_t offset, int32_t* dst, int64_t dpitch,
                            hipStream_t s) {
@@ -685,6 +906,13 @@ hipError_t launch_activity(const MazeDev* mazes, int32_t slot, int32_t H, int32_
     const int64_t blocks = (int64_t)H * col_blocks;
     hipLaunchKernelGGL(k_activity, dim3((uint32_t)blocks), dim3(256), 0, s, mazes, slot, parity,
                        offset, dst, dpitch, col_blocks);
+    return hipGetLastError();
+}
+
+hipError_t launch_clear_touched(const RoundArgs& a, int32_t slot, int32_t n_tiles, hipStream_t s) {
+    if (n_tiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_clear_touched, dim3((n_tiles + kWavesPerBlock - 1) / kWavesPerBlock),
+                       dim3(kBlockThreads), 0, s, a, slot, n_tiles);
     return hipGetLastError();
 }
 

@@ -70,8 +70,16 @@ struct Options {
     int check = 0;       // 0 = adaptive
 };
 
+// Defaults (measured on MI355X): the active schedule is latency-bound (few
+// tiles per round), so narrow strips (2 columns per lane) and short tiles keep
+// each tile visit short; the dense schedule is throughput-bound, so wide
+// strips (4 columns per lane) and tall tiles minimise halo work.
 static omap_status_t resolve_options(const omap_options* o, Options* out) {
     Options r;
+    const bool dense = o && o->schedule == OMAP_SCHEDULE_DENSE;
+    r.C = dense ? 4 : 2;
+    r.T = 16;
+    int th = 0;
     if (o) {
         if (o->lane_columns != 0) {
             if (o->lane_columns != 2 && o->lane_columns != 4)
@@ -79,24 +87,23 @@ static omap_status_t resolve_options(const omap_options* o, Options* out) {
             r.C = o->lane_columns;
         }
         if (o->temporal_depth != 0) r.T = o->temporal_depth;
-        if (!sweep_supported(r.T, r.C))
-            return fail(OMAP_ERR_INVALID_ARG,
-                        "temporal_depth %d is not available with %d columns per lane "
-                        "(4, 8, 12, 16; with 2 columns also 24, 32)", r.T, r.C);
         if (o->tile_rows != 0) {
             if (o->tile_rows < 2 || o->tile_rows > 4096 || (o->tile_rows & 1))
                 return fail(OMAP_ERR_INVALID_ARG, "tile_rows must be even in [2, 4096] (got %d)",
                             o->tile_rows);
-            r.TH = o->tile_rows;
-        } else {
-            r.TH = std::max(16, r.T);
+            th = o->tile_rows;
         }
         if (o->schedule != OMAP_SCHEDULE_ACTIVE && o->schedule != OMAP_SCHEDULE_DENSE)
             return fail(OMAP_ERR_INVALID_ARG, "schedule must be ACTIVE or DENSE (got %d)", o->schedule);
-        r.dense = o->schedule == OMAP_SCHEDULE_DENSE;
+        r.dense = dense;
         if (o->check_interval < 0) return fail(OMAP_ERR_INVALID_ARG, "check_interval < 0");
         r.check = o->check_interval;
     }
+    if (!sweep_supported(r.T, r.C))
+        return fail(OMAP_ERR_INVALID_ARG,
+                    "temporal_depth %d is not available with %d columns per lane "
+                    "(4, 8, 12, 16; with 2 columns also 24, 32)", r.T, r.C);
+    r.TH = th ? th : (dense ? 256 : std::max(16, r.T));
     if (r.TH < r.T)
         return fail(OMAP_ERR_INVALID_ARG, "tile_rows (%d) must be >= temporal_depth (%d)", r.TH, r.T);
     r.TW = 64 * r.C - 2 * r.T;
@@ -260,8 +267,10 @@ struct Slot {
     int32_t K = 0;
     int64_t L_req = 0;
     int64_t layers = -1;        // L or L* once finalized
+    int64_t first_round = 0;    // round index of the maze's first visit
     int64_t reached = 0;
     bool started = false, finalized = false;
+    bool cleared = false;       // both activity buffers are all zero outside touched tiles
 };
 
 class Solver {
@@ -277,11 +286,13 @@ class Solver {
     MazeDev* d_mazes = nullptr;
     int32_t* d_tile_maze = nullptr;
     int32_t* d_list[2] = {nullptr, nullptr};
-    int32_t* d_count = nullptr;               // [2]
+    int32_t* d_count = nullptr;               // [3] list counts by round mod 3
     int32_t* d_flags[2] = {nullptr, nullptr};
-    int32_t *d_changed = nullptr, *d_sched = nullptr, *d_state = nullptr;
-    unsigned long long* d_sched_cells = nullptr;
-    int64_t *d_rounds = nullptr, *d_visits = nullptr, *d_cell_visits = nullptr;
+    int32_t* d_sched = nullptr;               // [3][cap_slots] scheduled tiles by round mod 3
+    int32_t* d_dchg = nullptr;                // [3][cap_slots] dense: changed, by round mod 3
+    int32_t* d_last_round = nullptr;          // per slot
+    uint8_t* d_touched = nullptr;             // per tile id
+    int64_t *d_visits = nullptr, *d_cell_visits = nullptr;
     unsigned long long* d_total_cells = nullptr;
     int32_t* d_bad_slot = nullptr;            // per slot: sources found on obstacles
     int32_t* h_bad = nullptr;                 // pinned mirror of d_bad_slot
@@ -295,7 +306,8 @@ class Solver {
     void* d_scratch = nullptr;                // grow-only path scratch
     size_t scratch_bytes = 0;
 
-    int parity = 0;
+    int64_t next_round = 0;                   // index of the next round to run
+    int parity = 0;                           // next_round mod 2: activity buffer holding the latest values
     int grid = 0;
     std::vector<void*> owned;                 // solver-level device allocations
 
@@ -351,18 +363,17 @@ class Solver {
         OK_TRY(dalloc(&d_tile_maze, cap_tiles));
         OK_TRY(dalloc(&d_list[0], cap_tiles));
         OK_TRY(dalloc(&d_list[1], cap_tiles));
-        OK_TRY(dalloc(&d_count, 2));
+        OK_TRY(dalloc(&d_count, 3));
         OK_TRY(dalloc(&d_flags[0], cap_tiles));
         OK_TRY(dalloc(&d_flags[1], cap_tiles));
-        OK_TRY(dalloc(&d_changed, cap_slots));
-        OK_TRY(dalloc(&d_sched, cap_slots));
-        OK_TRY(dalloc(&d_state, cap_slots));
-        OK_TRY(dalloc(&d_sched_cells, cap_slots));
+        OK_TRY(dalloc(&d_sched, 3 * (size_t)cap_slots));
+        OK_TRY(dalloc(&d_dchg, 3 * (size_t)cap_slots));
+        OK_TRY(dalloc(&d_last_round, cap_slots));
+        OK_TRY(dalloc(&d_touched, cap_tiles));
         OK_TRY(dalloc(&d_bad_slot, cap_slots));
         HIP_TRY(hipHostMalloc((void**)&h_bad, sizeof(int32_t) * cap_slots, hipHostMallocDefault));
         h_mazes.assign(cap_slots, MazeDev());
         h_tile_maze.assign(cap_tiles, -1);
-        OK_TRY(dalloc(&d_rounds, cap_slots));
         OK_TRY(dalloc(&d_visits, cap_slots));
         OK_TRY(dalloc(&d_cell_visits, cap_slots));
         OK_TRY(dalloc(&d_total_cells, 1));
@@ -374,13 +385,12 @@ class Solver {
         HIP_TRY(hipMemsetAsync(d_tile_maze, 0xff, sizeof(int32_t) * cap_tiles, stream));
         HIP_TRY(hipMemsetAsync(d_flags[0], 0, sizeof(int32_t) * cap_tiles, stream));
         HIP_TRY(hipMemsetAsync(d_flags[1], 0, sizeof(int32_t) * cap_tiles, stream));
-        HIP_TRY(hipMemsetAsync(d_count, 0, 2 * sizeof(int32_t), stream));
-        HIP_TRY(hipMemsetAsync(d_changed, 0, sizeof(int32_t) * cap_slots, stream));
-        HIP_TRY(hipMemsetAsync(d_sched, 0, sizeof(int32_t) * cap_slots, stream));
-        HIP_TRY(hipMemsetAsync(d_state, 0, sizeof(int32_t) * cap_slots, stream));
-        HIP_TRY(hipMemsetAsync(d_sched_cells, 0, sizeof(unsigned long long) * cap_slots, stream));
+        HIP_TRY(hipMemsetAsync(d_count, 0, 3 * sizeof(int32_t), stream));
+        HIP_TRY(hipMemsetAsync(d_sched, 0, 3 * sizeof(int32_t) * cap_slots, stream));
+        HIP_TRY(hipMemsetAsync(d_dchg, 0, 3 * sizeof(int32_t) * cap_slots, stream));
+        HIP_TRY(hipMemsetAsync(d_last_round, 0, sizeof(int32_t) * cap_slots, stream));
+        HIP_TRY(hipMemsetAsync(d_touched, 0, cap_tiles, stream));
         HIP_TRY(hipMemsetAsync(d_bad_slot, 0, sizeof(int32_t) * cap_slots, stream));
-        HIP_TRY(hipMemsetAsync(d_rounds, 0, sizeof(int64_t) * cap_slots, stream));
         HIP_TRY(hipMemsetAsync(d_visits, 0, sizeof(int64_t) * cap_slots, stream));
         HIP_TRY(hipMemsetAsync(d_cell_visits, 0, sizeof(int64_t) * cap_slots, stream));
         HIP_TRY(hipMemsetAsync(d_total_cells, 0, sizeof(unsigned long long), stream));
@@ -396,31 +406,36 @@ class Solver {
         return OMAP_OK;
     }
 
-    // Arguments of the round that reads parity `parity`.  With `seeding` the
-    // "out" list is the one that round itself reads (seeds schedule tiles for
-    // the round about to run).
+    // Arguments of round r = next_round.  With `seeding` the "out" list,
+    // count, flags and scheduled counts are those of round r itself (seeds
+    // schedule tiles for the round about to run).
     RoundArgs round_args(bool seeding = false) const {
         RoundArgs a;
-        const int pin = parity, pout = seeding ? parity : parity ^ 1;
+        const int r2 = (int)(next_round & 1), r3 = (int)(next_round % 3);
+        const int n2 = r2 ^ 1, n3 = (r3 + 1) % 3, nn3 = (r3 + 2) % 3;
         a.mazes = d_mazes;
         a.tile_maze = d_tile_maze;
         a.n_tile_ids = tile_hwm;
-        a.list_in = d_list[pin];
-        a.count_in = d_count + pin;
-        a.flags_in = d_flags[pin];
-        a.list_out = d_list[pout];
-        a.count_out = d_count + pout;
-        a.flags_out = d_flags[pout];
-        a.maze_changed = d_changed;
-        a.maze_sched = d_sched;
-        a.maze_sched_cells = d_sched_cells;
-        a.maze_state = d_state;
-        a.maze_rounds = d_rounds;
+        a.list_in = d_list[r2];
+        a.count_in = d_count + r3;
+        a.flags_in = d_flags[r2];
+        a.list_out = d_list[seeding ? r2 : n2];
+        a.count_out = d_count + (seeding ? r3 : n3);
+        a.flags_out = d_flags[seeding ? r2 : n2];
+        a.count_clear = d_count + nn3;
+        a.sched_out = d_sched + (size_t)(seeding ? r3 : n3) * cap_slots;
+        a.sched_clear = d_sched + (size_t)nn3 * cap_slots;
+        a.dchg_prev = d_dchg + (size_t)nn3 * cap_slots;   // written in round r-1
+        a.dchg_cur = d_dchg + (size_t)r3 * cap_slots;
+        a.dchg_clear = d_dchg + (size_t)n3 * cap_slots;
+        a.maze_last_round = d_last_round;
+        a.touched = d_touched;
         a.maze_visits = d_visits;
         a.maze_cell_visits = d_cell_visits;
         a.total_cells = d_total_cells;
         a.n_slots = cap_slots;
-        a.parity = parity;
+        a.round_id = (int32_t)next_round;
+        a.parity = r2;
         a.tile_rows = opt.TH;
         a.tile_cols = opt.TW;
         a.dense = opt.dense;
@@ -593,7 +608,6 @@ class Solver {
         if (!s.used) return OMAP_OK;
         if (s.n_tiles > 0) {
             OK_TRY(upload_tile_range(s.tile_base, s.n_tiles, -1));
-            HIP_TRY(hipMemsetAsync(d_state + k, 0, sizeof(int32_t), stream));   // kMazeIdle
             give_tiles(s.tile_base, s.n_tiles);
         }
         free_slot_buffers(s);
@@ -611,12 +625,18 @@ class Solver {
         s.L_req = L;
         s.K = L < 0 ? 0x7fffffff : (int32_t)(L + 1);
         OK_TRY(upload_desc(k));
-        HIP_TRY(launch_fill(s.V[0], s.g.v_bytes / 4, 0, stream));
-        HIP_TRY(launch_fill(s.V[1], s.g.v_bytes / 4, 0, stream));
         const RoundArgs a = round_args(true);
+        if (s.cleared) {
+            HIP_TRY(launch_clear_touched(a, k, s.n_tiles, stream));
+        } else {
+            HIP_TRY(launch_fill(s.V[0], s.g.v_bytes / 4, 0, stream));
+            HIP_TRY(launch_fill(s.V[1], s.g.v_bytes / 4, 0, stream));
+            HIP_TRY(hipMemsetAsync(d_touched + s.tile_base, 0, s.n_tiles, stream));
+            s.cleared = true;
+        }
         HIP_TRY(launch_slot_reset(a, k, stream));
         HIP_TRY(launch_seed(a, k, s.d_src, (int32_t)(s.src.size() / 2), d_bad, stream));
-        if (opt.dense) HIP_TRY(launch_schedule_all(a, k, s.n_tiles, stream));
+        s.first_round = next_round;
         s.started = true;
         s.finalized = false;
         s.layers = -1;
@@ -625,16 +645,15 @@ class Solver {
 
     // Empty schedule (before starting every resident maze afresh).
     omap_status_t reset_schedule() {
-        HIP_TRY(hipMemsetAsync(d_count, 0, 2 * sizeof(int32_t), stream));
+        HIP_TRY(hipMemsetAsync(d_count, 0, 3 * sizeof(int32_t), stream));
         HIP_TRY(hipMemsetAsync(d_flags[0], 0, sizeof(int32_t) * std::max(tile_hwm, 1), stream));
         HIP_TRY(hipMemsetAsync(d_flags[1], 0, sizeof(int32_t) * std::max(tile_hwm, 1), stream));
-        HIP_TRY(hipMemsetAsync(d_sched, 0, sizeof(int32_t) * cap_slots, stream));
-        HIP_TRY(hipMemsetAsync(d_sched_cells, 0, sizeof(unsigned long long) * cap_slots, stream));
-        HIP_TRY(hipMemsetAsync(d_changed, 0, sizeof(int32_t) * cap_slots, stream));
+        HIP_TRY(hipMemsetAsync(d_sched, 0, 3 * sizeof(int32_t) * cap_slots, stream));
+        HIP_TRY(hipMemsetAsync(d_dchg, 0, 3 * sizeof(int32_t) * cap_slots, stream));
         return OMAP_OK;
     }
 
-    // One round: the sweep over this round's tiles, then the one-block finish.
+    // One round: one sweep launch.
     omap_status_t round() {
         const RoundArgs a = round_args();
         if (prof) {
@@ -648,13 +667,13 @@ class Solver {
         } else {
             HIP_TRY(launch_sweep(opt.T, opt.C, a, grid, stream));
         }
-        HIP_TRY(launch_finish(a, stream));
-        parity ^= 1;
+        ++next_round;
+        parity = (int)(next_round & 1);
         return OMAP_OK;
     }
 
     omap_status_t scheduled_count(int32_t* n) {
-        HIP_TRY(hipMemcpyAsync(h_pinned, d_count + parity, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+        HIP_TRY(hipMemcpyAsync(h_pinned, d_count + next_round % 3, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
         HIP_TRY(hipStreamSynchronize(stream));
         *n = h_pinned[0];
         return OMAP_OK;
@@ -726,12 +745,15 @@ class Solver {
 
     omap_status_t info(int32_t k, omap_propagate_info* out) {
         OK_TRY(ensure_finalized(k));
-        int64_t v[3];
-        HIP_TRY(hipMemcpyAsync(&v[0], d_rounds + k, sizeof(int64_t), hipMemcpyDeviceToHost, stream));
+        int64_t v[3] = {0, 0, 0};
+        int32_t last = 0;
+        HIP_TRY(hipMemcpyAsync(&last, d_last_round + k, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
         HIP_TRY(hipMemcpyAsync(&v[1], d_visits + k, sizeof(int64_t), hipMemcpyDeviceToHost, stream));
         HIP_TRY(hipMemcpyAsync(&v[2], d_cell_visits + k, sizeof(int64_t), hipMemcpyDeviceToHost, stream));
         HIP_TRY(hipStreamSynchronize(stream));
         const Slot& s = slots[k];
+        v[0] = (int64_t)(int32_t)(last - (int32_t)s.first_round) + 1;   // rounds the maze was visited
+        if (v[0] < 0) v[0] = 0;
         out->layers = s.layers;
         out->rounds = v[0];
         out->sweeps_executed = v[0] * opt.T;
@@ -741,35 +763,85 @@ class Solver {
     }
 
     // Paths of the targets of `which` (in that order), written to caller
-    // buffers (device).  len/off/cells may be device pointers owned by the
-    // caller; scratch comes from `mem`.
+    // buffers: device buffers, or host buffers with host_out.  mode: 0 simple
+    // reconstruction (fixed tie order), 1 simple with seeded random ties,
+    // 2 Euclidean.  src_out (optional): index of the source each path ends on.
+    // Scratch comes from a grow-only device buffer.
     omap_status_t extract(const std::vector<int32_t>& which, int32_t* len_out, int64_t* off_out,
-                          int32_t* cells_out, int64_t capacity, int64_t* needed, bool host_out) {
-        std::vector<int32_t> tslot, trc;
+                          int32_t* cells_out, int64_t capacity, int64_t* needed, bool host_out,
+                          int mode = 0, uint64_t seed = 0, int32_t* src_out = nullptr) {
+        std::vector<int32_t> tslot, trc, tlocal, sbase, scount, ssorted;
         for (int32_t k : which) {
             const Slot& s = slots[k];
             if (!s.started) return fail(OMAP_ERR_NOT_PROPAGATED, "maze %d has not been propagated", k);
             const int32_t n = (int32_t)(s.tgt.size() / 2);
             tslot.insert(tslot.end(), n, k);
             trc.insert(trc.end(), s.tgt.begin(), s.tgt.end());
+            for (int32_t t = 0; t < n; ++t) tlocal.push_back(t);
+            if (src_out) {
+                // (linear cell, first list index), sorted by cell, duplicates dropped
+                std::vector<std::pair<int32_t, int32_t>> v;
+                for (size_t j = 0; j < s.src.size() / 2; ++j)
+                    v.push_back({s.src[2 * j] * s.g.W + s.src[2 * j + 1], (int32_t)j});
+                std::sort(v.begin(), v.end());
+                v.erase(std::unique(v.begin(), v.end(),
+                                    [](const std::pair<int32_t, int32_t>& a, const std::pair<int32_t, int32_t>& b) {
+                                        return a.first == b.first;
+                                    }),
+                        v.end());
+                const int32_t base = (int32_t)(ssorted.size() / 2);
+                for (auto& e : v) {
+                    ssorted.push_back(e.first);
+                    ssorted.push_back(e.second);
+                }
+                sbase.insert(sbase.end(), n, base);
+                scount.insert(scount.end(), n, (int32_t)v.size());
+            }
         }
         const int32_t n = (int32_t)tslot.size();
         auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
-        const size_t b_slot = up(sizeof(int32_t) * (n + 1)), b_rc = up(sizeof(int32_t) * (2 * n + 2));
-        const size_t b_len = up(sizeof(int32_t) * (n + 1)), b_off = up(sizeof(int64_t) * (n + 1));
+        const size_t b_i = up(sizeof(int32_t) * (n + 1)), b_rc = up(sizeof(int32_t) * (2 * n + 2));
+        const size_t b_off = up(sizeof(int64_t) * (n + 1)), b_ss = up(sizeof(int32_t) * (ssorted.size() + 2));
+        // layout: tslot | trc | tlocal | len | off | sbase | scount | ssorted | (cells for host_out)
+        const size_t fixed = b_i + b_rc + b_i + b_i + b_off + b_i + b_i + b_ss;
         char* base = nullptr;
-        OK_TRY(scratch(b_slot + b_rc + b_len + b_off, &base));
-        int32_t* d_tslot = reinterpret_cast<int32_t*>(base);
-        int32_t* d_trc = reinterpret_cast<int32_t*>(base + b_slot);
-        int32_t* d_len = reinterpret_cast<int32_t*>(base + b_slot + b_rc);
-        int64_t* d_off = reinterpret_cast<int64_t*>(base + b_slot + b_rc + b_len);
-        if (n > 0) {
-            HIP_TRY(hipMemcpyAsync(d_tslot, tslot.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, stream));
-            HIP_TRY(hipMemcpyAsync(d_trc, trc.data(), sizeof(int32_t) * 2 * n, hipMemcpyHostToDevice, stream));
-            HIP_TRY(launch_path_lengths(d_mazes, d_tslot, d_trc, n, parity, d_len, stream));
-        }
-        HIP_TRY(launch_scan_offsets(d_len, n, d_off, stream));
-        HIP_TRY(hipMemcpyAsync(h_pinned, d_off + n, sizeof(int64_t), hipMemcpyDeviceToHost, stream));
+        OK_TRY(scratch(fixed, &base));
+        auto carve = [&](char* b) {
+            struct P { int32_t *tslot, *trc, *tlocal, *len; int64_t* off; int32_t *sbase, *scount, *ss; char* end; } q;
+            q.tslot = reinterpret_cast<int32_t*>(b); b += b_i;
+            q.trc = reinterpret_cast<int32_t*>(b); b += b_rc;
+            q.tlocal = reinterpret_cast<int32_t*>(b); b += b_i;
+            q.len = reinterpret_cast<int32_t*>(b); b += b_i;
+            q.off = reinterpret_cast<int64_t*>(b); b += b_off;
+            q.sbase = reinterpret_cast<int32_t*>(b); b += b_i;
+            q.scount = reinterpret_cast<int32_t*>(b); b += b_i;
+            q.ss = reinterpret_cast<int32_t*>(b); b += b_ss;
+            q.end = b;
+            return q;
+        };
+        auto q = carve(base);
+        // lengths and offsets (the Euclidean walk learns its lengths by walking)
+        auto lengths = [&](decltype(q)& d) -> omap_status_t {
+            if (n > 0) {
+                HIP_TRY(hipMemcpyAsync(d.tslot, tslot.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, stream));
+                HIP_TRY(hipMemcpyAsync(d.trc, trc.data(), sizeof(int32_t) * 2 * n, hipMemcpyHostToDevice, stream));
+                HIP_TRY(hipMemcpyAsync(d.tlocal, tlocal.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, stream));
+                if (src_out) {
+                    HIP_TRY(hipMemcpyAsync(d.sbase, sbase.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, stream));
+                    HIP_TRY(hipMemcpyAsync(d.scount, scount.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, stream));
+                    HIP_TRY(hipMemcpyAsync(d.ss, ssorted.data(), sizeof(int32_t) * ssorted.size(),
+                                           hipMemcpyHostToDevice, stream));
+                }
+                if (mode == 2)
+                    HIP_TRY(launch_walk_euclid(false, d_mazes, d.tslot, d.trc, n, parity, d.len, nullptr, nullptr, stream));
+                else
+                    HIP_TRY(launch_path_lengths(d_mazes, d.tslot, d.trc, n, parity, d.len, stream));
+            }
+            HIP_TRY(launch_scan_offsets(d.len, n, d.off, stream));
+            return OMAP_OK;
+        };
+        OK_TRY(lengths(q));
+        HIP_TRY(hipMemcpyAsync(h_pinned, q.off + n, sizeof(int64_t), hipMemcpyDeviceToHost, stream));
         HIP_TRY(hipStreamSynchronize(stream));   // also retires the host sources of the uploads
         int64_t total = 0;
         std::memcpy(&total, h_pinned, sizeof total);
@@ -778,30 +850,30 @@ class Solver {
             return fail(OMAP_ERR_BUFFER_TOO_SMALL, "paths need %lld cells, capacity %lld",
                         (long long)total, (long long)capacity);
         int32_t* walk_dst = cells_out;
-        if (host_out) {
-            // the walk writes into scratch behind the offsets, then everything goes to host
+        if (host_out || src_out) {
+            // cells go to scratch first (host copy and/or source lookup read them there)
             const size_t b_cells = up(sizeof(int32_t) * (size_t)(total + 1));
             char* base2 = nullptr;
-            OK_TRY(scratch(b_slot + b_rc + b_len + b_off + b_cells, &base2));
-            if (base2 != base) {   // scratch moved: lengths/offsets must be recomputed
-                d_tslot = reinterpret_cast<int32_t*>(base2);
-                d_trc = reinterpret_cast<int32_t*>(base2 + b_slot);
-                d_len = reinterpret_cast<int32_t*>(base2 + b_slot + b_rc);
-                d_off = reinterpret_cast<int64_t*>(base2 + b_slot + b_rc + b_len);
-                if (n > 0) {
-                    HIP_TRY(hipMemcpyAsync(d_tslot, tslot.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, stream));
-                    HIP_TRY(hipMemcpyAsync(d_trc, trc.data(), sizeof(int32_t) * 2 * n, hipMemcpyHostToDevice, stream));
-                    HIP_TRY(launch_path_lengths(d_mazes, d_tslot, d_trc, n, parity, d_len, stream));
-                }
-                HIP_TRY(launch_scan_offsets(d_len, n, d_off, stream));
+            OK_TRY(scratch(fixed + b_cells, &base2));
+            if (base2 != base) {   // scratch moved: redo the lengths in the new place
+                q = carve(base2);
+                OK_TRY(lengths(q));
                 base = base2;
             }
-            walk_dst = reinterpret_cast<int32_t*>(base + b_slot + b_rc + b_len + b_off);
+            if (host_out) walk_dst = reinterpret_cast<int32_t*>(q.end);
         }
-        HIP_TRY(launch_walk(d_mazes, d_tslot, d_trc, n, parity, d_len, d_off, walk_dst, stream));
+        if (mode == 2)
+            HIP_TRY(launch_walk_euclid(true, d_mazes, q.tslot, q.trc, n, parity, q.len, q.off, walk_dst, stream));
+        else if (mode == 1)
+            HIP_TRY(launch_walk_random(d_mazes, q.tslot, q.trc, q.tlocal, n, parity, seed, q.len, q.off, walk_dst, stream));
+        else
+            HIP_TRY(launch_walk(d_mazes, q.tslot, q.trc, n, parity, q.len, q.off, walk_dst, stream));
         const hipMemcpyKind kind = host_out ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
-        if (n > 0) HIP_TRY(hipMemcpyAsync(len_out, d_len, sizeof(int32_t) * n, kind, stream));
-        HIP_TRY(hipMemcpyAsync(off_out, d_off, sizeof(int64_t) * (n + 1), kind, stream));
+        if (src_out)
+            HIP_TRY(launch_source_index(d_mazes, q.tslot, n, q.len, q.off, walk_dst, q.ss, q.sbase, q.scount,
+                                        src_out, stream));
+        if (n > 0) HIP_TRY(hipMemcpyAsync(len_out, q.len, sizeof(int32_t) * n, kind, stream));
+        HIP_TRY(hipMemcpyAsync(off_out, q.off, sizeof(int64_t) * (n + 1), kind, stream));
         if (host_out && total > 0)
             HIP_TRY(hipMemcpyAsync(cells_out, walk_dst, sizeof(int32_t) * total, kind, stream));
         HIP_TRY(hipStreamSynchronize(stream));
@@ -961,16 +1033,23 @@ static omap_status_t engine_admit(omap_engine_s* e) {
 
 static omap_status_t engine_retire(omap_engine_s* e) {
     if (e->resident.empty()) return OMAP_OK;
-    std::vector<int32_t> states(e->solver.cap_slots);
-    HIP_TRY(hipMemcpyAsync(states.data(), e->solver.d_state, sizeof(int32_t) * states.size(),
-                           hipMemcpyDeviceToHost, e->solver.stream));
-    HIP_TRY(hipStreamSynchronize(e->solver.stream));
+    // A resident maze is done when nothing of it is scheduled for the next
+    // round: no listed tile (active schedule) / no change in the last round
+    // (dense schedule).
+    Solver& sv = e->solver;
+    const int64_t r = sv.next_round;
+    const int32_t* src = sv.opt.dense ? sv.d_dchg + (size_t)((r + 2) % 3) * sv.cap_slots
+                                      : sv.d_sched + (size_t)(r % 3) * sv.cap_slots;
+    std::vector<int32_t> pending(sv.cap_slots);
+    HIP_TRY(hipMemcpyAsync(pending.data(), src, sizeof(int32_t) * pending.size(), hipMemcpyDeviceToHost,
+                           sv.stream));
+    HIP_TRY(hipStreamSynchronize(sv.stream));
     std::vector<int64_t> keep;
     std::vector<int32_t> done_slots;
     std::vector<int64_t> done_ids;
     for (int64_t id : e->resident) {
         Query& q = e->queries[id];
-        if (states[q.slot] == kMazeDone) {
+        if (pending[q.slot] == 0) {
             done_slots.push_back(q.slot);
             done_ids.push_back(id);
         } else {
@@ -1114,6 +1193,34 @@ omap_status_t omap_extract_paths(omap_plan_t plan, int32_t* len_dev, int64_t* of
     API_GUARD_END
 }
 
+static omap_status_t walk_mode(const omap_walk_options* w, int* mode, uint64_t* seed) {
+    *mode = 0;
+    *seed = 0;
+    if (!w) return OMAP_OK;
+    if (w->mode != OMAP_WALK_FIRST_MAX && w->mode != OMAP_WALK_RANDOM_TIES && w->mode != OMAP_WALK_EUCLIDEAN)
+        return fail(OMAP_ERR_INVALID_ARG, "walk mode %d", w->mode);
+    *mode = w->mode;
+    *seed = w->seed;
+    return OMAP_OK;
+}
+
+omap_status_t omap_extract_paths_ex(omap_plan_t plan, const omap_walk_options* walk, int32_t* len_dev,
+                                    int64_t* offsets_dev, int32_t* cells_dev, int64_t cells_capacity,
+                                    int64_t* cells_needed_host, int32_t* source_index_dev) {
+    API_GUARD_BEGIN
+    if (!plan) return fail(OMAP_ERR_INVALID_ARG, "plan is NULL");
+    int mode = 0;
+    uint64_t seed = 0;
+    OK_TRY(walk_mode(walk, &mode, &seed));
+    if (!plan->propagated) return fail(OMAP_ERR_NOT_PROPAGATED, "call omap_propagate first");
+    const int32_t nt = (int32_t)(plan->solver.slots[plan->slot].tgt.size() / 2);
+    if (!offsets_dev || (nt > 0 && !len_dev)) return fail(OMAP_ERR_INVALID_ARG, "len/offsets pointer is NULL");
+    std::vector<int32_t> one{plan->slot};
+    return plan->solver.extract(one, len_dev, offsets_dev, cells_dev, cells_capacity, cells_needed_host, false,
+                                mode, seed, source_index_dev);
+    API_GUARD_END
+}
+
 omap_status_t omap_plan_destroy(omap_plan_t plan) {
     API_GUARD_BEGIN
     if (!plan) return OMAP_OK;
@@ -1215,6 +1322,22 @@ omap_status_t omap_batch_extract_paths(omap_batch_t batch, int32_t* len_dev, int
     if (!offsets_dev || !len_dev) return fail(OMAP_ERR_INVALID_ARG, "len/offsets pointer is NULL");
     return batch->solver.extract(batch->slots, len_dev, offsets_dev, cells_dev, cells_capacity,
                                  cells_needed_host, false);
+    API_GUARD_END
+}
+
+omap_status_t omap_batch_extract_paths_ex(omap_batch_t batch, const omap_walk_options* walk,
+                                          int32_t* len_dev, int64_t* offsets_dev, int32_t* cells_dev,
+                                          int64_t cells_capacity, int64_t* cells_needed_host,
+                                          int32_t* source_index_dev) {
+    API_GUARD_BEGIN
+    if (!batch) return fail(OMAP_ERR_INVALID_ARG, "batch is NULL");
+    int mode = 0;
+    uint64_t seed = 0;
+    OK_TRY(walk_mode(walk, &mode, &seed));
+    if (!batch->propagated) return fail(OMAP_ERR_NOT_PROPAGATED, "call omap_batch_propagate first");
+    if (!offsets_dev || !len_dev) return fail(OMAP_ERR_INVALID_ARG, "len/offsets pointer is NULL");
+    return batch->solver.extract(batch->slots, len_dev, offsets_dev, cells_dev, cells_capacity,
+                                 cells_needed_host, false, mode, seed, source_index_dev);
     API_GUARD_END
 }
 
