@@ -184,8 +184,7 @@ def bench_plain(args):
         "vs_baseline": None, "dtype": "int32", "data": "synthetic",
         "config": {"workload": m.name, "cells": N, "sources": len(m.sources), "targets": nt,
                    "layers_run_time": L_star, "effective_layers": S_J,
-                   "temporal_depth": args.depth or 16, "tile_rows": args.tile_rows or 64,
-                   "schedule": "dense" if args.schedule else "active"},
+                   "options": omap.resolve_options(**opts)},
         "paths_per_s": round(nt / step_s, 1),
         "path_cells": int(cells0.numel()),
         "phase_ms": {"ingest": round(t_load, 3), "propagate": round(t_prop, 3), "extract": round(t_ext, 3)},

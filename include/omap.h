@@ -88,7 +88,21 @@ typedef struct omap_options {
                              /* 0 = adaptive                                                */
     int32_t lane_columns;    /* columns each lane owns (tile strip = 64 x this): 2 or 4;   */
                              /* 0 = default (active: 2; dense: 4)                          */
+    int32_t round_launch;    /* OMAP_LAUNCH_PER_ROUND (default): one launch per round;     */
+                             /* OMAP_LAUNCH_PERSISTENT: one cooperative launch runs rounds */
+                             /* until convergence, separated by a device-wide barrier      */
+                             /* (bit-identical results; slower on MI355X, where the        */
+                             /* barrier costs more than a kernel boundary)                 */
 } omap_options;
+
+#define OMAP_LAUNCH_PER_ROUND 0
+#define OMAP_LAUNCH_PERSISTENT 1
+
+/* The options a plan, batch or engine created with `options` (NULL = all
+ * defaults) would run with: every zero field replaced by its default.  Host
+ * only, no device call.  Returns OMAP_ERR_INVALID_ARG (and leaves *resolved
+ * untouched) for the same option values the create calls reject. */
+omap_status_t omap_resolve_options(const omap_options *options, omap_options *resolved);
 
 /* Per-maze report of a propagation. */
 typedef struct omap_propagate_info {

@@ -47,7 +47,7 @@ class OmapError(RuntimeError):
 class Options(ctypes.Structure):
     _fields_ = [("temporal_depth", ctypes.c_int32), ("tile_rows", ctypes.c_int32),
                 ("schedule", ctypes.c_int32), ("check_interval", ctypes.c_int32),
-                ("lane_columns", ctypes.c_int32)]
+                ("lane_columns", ctypes.c_int32), ("round_launch", ctypes.c_int32)]
 
 
 class PropagateInfo(ctypes.Structure):
@@ -110,6 +110,7 @@ def lib() -> ctypes.CDLL:
         "omap_profile_enable": [P, i32, i32],
         "omap_profile_read": [P, i32, P, P, P],
         "omap_selftest": [P],
+        "omap_resolve_options": [P, P],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -144,9 +145,20 @@ def _stream(stream=None) -> int:
     return int(stream.cuda_stream) if hasattr(stream, "cuda_stream") else int(stream)
 
 
+LAUNCH_PER_ROUND, LAUNCH_PERSISTENT = 0, 1
+
+
 def _options(temporal_depth=0, tile_rows=0, schedule=SCHEDULE_ACTIVE, check_interval=0,
-             lane_columns=0):
-    return Options(temporal_depth, tile_rows, schedule, check_interval, lane_columns)
+             lane_columns=0, round_launch=LAUNCH_PER_ROUND):
+    return Options(temporal_depth, tile_rows, schedule, check_interval, lane_columns, round_launch)
+
+
+def resolve_options(**options) -> dict:
+    """The options a plan / batch / engine created with these keyword options
+    runs with (defaults filled in); host only."""
+    out = Options()
+    _check(lib().omap_resolve_options(ctypes.byref(_options(**options)), ctypes.byref(out)))
+    return {f: getattr(out, f) for f, _ in Options._fields_}
 
 
 def _device_u8(occ):

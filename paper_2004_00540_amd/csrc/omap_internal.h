@@ -60,6 +60,23 @@ struct RoundArgs {
     int32_t dense;                // 1 = dense schedule
 };
 
+// Arguments of a persistent launch running rounds r0, r0+1, ... : the
+// per-round pointers are derived on the device from these bases exactly as
+// the host derives them for a single-round launch.
+struct PersistentArgs {
+    RoundArgs base;               // constant fields; round_id = r0
+    int32_t* list[2];
+    int32_t* count;               // [3]
+    int32_t* flags[2];
+    int32_t* sched;               // [3][n_slots]
+    int32_t* dchg;                // [3][n_slots]
+    int32_t r0_mod6;              // r0 mod 6 (both mod-2 and mod-3 phases)
+    int32_t max_rounds;
+    unsigned int* bar_count;      // barrier state, zero between launches
+    unsigned int* bar_gen;
+    int32_t* rounds_done;         // rounds actually run
+};
+
 // ---- launch wrappers (omap_kernels.hip) -------------------------------------
 hipError_t launch_pack_mask(const uint8_t* occ, int32_t H, int32_t W, uint32_t* mask,
                             int32_t mpitch, hipStream_t s);
@@ -73,6 +90,9 @@ hipError_t launch_check_sources(const uint32_t* mask, int32_t mpitch, const int3
                                 int32_t n_src, int32_t* bad_count, hipStream_t s);
 bool sweep_supported(int T, int C);
 hipError_t launch_sweep(int T, int C, const RoundArgs& a, int32_t grid, hipStream_t s);
+// Cooperative launch of up to p.max_rounds rounds (grid must fit co-resident).
+hipError_t launch_sweep_persistent(int T, int C, const PersistentArgs& p, int32_t grid, hipStream_t s);
+int sweep_persistent_blocks_per_cu(int T, int C);
 // Clears slot's counters before its seeds (last round = r-1; dense: marks the
 // maze for a visit in the round about to run through a.dchg_prev).
 hipError_t launch_slot_reset(const RoundArgs& a, int32_t slot, hipStream_t s);

@@ -302,13 +302,20 @@ __global__ void k_slot_reset(RoundArgs a, int32_t slot) {
     if (a.dense) a.dchg_prev[slot] = 1;
 }
 
+// Loads of scheduling data that another block may have written in an earlier
+// round of the same (persistent) launch: agent-scope atomic loads bypass the
+// per-CU caches.
+__device__ __forceinline__ int32_t load_shared(const int32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Round r: every scheduled tile gets T layers.  Active schedule: the tiles of
 // a.list_in; a changed tile schedules itself and its 8 neighbour tiles for
 // round r+1.  Dense schedule: every tile of each maze that changed in round
 // r-1; a changed tile flags its maze for round r+1.  Block 0 also clears the
 // buffers round r+1 will fill.
 template <int T, int C>
-__global__ __launch_bounds__(kBlockThreads) void k_sweep(RoundArgs a) {
+__device__ __forceinline__ void sweep_round(const RoundArgs& a) {
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = lane_id();
     if (blockIdx.x == 0) {
@@ -318,16 +325,16 @@ __global__ __launch_bounds__(kBlockThreads) void k_sweep(RoundArgs a) {
             a.dchg_clear[m] = 0;
         }
     }
-    const int n = a.dense ? a.n_tile_ids : __builtin_amdgcn_readfirstlane(*a.count_in);
+    const int n = a.dense ? a.n_tile_ids : __builtin_amdgcn_readfirstlane(load_shared(a.count_in));
     const int stride = gridDim.x * kWavesPerBlock;
     for (int i = blockIdx.x * kWavesPerBlock + wave; i < n; i += stride) {
         int g, slot;
         if (a.dense) {
             g = i;
             slot = a.tile_maze[g];
-            if (slot < 0 || a.dchg_prev[slot] == 0) continue;
+            if (slot < 0 || __builtin_amdgcn_readfirstlane(load_shared(a.dchg_prev + slot)) == 0) continue;
         } else {
-            g = a.list_in[i];
+            g = __builtin_amdgcn_readfirstlane(load_shared(a.list_in + i));
             if (lane == 0) a.flags_in[g] = 0;
             slot = a.tile_maze[g];
         }
@@ -357,6 +364,69 @@ __global__ __launch_bounds__(kBlockThreads) void k_sweep(RoundArgs a) {
             }
         }
     }
+}
+
+template <int T, int C>
+__global__ __launch_bounds__(kBlockThreads) void k_sweep(RoundArgs a) {
+    sweep_round<T, C>(a);
+}
+
+// Device-wide barrier of a cooperative launch (all blocks resident): the last
+// block to arrive resets the counter and advances the generation; the others
+// wait for the generation to change.  Fences on both sides publish this
+// block's writes and drop stale lines from the CU's caches.
+__device__ __forceinline__ void grid_barrier(unsigned int* count, unsigned int* gen) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned int g = __hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __threadfence();
+        if (atomicAdd(count, 1u) == gridDim.x - 1) {
+            __hip_atomic_store(count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __threadfence();
+            atomicAdd(gen, 1u);
+        } else {
+            while (__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g)
+                __builtin_amdgcn_s_sleep(1);
+        }
+    }
+    __syncthreads();
+    __threadfence();
+}
+
+// Up to p.max_rounds rounds in one cooperative launch, stopping after the
+// first round that schedules nothing (every resident maze converged).  The
+// stop test reads the round's final count after the barrier, so every block
+// takes the same decision.
+template <int T, int C>
+__global__ __launch_bounds__(kBlockThreads) void k_sweep_persistent(PersistentArgs p) {
+    int k = 0;
+    for (; k < p.max_rounds; ++k) {
+        RoundArgs a = p.base;
+        const int r = p.r0_mod6 + k;
+        const int r2 = r & 1, r3 = r % 3, n3 = (r3 + 1) % 3, nn3 = (r3 + 2) % 3;
+        const size_t cs = (size_t)p.base.n_slots;
+        a.list_in = p.list[r2];
+        a.count_in = p.count + r3;
+        a.flags_in = p.flags[r2];
+        a.list_out = p.list[r2 ^ 1];
+        a.count_out = p.count + n3;
+        a.flags_out = p.flags[r2 ^ 1];
+        a.count_clear = p.count + nn3;
+        a.sched_out = p.sched + n3 * cs;
+        a.sched_clear = p.sched + nn3 * cs;
+        a.dchg_prev = p.dchg + nn3 * cs;
+        a.dchg_cur = p.dchg + r3 * cs;
+        a.dchg_clear = p.dchg + n3 * cs;
+        a.round_id = p.base.round_id + k;
+        a.parity = r2;
+        sweep_round<T, C>(a);
+        grid_barrier(p.bar_count, p.bar_gen);
+        if (load_shared(a.count_out) == 0) {
+            ++k;
+            break;
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) *p.rounds_done = k;
 }
 
 // One wave per tile of `slot`: zero the interior of touched tiles in both
@@ -815,6 +885,29 @@ hipError_t launch_slot_reset(const RoundArgs& a, int32_t slot, hipStream_t s) {
 // Sweep kernels instantiated for (layers per visit, columns per lane).
 #define OMAP_SWEEP_VARIANTS(X) \
     X(4, 4) X(8, 4) X(12, 4) X(16, 4) X(4, 2) X(8, 2) X(12, 2) X(16, 2) X(24, 2) X(32, 2)
+
+hipError_t launch_sweep_persistent(int T, int C, const PersistentArgs& p, int32_t grid, hipStream_t s) {
+    void* args[] = {const_cast<PersistentArgs*>(&p)};
+#define X(t, c)                                                                                      \
+    if (T == t && C == c)                                                                            \
+        return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_sweep_persistent<t, c>),   \
+                                          dim3(grid), dim3(kBlockThreads), args, 0, s);
+    OMAP_SWEEP_VARIANTS(X)
+#undef X
+    return hipErrorInvalidValue;
+}
+
+int sweep_persistent_blocks_per_cu(int T, int C) {
+    int blocks = 0;
+    hipError_t e = hipErrorInvalidValue;
+#define X(t, c)                                                                                       \
+    if (T == t && C == c)                                                                             \
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_sweep_persistent<t, c>, kBlockThreads, 0);
+    OMAP_SWEEP_VARIANTS(X)
+#undef X
+    if (e != hipSuccess) blocks = 0;
+    return blocks;
+}
 
 bool sweep_supported(int T, int C) {
 #define X(t, c) if (T == t && C == c) return true;

@@ -68,6 +68,7 @@ struct Options {
     int TW = 64 * 4 - 2 * 16;
     int dense = 0;
     int check = 0;       // 0 = adaptive
+    int per_round = 1;   // 0 = one persistent launch instead of one launch per round
 };
 
 // Defaults (measured on MI355X): the active schedule is latency-bound (few
@@ -98,6 +99,10 @@ static omap_status_t resolve_options(const omap_options* o, Options* out) {
         r.dense = dense;
         if (o->check_interval < 0) return fail(OMAP_ERR_INVALID_ARG, "check_interval < 0");
         r.check = o->check_interval;
+        if (o->round_launch != OMAP_LAUNCH_PERSISTENT && o->round_launch != OMAP_LAUNCH_PER_ROUND)
+            return fail(OMAP_ERR_INVALID_ARG, "round_launch must be PERSISTENT or PER_ROUND (got %d)",
+                        o->round_launch);
+        r.per_round = o->round_launch == OMAP_LAUNCH_PER_ROUND;
     }
     if (!sweep_supported(r.T, r.C))
         return fail(OMAP_ERR_INVALID_ARG,
@@ -292,6 +297,9 @@ class Solver {
     int32_t* d_dchg = nullptr;                // [3][cap_slots] dense: changed, by round mod 3
     int32_t* d_last_round = nullptr;          // per slot
     uint8_t* d_touched = nullptr;             // per tile id
+    unsigned int* d_bar = nullptr;            // [2] grid barrier of the persistent launch
+    int32_t* d_rounds_done = nullptr;
+    int pgrid = 0;                            // blocks of the persistent launch (0 = unavailable)
     int64_t *d_visits = nullptr, *d_cell_visits = nullptr;
     unsigned long long* d_total_cells = nullptr;
     int32_t* d_bad_slot = nullptr;            // per slot: sources found on obstacles
@@ -370,6 +378,8 @@ class Solver {
         OK_TRY(dalloc(&d_dchg, 3 * (size_t)cap_slots));
         OK_TRY(dalloc(&d_last_round, cap_slots));
         OK_TRY(dalloc(&d_touched, cap_tiles));
+        OK_TRY(dalloc(&d_bar, 2));
+        OK_TRY(dalloc(&d_rounds_done, 1));
         OK_TRY(dalloc(&d_bad_slot, cap_slots));
         HIP_TRY(hipHostMalloc((void**)&h_bad, sizeof(int32_t) * cap_slots, hipHostMallocDefault));
         h_mazes.assign(cap_slots, MazeDev());
@@ -390,6 +400,7 @@ class Solver {
         HIP_TRY(hipMemsetAsync(d_dchg, 0, 3 * sizeof(int32_t) * cap_slots, stream));
         HIP_TRY(hipMemsetAsync(d_last_round, 0, sizeof(int32_t) * cap_slots, stream));
         HIP_TRY(hipMemsetAsync(d_touched, 0, cap_tiles, stream));
+        HIP_TRY(hipMemsetAsync(d_bar, 0, 2 * sizeof(unsigned int), stream));
         HIP_TRY(hipMemsetAsync(d_bad_slot, 0, sizeof(int32_t) * cap_slots, stream));
         HIP_TRY(hipMemsetAsync(d_visits, 0, sizeof(int64_t) * cap_slots, stream));
         HIP_TRY(hipMemsetAsync(d_cell_visits, 0, sizeof(int64_t) * cap_slots, stream));
@@ -402,6 +413,10 @@ class Solver {
         grid = std::max(1, cus * std::max(1, waves / kWavesPerBlock));
         const int need = (cap_tiles + kWavesPerBlock - 1) / kWavesPerBlock;
         grid = std::max(1, std::min(grid, need));
+        int coop = 0;
+        HIP_TRY(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
+        const int per_cu = sweep_persistent_blocks_per_cu(opt.T, opt.C);
+        pgrid = (coop && per_cu > 0) ? std::max(1, std::min(cus * per_cu, need)) : 0;
         HIP_TRY(hipStreamSynchronize(stream));
         return OMAP_OK;
     }
@@ -679,8 +694,67 @@ class Solver {
         return OMAP_OK;
     }
 
+    // Up to `max_rounds` rounds in one cooperative launch; returns the rounds
+    // run (it stops early after a round that schedules nothing) and the
+    // number of tiles scheduled next (synchronous).
+    omap_status_t persistent(int32_t max_rounds, int32_t* ran, int32_t* scheduled) {
+        PersistentArgs p;
+        p.base = round_args();
+        p.list[0] = d_list[0];
+        p.list[1] = d_list[1];
+        p.count = d_count;
+        p.flags[0] = d_flags[0];
+        p.flags[1] = d_flags[1];
+        p.sched = d_sched;
+        p.dchg = d_dchg;
+        p.r0_mod6 = (int32_t)(next_round % 6);
+        p.max_rounds = max_rounds;
+        p.bar_count = d_bar;
+        p.bar_gen = d_bar + 1;
+        p.rounds_done = d_rounds_done;
+        std::pair<hipEvent_t, hipEvent_t> ev{};
+        if (prof) {
+            HIP_TRY(hipEventCreate(&ev.first));
+            HIP_TRY(hipEventCreate(&ev.second));
+            HIP_TRY(hipEventRecord(ev.first, stream));
+        }
+        HIP_TRY(launch_sweep_persistent(opt.T, opt.C, p, pgrid, stream));
+        if (prof) {
+            HIP_TRY(hipEventRecord(ev.second, stream));
+            prof_events.push_back(ev);
+        }
+        HIP_TRY(hipMemcpyAsync(h_pinned, d_rounds_done, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+        HIP_TRY(hipStreamSynchronize(stream));
+        *ran = h_pinned[0];
+        next_round += *ran;
+        parity = (int)(next_round & 1);
+        if (scheduled) OK_TRY(scheduled_count(scheduled));
+        return OMAP_OK;
+    }
+
+    bool use_persistent() const { return pgrid > 0 && !opt.per_round; }
+
+    // `rounds` rounds (fewer if everything converges first with the
+    // persistent launch).
+    omap_status_t run_rounds(int32_t rounds) {
+        if (rounds <= 0) return OMAP_OK;
+        if (use_persistent()) {
+            int32_t ran = 0;
+            return persistent(rounds, &ran, nullptr);
+        }
+        for (int32_t i = 0; i < rounds; ++i) OK_TRY(round());
+        return OMAP_OK;
+    }
+
     // Rounds until no tile is scheduled (every started maze converged).
     omap_status_t run_to_convergence() {
+        if (use_persistent()) {
+            for (;;) {
+                int32_t ran = 0, n = 0;
+                OK_TRY(persistent(1 << 30, &ran, &n));
+                if (n == 0) return OMAP_OK;
+            }
+        }
         int g = opt.check > 0 ? opt.check : 2;
         for (;;) {
             for (int i = 0; i < g; ++i) OK_TRY(round());
@@ -1104,6 +1178,19 @@ extern "C" {
 
 const char* omap_version(void) { return "omap-gfx950 0.1"; }
 
+omap_status_t omap_resolve_options(const omap_options* options, omap_options* resolved) {
+    if (!resolved) return fail(OMAP_ERR_INVALID_ARG, "resolved is NULL");
+    Options r;
+    OK_TRY(resolve_options(options, &r));
+    resolved->temporal_depth = r.T;
+    resolved->tile_rows = r.TH;
+    resolved->schedule = r.dense ? OMAP_SCHEDULE_DENSE : OMAP_SCHEDULE_ACTIVE;
+    resolved->check_interval = r.check;
+    resolved->lane_columns = r.C;
+    resolved->round_launch = r.per_round ? OMAP_LAUNCH_PER_ROUND : OMAP_LAUNCH_PERSISTENT;
+    return OMAP_OK;
+}
+
 const char* omap_last_error(void) { return g_last_error.c_str(); }
 
 const char* omap_status_string(omap_status_t s) {
@@ -1410,8 +1497,7 @@ omap_status_t omap_engine_step(omap_engine_t engine, int32_t rounds, int32_t* n_
     API_GUARD_BEGIN
     if (!engine || rounds < 0) return fail(OMAP_ERR_INVALID_ARG, "engine is NULL or rounds < 0");
     OK_TRY(engine_admit(engine));
-    if (!engine->resident.empty())
-        for (int32_t i = 0; i < rounds; ++i) OK_TRY(engine->solver.round());
+    if (!engine->resident.empty()) OK_TRY(engine->solver.run_rounds(rounds));
     OK_TRY(engine_retire(engine));
     OK_TRY(engine_admit(engine));
     if (n_resident) *n_resident = (int32_t)engine->resident.size();

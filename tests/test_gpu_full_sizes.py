@@ -1,0 +1,82 @@
+"""Parity at the full workload sizes, in the configuration bench.py times
+(default options, run-time L): the 23170^2 maze, all 512 batched mazes and a
+sample of serving queries.  Activity maps are compared with the oracle's BFS
+closed form (pinned to the literal network by the CPU tests), paths with the
+oracle's walk on that map."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from gpu_helpers import to_dev
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+
+def test_config3_full_size():
+    import torch
+    import paper_2004_00540_amd as omap
+    m = workloads.config3()
+    d, ecc = oracle.bfs(m.occ, m.sources)
+    print(f"config3: ecc {ecc}", flush=True)
+    with omap.Plan(to_dev(m.occ), m.sources, m.targets) as plan:
+        info = plan.propagate()
+        act = plan.activity()
+        ln, off, cells = (t.cpu().numpy() for t in plan.paths())
+        assert info["layers"] == ecc
+        # compare the whole map row band by row band (int32 closed form: ecc + 1 - d)
+        dd = torch.from_numpy(d)
+        for r0 in range(0, m.H, 2048):
+            want = torch.where(dd[r0:r0 + 2048] >= 0, ecc + 1 - dd[r0:r0 + 2048], torch.zeros((), dtype=torch.int32))
+            got = act[r0:r0 + 2048].cpu()
+            assert torch.equal(got, want.to(torch.int32)), f"rows {r0}.."
+        assert info["reached_cells"] == int((d >= 0).sum())
+    del act
+    A = oracle.activity_from_bfs(d, ecc)
+    rl, ro, rc = oracle.walk(A, m.sources, m.targets)
+    assert np.array_equal(ln, rl) and np.array_equal(off, ro) and np.array_equal(cells, rc)
+
+
+def test_config4_all_512_batched():
+    import paper_2004_00540_amd as omap
+    ms = workloads.config4()
+    with omap.Batch([(to_dev(m.occ), m.sources, m.targets) for m in ms]) as b:
+        infos = b.propagate()
+        ln, off, cells = (t.cpu().numpy() for t in b.paths())
+        t0 = 0
+        for i, m in enumerate(ms):
+            d, ecc = oracle.bfs(m.occ, m.sources)
+            assert infos[i]["layers"] == ecc, i
+            if i % 16 == 0:   # full activity maps for every 16th maze
+                act = b.activity(i).cpu().numpy()
+                assert np.array_equal(act, np.where(d >= 0, ecc + 1 - d, 0)), i
+            A = oracle.activity_from_bfs(d, ecc)
+            rl, ro, rc = oracle.walk(A, m.sources, m.targets)
+            n = len(m.targets)
+            assert np.array_equal(ln[t0:t0 + n], rl), i
+            assert np.array_equal(off[t0:t0 + n + 1] - off[t0], ro), i
+            assert np.array_equal(cells[off[t0]:off[t0 + n]], rc), i
+            t0 += n
+
+
+def test_serving_queries_sample():
+    import paper_2004_00540_amd as omap
+    qs = [workloads.serve_query(i) for i in range(6)]
+    with omap.Engine(24 << 30, max_slots=16) as eng:
+        ids = {eng.submit(q.occ, q.sources, q.targets): k for k, q in enumerate(qs)}
+        res = {}
+        n = 0
+        while len(res) < len(qs):
+            eng.step(rounds=8)
+            for qid, k in list(ids.items()):
+                if eng.poll(qid) == omap.QUERY_DONE:
+                    res[k] = eng.fetch(qid)
+                    del ids[qid]
+            n += 1
+            assert n < 1000000
+    for k, q in enumerate(qs):
+        d, ecc = oracle.bfs(q.occ, q.sources)
+        A = oracle.activity_from_bfs(d, ecc)
+        rl, ro, rc = oracle.walk(A, q.sources, q.targets)
+        assert res[k].info["layers"] == ecc
+        assert np.array_equal(res[k].lengths, rl) and np.array_equal(res[k].cells, rc), q.name

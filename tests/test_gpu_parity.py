@@ -138,3 +138,13 @@ def test_config2_full_size():
     assert_same(m, got, oracle_solution(m, -1, closed_form=True), "config2")
     got = run_plan(m, 1000, schedule=1)
     assert_same(m, got, oracle_solution(m, 1000, closed_form=True), "config2 L=1000 dense")
+
+
+@pytest.mark.parametrize("launch", [0, 1])
+def test_launch_modes_identical_bits(launch):
+    for i, (T, C) in enumerate([(16, 2), (16, 4), (8, 2), (32, 2)]):
+        m = workloads.random_maze(400, 700, 0.33, 2 + i, 30, 6060 + i)
+        for sched in (0, 1):
+            for L in (-1, 40):
+                got = run_plan(m, L, temporal_depth=T, lane_columns=C, schedule=sched, round_launch=launch)
+                assert_same(m, got, oracle_solution(m, L), f"launch={launch} T={T} C={C} sched={sched} L={L}")
