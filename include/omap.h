@@ -92,11 +92,19 @@ typedef struct omap_options {
                              /* OMAP_LAUNCH_PERSISTENT: one cooperative launch runs rounds */
                              /* until convergence, separated by a device-wide barrier      */
                              /* (bit-identical results; slower on MI355X, where the        */
-                             /* barrier costs more than a kernel boundary)                 */
+                             /* barrier costs more than a kernel boundary);                */
+                             /* OMAP_LAUNCH_ASYNC: waves take tiles from a work queue and  */
+                             /* update them in place, with no rounds (active schedule      */
+                             /* only; bit-identical results).  The serving engine always   */
+                             /* runs rounds (OMAP_LAUNCH_ASYNC acts as PER_ROUND there)    */
+    int32_t async_budget_us; /* OMAP_LAUNCH_ASYNC: microseconds one launch may spend taking */
+                             /* new tiles before it pauses and the host relaunches it with  */
+                             /* the tiles still queued; 0 = default (50000), else >= 10     */
 } omap_options;
 
 #define OMAP_LAUNCH_PER_ROUND 0
 #define OMAP_LAUNCH_PERSISTENT 1
+#define OMAP_LAUNCH_ASYNC 2
 
 /* The options a plan, batch or engine created with `options` (NULL = all
  * defaults) would run with: every zero field replaced by its default.  Host

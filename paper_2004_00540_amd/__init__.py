@@ -47,7 +47,8 @@ class OmapError(RuntimeError):
 class Options(ctypes.Structure):
     _fields_ = [("temporal_depth", ctypes.c_int32), ("tile_rows", ctypes.c_int32),
                 ("schedule", ctypes.c_int32), ("check_interval", ctypes.c_int32),
-                ("lane_columns", ctypes.c_int32), ("round_launch", ctypes.c_int32)]
+                ("lane_columns", ctypes.c_int32), ("round_launch", ctypes.c_int32),
+                ("async_budget_us", ctypes.c_int32)]
 
 
 class PropagateInfo(ctypes.Structure):
@@ -145,12 +146,13 @@ def _stream(stream=None) -> int:
     return int(stream.cuda_stream) if hasattr(stream, "cuda_stream") else int(stream)
 
 
-LAUNCH_PER_ROUND, LAUNCH_PERSISTENT = 0, 1
+LAUNCH_PER_ROUND, LAUNCH_PERSISTENT, LAUNCH_ASYNC = 0, 1, 2
 
 
 def _options(temporal_depth=0, tile_rows=0, schedule=SCHEDULE_ACTIVE, check_interval=0,
-             lane_columns=0, round_launch=LAUNCH_PER_ROUND):
-    return Options(temporal_depth, tile_rows, schedule, check_interval, lane_columns, round_launch)
+             lane_columns=0, round_launch=LAUNCH_PER_ROUND, async_budget_us=0):
+    return Options(temporal_depth, tile_rows, schedule, check_interval, lane_columns, round_launch,
+                   async_budget_us)
 
 
 def resolve_options(**options) -> dict:

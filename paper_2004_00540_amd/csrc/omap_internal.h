@@ -26,6 +26,22 @@ struct MazeDev {
     const uint32_t* mask;
 };
 
+// Work queue of the asynchronous launch.  A tile id is in the ring at most
+// once at a time (only a tile going from idle to "needs a visit" is pushed),
+// so a ring of at least twice (tile ids + waves) entries never wraps onto an
+// entry that has not been taken.
+struct AsyncQueue {
+    unsigned long long* ring;     // entries: 0 = empty, else (slot << 32) | (tile id + 1)
+    uint32_t ring_mask;           // ring size - 1 (a power of two)
+    uint32_t* head;               // tickets handed to waiting waves
+    uint32_t* tail;               // entries pushed
+    int32_t* state;               // per tile id: bit 0 = needs a visit, bit 1 = being visited
+    int32_t* pending;             // tiles that need or are receiving a visit
+    int32_t* done;                // 1 once pending reached 0
+    int32_t* error;               // nonzero: a ring entry was still occupied (cannot happen by the sizing)
+    unsigned long long budget;    // wall-clock ticks a launch may take on new tiles (then it pauses)
+};
+
 // Arguments of round r of the tile schedule.  The tile lists and their dedup
 // flags alternate by r mod 2; the list counts, the per-maze scheduled counts
 // and the dense schedule's "changed" flags rotate over three buffers by r mod
@@ -35,10 +51,10 @@ struct RoundArgs {
     const MazeDev* mazes;
     const int32_t* tile_maze;     // global tile id -> maze slot (-1 = unused id)
     int32_t n_tile_ids;           // size of the tile id space
-    const int32_t* list_in;       // tiles of round r (active schedule)
+    const int32_t* list_in;       // (tile id, slot) pairs of round r (active schedule)
     const int32_t* count_in;      // their number
     int32_t* flags_in;            // cleared as the tiles of round r are visited
-    int32_t* list_out;            // tiles scheduled for round r+1
+    int32_t* list_out;            // (tile id, slot) pairs scheduled for round r+1
     int32_t* count_out;           // their number (dense: 1 = some tile changed)
     int32_t* flags_out;           // 1 = already scheduled for round r+1
     int32_t* count_clear;         // count of round r+2, zeroed by round r
@@ -58,6 +74,8 @@ struct RoundArgs {
     int32_t tile_rows;            // interior rows per tile
     int32_t tile_cols;            // interior columns per tile (64*C - 2T)
     int32_t dense;                // 1 = dense schedule
+    int32_t async;                // 1 = seeds go to the asynchronous work queue
+    AsyncQueue q;
 };
 
 // Arguments of a persistent launch running rounds r0, r0+1, ... : the
@@ -95,9 +113,17 @@ hipError_t launch_sweep_persistent(int T, int C, const PersistentArgs& p, int32_
 int sweep_persistent_blocks_per_cu(int T, int C);
 // Clears slot's counters before its seeds (last round = r-1; dense: marks the
 // maze for a visit in the round about to run through a.dchg_prev).
+// Asynchronous launch: waves take tiles from a.q until no tile needs a visit
+// (*a.q.done = 1) or the time budget is spent (tiles still queued stay in the
+// ring; launch_queue_compact then moves them to the ring's start).
+hipError_t launch_sweep_async(int T, int C, const RoundArgs& a, int32_t grid, hipStream_t s);
+hipError_t launch_queue_compact(const AsyncQueue& q, unsigned long long* tmp, uint32_t* tmp_count, hipStream_t s);
+int sweep_async_waves_per_cu(int T, int C);
 hipError_t launch_slot_reset(const RoundArgs& a, int32_t slot, hipStream_t s);
-hipError_t launch_reduce(const MazeDev* mazes, const int32_t* tile_maze, int32_t tile_begin,
-                         int32_t tile_end, const int32_t* slot_select, int32_t tile_rows,
+// Smallest positive activity and reached count of the touched tiles in
+// [tile_begin, tile_end) of the selected slots.
+hipError_t launch_reduce(const MazeDev* mazes, const int32_t* tile_maze, const uint8_t* touched,
+                         int32_t tile_begin, int32_t tile_end, const int32_t* slot_select, int32_t tile_rows,
                          int32_t tile_cols, int32_t parity, int32_t* maze_min,
                          unsigned long long* maze_reached, hipStream_t s);
 hipError_t launch_path_lengths(const MazeDev* mazes, const int32_t* tgt_slot, const int32_t* tgt_rc,

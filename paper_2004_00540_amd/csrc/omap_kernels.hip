@@ -100,14 +100,51 @@ __device__ __forceinline__ int64_t tile_cells(const MazeDev& md, int ty, int tx,
 }
 
 // Append tile (ty, tx) of `slot` to a.list_out unless it is already there
-// (flag exchange) and count it in the slot's scheduled tiles.
+// (flag exchange) and count it in the slot's scheduled tiles.  One lane.
 __device__ __forceinline__ void schedule_tile(const RoundArgs& a, const MazeDev& md, int slot, int ty,
                                               int tx) {
     const int g = md.tile_base + ty * md.tiles_x + tx;
     if (atomicExch(&a.flags_out[g], 1) == 0) {
-        a.list_out[atomicAdd(a.count_out, 1)] = g;
+        const int k = atomicAdd(a.count_out, 1);
+        a.list_out[2 * k] = g;
+        a.list_out[2 * k + 1] = slot;
         atomicAdd(&a.sched_out[slot], 1);
     }
+}
+
+// The same for the 3x3 tiles around (ty, tx), from a whole wave: lanes 0..8
+// claim one tile each, then a single atomic reserves the list entries of all
+// the lanes that won their claim.
+__device__ __forceinline__ void schedule_neighbourhood(const RoundArgs& a, const MazeDev& md, int slot,
+                                                       int ty, int tx) {
+    const int lane = lane_id();
+    const int ny = ty + lane / 3 - 1, nx = tx + lane % 3 - 1;
+    const int g = md.tile_base + ny * md.tiles_x + nx;
+    bool won = false;
+    if (lane < 9 && ny >= 0 && ny < md.tiles_y && nx >= 0 && nx < md.tiles_x)
+        won = atomicExch(&a.flags_out[g], 1) == 0;
+    const uint64_t mask = __ballot(won);
+    if (mask == 0) return;
+    const int n = __popcll(mask);
+    int base = 0;
+    if (lane == 0) {
+        base = atomicAdd(a.count_out, n);
+        atomicAdd(&a.sched_out[slot], n);
+    }
+    base = __builtin_amdgcn_readfirstlane(base);
+    if (won) {
+        const int k = base + __popcll(mask & ((1ull << lane) - 1));
+        a.list_out[2 * k] = g;
+        a.list_out[2 * k + 1] = slot;
+    }
+}
+
+// Pushes one tile, already counted as pending, onto the asynchronous work
+// queue (see k_sweep_async).  One lane.
+__device__ __forceinline__ void queue_push(const AsyncQueue& q, int g, int slot) {
+    const uint32_t k = atomicAdd(q.tail, 1u);
+    const unsigned long long e = ((unsigned long long)(uint32_t)slot << 32) | (uint32_t)(g + 1);
+    if (atomicCAS(q.ring + (k & q.ring_mask), 0ull, e) != 0ull) atomicAdd(q.error, 1);
 }
 
 // Seed V := K at the sources (both buffers) and, when `schedule` is set,
@@ -126,12 +163,19 @@ __global__ void k_seed(RoundArgs a, int32_t slot, const int32_t* __restrict__ sr
     const int64_t x = (int64_t)r * md.pitch + c;
     md.V[0][x] = md.K;
     md.V[1][x] = md.K;
-    if (!schedule) return;
     const int ty = r / a.tile_rows, tx = c / a.tile_cols;
+    a.touched[md.tile_base + ty * md.tiles_x + tx] = 1;
+    if (!schedule) return;
     for (int dy = -1; dy <= 1; ++dy)
         for (int dx = -1; dx <= 1; ++dx) {
             const int ny = ty + dy, nx = tx + dx;
-            if (ny >= 0 && ny < md.tiles_y && nx >= 0 && nx < md.tiles_x) schedule_tile(a, md, slot, ny, nx);
+            if (ny < 0 || ny >= md.tiles_y || nx < 0 || nx >= md.tiles_x) continue;
+            if (a.async) {
+                const int g = md.tile_base + ny * md.tiles_x + nx;
+                if (atomicOr(&a.q.state[g], 1) == 0 && atomicAdd(a.q.pending, 1) >= 0) queue_push(a.q, g, slot);
+            } else {
+                schedule_tile(a, md, slot, ny, nx);
+            }
         }
 }
 
@@ -204,7 +248,7 @@ __device__ __forceinline__ void gstore(int32_t* p, typename LaneVec<C>::type v) 
 // address (the loads are unconditional, so they can stay in flight); the decode
 // in sweep_iter turns them into obstacles.
 template <int C>
-__device__ __forceinline__ void load_row(const MazeDev& md, const int32_t* __restrict__ Vin, int R,
+__device__ __forceinline__ void load_row(const MazeDev& md, const int32_t* Vin, int R,
                                          int col, bool col_ok, typename LaneVec<C>::type& v,
                                          uint32_t& w) {
     const int Rc = min(max(R, 0), md.H - 1);
@@ -220,8 +264,7 @@ __device__ __forceinline__ void load_row(const MazeDev& md, const int32_t* __res
 template <int T, int P, int C>
 __device__ __forceinline__ void sweep_iter(uint32_t (&st)[T][3][C], typename LaneVec<C>::type& v,
                                            uint32_t& w, const MazeDev& md,
-                                           const int32_t* __restrict__ Vin,
-                                           int32_t* __restrict__ Vout, int R, int r0, int r_end,
+                                           const int32_t* Vin, int32_t* Vout, int R, int r0, int r_end,
                                            int col, bool col_ok, bool inner,
                                            uint64_t& sum_in, uint64_t& sum_out) {
     const bool ok = R >= 0 && R < md.H && col_ok;
@@ -255,7 +298,10 @@ __device__ __forceinline__ void sweep_iter(uint32_t (&st)[T][3][C], typename Lan
 
 // Returns true (wave-uniform) if any interior cell of the tile changed.  The
 // wave streams the strip of 64*C columns starting T columns left of the tile.
-template <int T, int C>
+// In place (IN_PLACE) the tile reads and writes buffer `parity`: a row is
+// stored only after it and the T rows below it were loaded, so the visit never
+// reads its own output.
+template <int T, int C, bool IN_PLACE = false>
 __device__ bool sweep_tile(const MazeDev& md, int ty, int tx, int tile_rows, int parity) {
     constexpr int TW = kLanes * C - 2 * T;
     constexpr int HALO_LANES = T / C;
@@ -265,8 +311,8 @@ __device__ bool sweep_tile(const MazeDev& md, int ty, int tx, int tile_rows, int
     const int col = tx * TW - T + C * lane;
     const bool col_ok = col >= 0 && col < md.pitch;
     const bool inner = lane >= HALO_LANES && lane < kLanes - HALO_LANES && col < md.W;
-    const int32_t* __restrict__ Vin = parity ? md.V[1] : md.V[0];
-    int32_t* __restrict__ Vout = parity ? md.V[0] : md.V[1];
+    int32_t* const Vin = parity ? md.V[1] : md.V[0];
+    int32_t* const Vout = IN_PLACE ? Vin : (parity ? md.V[0] : md.V[1]);
 
     uint32_t st[T][3][C];
 #pragma unroll
@@ -309,6 +355,11 @@ __device__ __forceinline__ int32_t load_shared(const int32_t* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// The same for an 8-byte-aligned pair of int32 (low word first).
+__device__ __forceinline__ uint64_t load_shared64(const int32_t* p) {
+    return __hip_atomic_load(reinterpret_cast<const uint64_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Round r: every scheduled tile gets T layers.  Active schedule: the tiles of
 // a.list_in; a changed tile schedules itself and its 8 neighbour tiles for
 // round r+1.  Dense schedule: every tile of each maze that changed in round
@@ -325,18 +376,23 @@ __device__ __forceinline__ void sweep_round(const RoundArgs& a) {
             a.dchg_clear[m] = 0;
         }
     }
-    const int n = a.dense ? a.n_tile_ids : __builtin_amdgcn_readfirstlane(load_shared(a.count_in));
     const int stride = gridDim.x * kWavesPerBlock;
-    for (int i = blockIdx.x * kWavesPerBlock + wave; i < n; i += stride) {
+    int i = blockIdx.x * kWavesPerBlock + wave;
+    // the count and the first list entry are loaded together (the entry is in
+    // bounds for any i below the tile id space, and used only if i < n)
+    const int n = a.dense ? a.n_tile_ids : __builtin_amdgcn_readfirstlane(load_shared(a.count_in));
+    uint64_t e = (!a.dense && i < a.n_tile_ids) ? load_shared64(a.list_in + 2 * i) : 0;
+    for (; i < n; i += stride) {
         int g, slot;
         if (a.dense) {
             g = i;
             slot = a.tile_maze[g];
             if (slot < 0 || __builtin_amdgcn_readfirstlane(load_shared(a.dchg_prev + slot)) == 0) continue;
         } else {
-            g = __builtin_amdgcn_readfirstlane(load_shared(a.list_in + i));
+            g = __builtin_amdgcn_readfirstlane((int)(uint32_t)e);
+            slot = __builtin_amdgcn_readfirstlane((int)(uint32_t)(e >> 32));
+            if (i + stride < n) e = load_shared64(a.list_in + 2 * (i + stride));
             if (lane == 0) a.flags_in[g] = 0;
-            slot = a.tile_maze[g];
         }
         const MazeDev md = a.mazes[slot];
         const int lt = g - md.tile_base;
@@ -357,10 +413,8 @@ __device__ __forceinline__ void sweep_round(const RoundArgs& a) {
                     a.dchg_cur[slot] = 1;
                     *a.count_out = 1;
                 }
-            } else if (lane < 9) {
-                const int ny = ty + lane / 3 - 1, nx = tx + lane % 3 - 1;
-                if (ny >= 0 && ny < md.tiles_y && nx >= 0 && nx < md.tiles_x)
-                    schedule_tile(a, md, slot, ny, nx);
+            } else {
+                schedule_neighbourhood(a, md, slot, ty, tx);
             }
         }
     }
@@ -429,6 +483,139 @@ __global__ __launch_bounds__(kBlockThreads) void k_sweep_persistent(PersistentAr
     if (blockIdx.x == 0 && threadIdx.x == 0) *p.rounds_done = k;
 }
 
+// ---------------------------------------------------------------------------
+// asynchronous launch: a work queue instead of rounds
+// ---------------------------------------------------------------------------
+//
+// Tiles are visited in place, in any order, by waves that take them from a
+// ring of (slot, tile) entries.  A tile whose visit changed its interior marks
+// itself and its 8 neighbour tiles as needing a visit: an idle tile is pushed,
+// a tile being visited is flagged and pushed again when its visit ends (the
+// values that visit read may predate the change).  Because the update is
+// monotone and bounded by its fixpoint, values read while a neighbour is being
+// written are lower bounds, every visit only raises values, and the launch
+// reaches the same fixpoint bits as the round schedules once no tile needs a
+// visit.  Agent-scope release / acquire fences order a tile's stores before
+// the marks it makes and a visit's loads after the mark that queued it.
+
+// Marks `slot`'s tiles around (ty, tx) (lanes 0..8, one tile each); idle tiles
+// are counted as pending and pushed with one reservation for the whole wave.
+__device__ __forceinline__ void queue_mark_neighbourhood(const AsyncQueue& q, const MazeDev& md, int slot,
+                                                         int ty, int tx) {
+    const int lane = lane_id();
+    const int ny = ty + lane / 3 - 1, nx = tx + lane % 3 - 1;
+    const int g = md.tile_base + ny * md.tiles_x + nx;
+    bool won = false;
+    if (lane < 9 && ny >= 0 && ny < md.tiles_y && nx >= 0 && nx < md.tiles_x)
+        won = atomicOr(&q.state[g], 1) == 0;
+    const uint64_t mask = __ballot(won);
+    if (mask == 0) return;
+    const int n = __popcll(mask);
+    uint32_t base = 0;
+    if (lane == 0) {
+        // pending is raised before the entries can be taken: the second
+        // atomic's operand depends on the first one's result (p >= 0 always)
+        const int p = atomicAdd(q.pending, n);
+        base = atomicAdd(q.tail, (uint32_t)n + (uint32_t)(p < 0));
+    }
+    base = __builtin_amdgcn_readfirstlane(base);
+    if (won) {
+        const uint32_t k = base + (uint32_t)__popcll(mask & ((1ull << lane) - 1));
+        const unsigned long long e = ((unsigned long long)(uint32_t)slot << 32) | (uint32_t)(g + 1);
+        if (atomicCAS(q.ring + (k & q.ring_mask), 0ull, e) != 0ull) atomicAdd(q.error, 1);
+    }
+}
+
+template <int T, int C>
+__global__ __launch_bounds__(kBlockThreads) void k_sweep_async(RoundArgs a) {
+    const AsyncQueue& q = a.q;
+    const int lane = lane_id();
+    const unsigned long long t0 = wall_clock64();
+    for (;;) {
+        if (wall_clock64() - t0 > q.budget) break;          // pause: the host relaunches
+        uint32_t ticket = 0;
+        if (lane == 0) ticket = atomicAdd(q.head, 1u);
+        ticket = __builtin_amdgcn_readfirstlane(ticket);
+        unsigned long long* ep = q.ring + (ticket & q.ring_mask);
+        unsigned long long e = 0;
+        for (int poll = 0;; ++poll) {
+            e = __hip_atomic_load(ep, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            e = ((unsigned long long)__builtin_amdgcn_readfirstlane((uint32_t)(e >> 32)) << 32) |
+                __builtin_amdgcn_readfirstlane((uint32_t)e);
+            if (e != 0) break;
+            if ((poll & 7) == 7 && (__builtin_amdgcn_readfirstlane(load_shared(q.done)) != 0 ||
+                                    wall_clock64() - t0 > q.budget))
+                break;
+            __builtin_amdgcn_s_sleep(32);
+        }
+        if (e == 0) break;   // converged, or paused with this ticket unfilled
+        const int g = (int)(uint32_t)e - 1;
+        const int slot = (int)(e >> 32);
+        if (lane == 0) {
+            __hip_atomic_store(ep, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            atomicExch(&q.state[g], 2);                      // being visited; clears "needs a visit"
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        const MazeDev md = a.mazes[slot];
+        const int lt = g - md.tile_base;
+        const int ty = lt / md.tiles_x;
+        const int tx = lt - ty * md.tiles_x;
+        if (lane == 0) {
+            const unsigned long long cells =
+                (unsigned long long)tile_cells(md, ty, tx, a.tile_rows, a.tile_cols);
+            atomicAdd(reinterpret_cast<unsigned long long*>(&a.maze_visits[slot]), 1ull);
+            atomicAdd(reinterpret_cast<unsigned long long*>(&a.maze_cell_visits[slot]), cells);
+            atomicAdd(a.total_cells, cells);
+            a.touched[g] = 1;
+        }
+        if (sweep_tile<T, C, true>(md, ty, tx, a.tile_rows, a.parity)) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            queue_mark_neighbourhood(q, md, slot, ty, tx);
+        }
+        if (lane == 0) {
+            const int old = atomicCAS(&q.state[g], 2, 0);
+            if (old == 2) {
+                if (atomicSub(q.pending, 1) == 1) __hip_atomic_store(q.done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            } else {
+                // marked while being visited: needs another visit (still pending)
+                atomicExch(&q.state[g], 1);
+                queue_push(q, g, slot);
+            }
+        }
+    }
+}
+
+// After a paused launch: moves the entries still in the ring (in ring order)
+// to a temporary array; the host copies them back to the ring's start and
+// sets head = 0, tail = count.  One block.
+__global__ __launch_bounds__(1024) void k_queue_gather(AsyncQueue q, unsigned long long* __restrict__ tmp,
+                                                       uint32_t* __restrict__ count) {
+    __shared__ uint32_t wsum[16];
+    __shared__ uint32_t base_s;
+    if (threadIdx.x == 0) base_s = 0;
+    __syncthreads();
+    const uint32_t n = q.ring_mask + 1;
+    for (uint32_t i0 = 0; i0 < n; i0 += 1024) {
+        const uint32_t i = i0 + threadIdx.x;
+        const unsigned long long e = i < n ? q.ring[i] : 0ull;
+        const uint64_t m = __ballot(e != 0);
+        const int w = threadIdx.x >> 6;
+        if (lane_id() == 0) wsum[w] = (uint32_t)__popcll(m);
+        __syncthreads();
+        uint32_t before = base_s;
+        for (int k = 0; k < w; ++k) before += wsum[k];
+        if (e != 0) {
+            tmp[before + (uint32_t)__popcll(m & ((1ull << lane_id()) - 1))] = e;
+            q.ring[i] = 0ull;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0)
+            for (int k = 0; k < 16; ++k) base_s += wsum[k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *count = base_s;
+}
+
 // One wave per tile of `slot`: zero the interior of touched tiles in both
 // activity buffers (everything else is still 0 from the last full clear).
 __global__ __launch_bounds__(kBlockThreads) void k_clear_touched(RoundArgs a, int32_t slot,
@@ -456,13 +643,15 @@ __global__ __launch_bounds__(kBlockThreads) void k_clear_touched(RoundArgs a, in
 
 __global__ __launch_bounds__(256) void k_reduce(const MazeDev* __restrict__ mazes,
                                                 const int32_t* __restrict__ tile_maze,
+                                                const uint8_t* __restrict__ touched,
                                                 int32_t tile_begin, const int32_t* __restrict__ sel,
                                                 int32_t tile_rows, int32_t tile_cols, int32_t parity,
                                                 int32_t* __restrict__ maze_min,
                                                 unsigned long long* __restrict__ maze_reached) {
     const int g = tile_begin + blockIdx.x;
     const int slot = tile_maze[g];
-    if (slot < 0 || (sel != nullptr && sel[slot] == 0)) return;
+    // tiles never written since the last clear hold only zeros
+    if (slot < 0 || (sel != nullptr && sel[slot] == 0) || !touched[g]) return;
     const MazeDev md = mazes[slot];
     const int lt = g - md.tile_base;
     const int ty = lt / md.tiles_x, tx = lt - ty * md.tiles_x;
@@ -542,104 +731,91 @@ __global__ __launch_bounds__(1024) void k_scan(const int32_t* __restrict__ len, 
     }
 }
 
-// The walk is bound by dependent-load latency, so each lane loads the 7x7
-// window around its current cell once and resolves up to three steps from
-// registers: after each step the window is re-centred (5x5, then 3x3) by
-// selects, with no dynamic register indexing.  Window cells outside the grid
-// read as -1, below every in-grid value.
-constexpr int kWalkSteps = 3;
-constexpr int kWalkWin = 2 * kWalkSteps + 1;
-
-// Index (0..7, fixed order) of the first maximal 8-neighbour of the window centre.
-template <int N>
-__device__ __forceinline__ int first_max_neighbour(const int (&w)[N][N]) {
-    constexpr int m = N / 2;
-    const int nv[8] = {w[m - 1][m - 1], w[m - 1][m], w[m - 1][m + 1], w[m][m - 1],
-                       w[m][m + 1],     w[m + 1][m - 1], w[m + 1][m], w[m + 1][m + 1]};
-    int best = 0, bv = nv[0];
-#pragma unroll
-    for (int k = 1; k < 8; ++k)
-        if (nv[k] > bv) {
-            bv = nv[k];
-            best = k;
-        }
-    return best;
-}
-
 __device__ __forceinline__ int dir_dr(int k) { return k < 3 ? -1 : (k < 5 ? 0 : 1); }
 __device__ __forceinline__ int dir_dc(int k) {
     return (k == 0 || k == 3 || k == 5) ? -1 : ((k == 1 || k == 6) ? 0 : 1);
 }
 
-// Window of size N-2 centred on the neighbour (dr, dc) of the centre of w.
-// The choice between the three candidate cells is a mask blend rather than a
-// conditional expression, which keeps the windows in registers (a select
-// between two array elements would become a load from a selected address).
-template <int N>
-__device__ __forceinline__ void recentre(const int (&w)[N][N], int dr, int dc, int (&o)[N - 2][N - 2]) {
-    const int rm = -(int)(dr < 0), r0 = -(int)(dr == 0), rp = -(int)(dr > 0);
-    const int cm = -(int)(dc < 0), c0 = -(int)(dc == 0), cp = -(int)(dc > 0);
-    int t[N - 2][N];
-#pragma unroll
-    for (int i = 0; i < N - 2; ++i)
-#pragma unroll
-        for (int j = 0; j < N; ++j) t[i][j] = (w[i][j] & rm) | (w[i + 1][j] & r0) | (w[i + 2][j] & rp);
-#pragma unroll
-    for (int i = 0; i < N - 2; ++i)
-#pragma unroll
-        for (int j = 0; j < N - 2; ++j) o[i][j] = (t[i][j] & cm) | (t[i][j + 1] & c0) | (t[i][j + 2] & cp);
-}
+// The walk is a chain of dependent loads, one step after the other, so its
+// time is the longest path times the latency of one step.  One wave follows
+// one target: it loads a kWinRows x kWinCols window of the activity around the
+// current cell into LDS with wide coalesced loads (one global round trip) and
+// then takes up to kWinSteps steps from LDS, where a step costs a few LDS
+// reads.  Window cells outside the grid read as -1, below every in-grid value.
+constexpr int kWinRows = 32;
+constexpr int kWinCols = 48;                   // 12 chunks of 4 columns
+constexpr int kWinSteps = 15;                  // the window reaches >= 15 cells from its start in every direction
+constexpr int kWinChunks = kWinRows * kWinCols / 4;
+constexpr int kWalkWaves = 4;
 
-__global__ void k_walk(const MazeDev* __restrict__ mazes, const int32_t* __restrict__ tslot,
-                       const int32_t* __restrict__ trc, int32_t n, int32_t parity,
-                       const int32_t* __restrict__ len, const int64_t* __restrict__ off,
-                       int32_t* __restrict__ cells) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(kLanes * kWalkWaves) void k_walk(
+    const MazeDev* __restrict__ mazes, const int32_t* __restrict__ tslot, const int32_t* __restrict__ trc,
+    int32_t n, int32_t parity, const int32_t* __restrict__ len, const int64_t* __restrict__ off,
+    int32_t* __restrict__ cells) {
+    __shared__ __attribute__((aligned(16))) int32_t win_all[kWalkWaves][kWinRows * kWinCols];
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = lane_id();
+    const int i = blockIdx.x * kWalkWaves + wave;
     if (i >= n) return;
-    const int steps = len[i];
+    const int steps = __builtin_amdgcn_readfirstlane(len[i]);
     if (steps < 0) return;
-    const MazeDev md = mazes[tslot[i]];
+    const int slot = __builtin_amdgcn_readfirstlane(tslot[i]);
+    const MazeDev md = mazes[slot];
     const int32_t* __restrict__ V = parity ? md.V[1] : md.V[0];
-    int r = trc[2 * i], c = trc[2 * i + 1];
+    int32_t* win = win_all[wave];
+    int r = __builtin_amdgcn_readfirstlane(trc[2 * i]);
+    int c = __builtin_amdgcn_readfirstlane(trc[2 * i + 1]);
     int64_t o = off[i];
-    cells[o++] = r * md.W + c;
-    int s = 0;
-    while (s < steps) {
-        int w7[kWalkWin][kWalkWin];
+    if (lane == 0) cells[o] = r * md.W + c;
+    ++o;
+    for (int s = 0; s < steps;) {
+        // window rows r-15 .. r+16, columns C0 .. C0+47 with C0 = 4*floor((c-16)/4)
+        const int R0 = r - (kWinSteps), C0 = (c - 16) & ~3;
 #pragma unroll
-        for (int a = 0; a < kWalkWin; ++a) {
-            const int rr = r - kWalkSteps + a;
-            const int rc = min(max(rr, 0), md.H - 1);
-            const int32_t* row = V + (int64_t)rc * md.pitch;
+        for (int k = 0; k < kWinChunks / kLanes; ++k) {
+            const int q = lane + kLanes * k;
+            const int wr = q / (kWinCols / 4), wc = 4 * (q % (kWinCols / 4));
+            const int R = R0 + wr, cs = C0 + wc;
+            const bool rok = R >= 0 && R < md.H;
+            const bool cok = cs >= 0 && cs < md.pitch;   // a chunk lies wholly inside or outside a row
+            const v4i32 v = *(const __attribute__((address_space(1))) v4i32*)(
+                V + (int64_t)(rok ? R : 0) * md.pitch + (cok ? cs : 0));
+            v4i32 m;
 #pragma unroll
-            for (int b = 0; b < kWalkWin; ++b) {
-                const int cc = c - kWalkSteps + b;
-                const int v = row[min(max(cc, 0), md.W - 1)];
-                w7[a][b] = (rr >= 0 && rr < md.H && cc >= 0 && cc < md.W) ? v : -1;
-            }
+            for (int e = 0; e < 4; ++e) m[e] = (rok && cs + e >= 0 && cs + e < md.W) ? v[e] : -1;
+            *(__attribute__((address_space(3))) v4i32*)(win + wr * kWinCols + wc) = m;
         }
-        int k = first_max_neighbour<7>(w7);
-        int dr = dir_dr(k), dc = dir_dc(k);
-        r += dr;
-        c += dc;
-        cells[o++] = r * md.W + c;
-        if (++s >= steps) break;
-        int w5[5][5];
-        recentre<7>(w7, dr, dc, w5);
-        k = first_max_neighbour<5>(w5);
-        dr = dir_dr(k);
-        dc = dir_dc(k);
-        r += dr;
-        c += dc;
-        cells[o++] = r * md.W + c;
-        if (++s >= steps) break;
-        int w3[3][3];
-        recentre<5>(w5, dr, dc, w3);
-        k = first_max_neighbour<3>(w3);
-        r += dir_dr(k);
-        c += dir_dc(k);
-        cells[o++] = r * md.W + c;
-        ++s;
+        // the same wave reads what its lanes wrote: LDS operations of a wave
+        // complete in order; the wave barrier keeps the compiler from moving
+        // the reads above the writes
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        int lr = r - R0, lc = c - C0;
+        const int todo = min(kWinSteps, steps - s);
+        for (int k = 0; k < todo; ++k) {
+            const int32_t* b = win + (lr - 1) * kWinCols + (lc - 1);
+            const int nv[8] = {b[0], b[1], b[2], b[kWinCols], b[kWinCols + 2],
+                               b[2 * kWinCols], b[2 * kWinCols + 1], b[2 * kWinCols + 2]};
+            int best = 0, bv = nv[0];
+#pragma unroll
+            for (int j = 1; j < 8; ++j)
+                if (nv[j] > bv) {
+                    bv = nv[j];
+                    best = j;
+                }
+            lr += dir_dr(best);
+            lc += dir_dc(best);
+            if (lane == 0) cells[o] = (R0 + lr) * md.W + (C0 + lc);
+            ++o;
+        }
+        s += todo;
+        r = R0 + lr;
+        c = C0 + lc;
+        // the next window overwrites this one only after every lane's reads
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
 }
 
@@ -927,12 +1103,12 @@ hipError_t launch_sweep(int T, int C, const RoundArgs& a, int32_t grid, hipStrea
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_reduce(const MazeDev* mazes, const int32_t* tile_maze, int32_t tile_begin,
-                         int32_t tile_end, const int32_t* slot_select, int32_t tile_rows,
+hipError_t launch_reduce(const MazeDev* mazes, const int32_t* tile_maze, const uint8_t* touched,
+                         int32_t tile_begin, int32_t tile_end, const int32_t* slot_select, int32_t tile_rows,
                          int32_t tile_cols, int32_t parity, int32_t* maze_min,
                          unsigned long long* maze_reached, hipStream_t s) {
     if (tile_end <= tile_begin) return hipSuccess;
-    hipLaunchKernelGGL(k_reduce, dim3(tile_end - tile_begin), dim3(256), 0, s, mazes, tile_maze,
+    hipLaunchKernelGGL(k_reduce, dim3(tile_end - tile_begin), dim3(256), 0, s, mazes, tile_maze, touched,
                        tile_begin, slot_select, tile_rows, tile_cols, parity, maze_min,
                        maze_reached);
     return hipGetLastError();
@@ -955,8 +1131,8 @@ hipError_t launch_walk(const MazeDev* mazes, const int32_t* tgt_slot, const int3
                        int32_t n_tgt, int32_t parity, const int32_t* len, const int64_t* offsets,
                        int32_t* cells, hipStream_t s) {
     if (n_tgt <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_walk, dim3(grid_for(n_tgt, 64)), dim3(64), 0, s, mazes, tgt_slot, tgt_rc,
-                       n_tgt, parity, len, offsets, cells);
+    hipLaunchKernelGGL(k_walk, dim3((n_tgt + kWalkWaves - 1) / kWalkWaves), dim3(kLanes * kWalkWaves), 0, s,
+                       mazes, tgt_slot, tgt_rc, n_tgt, parity, len, offsets, cells);
     return hipGetLastError();
 }
 
@@ -1012,6 +1188,34 @@ hipError_t launch_clear_touched(const RoundArgs& a, int32_t slot, int32_t n_tile
 hipError_t launch_selftest(int32_t* out, hipStream_t s) {
     hipLaunchKernelGGL(k_selftest, dim3(1), dim3(64), 0, s, out);
     return hipGetLastError();
+}
+
+hipError_t launch_sweep_async(int T, int C, const RoundArgs& a, int32_t grid, hipStream_t s) {
+#define X(t, c)                                                                                   \
+    if (T == t && C == c) {                                                                       \
+        hipLaunchKernelGGL((k_sweep_async<t, c>), dim3(grid), dim3(kBlockThreads), 0, s, a);     \
+        return hipGetLastError();                                                                 \
+    }
+    OMAP_SWEEP_VARIANTS(X)
+#undef X
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_queue_compact(const AsyncQueue& q, unsigned long long* tmp, uint32_t* tmp_count, hipStream_t s) {
+    hipLaunchKernelGGL(k_queue_gather, dim3(1), dim3(1024), 0, s, q, tmp, tmp_count);
+    return hipGetLastError();
+}
+
+int sweep_async_waves_per_cu(int T, int C) {
+    int blocks = 0;
+    hipError_t e = hipErrorInvalidValue;
+#define X(t, c)                                                                                  \
+    if (T == t && C == c)                                                                        \
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_sweep_async<t, c>, kBlockThreads, 0);
+    OMAP_SWEEP_VARIANTS(X)
+#undef X
+    if (e != hipSuccess || blocks < 1) blocks = 1;
+    return blocks * kWavesPerBlock;
 }
 
 int sweep_max_waves_per_cu(int T, int C) {

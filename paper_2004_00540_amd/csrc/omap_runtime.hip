@@ -69,6 +69,8 @@ struct Options {
     int dense = 0;
     int check = 0;       // 0 = adaptive
     int per_round = 1;   // 0 = one persistent launch instead of one launch per round
+    int async = 0;       // 1 = asynchronous work-queue launch (active schedule only)
+    int budget_us = 50000;   // asynchronous launch: time taking new tiles per launch
 };
 
 // Defaults (measured on MI355X): the active schedule is latency-bound (few
@@ -99,10 +101,19 @@ static omap_status_t resolve_options(const omap_options* o, Options* out) {
         r.dense = dense;
         if (o->check_interval < 0) return fail(OMAP_ERR_INVALID_ARG, "check_interval < 0");
         r.check = o->check_interval;
-        if (o->round_launch != OMAP_LAUNCH_PERSISTENT && o->round_launch != OMAP_LAUNCH_PER_ROUND)
-            return fail(OMAP_ERR_INVALID_ARG, "round_launch must be PERSISTENT or PER_ROUND (got %d)",
+        if (o->round_launch != OMAP_LAUNCH_PERSISTENT && o->round_launch != OMAP_LAUNCH_PER_ROUND &&
+            o->round_launch != OMAP_LAUNCH_ASYNC)
+            return fail(OMAP_ERR_INVALID_ARG, "round_launch must be PER_ROUND, PERSISTENT or ASYNC (got %d)",
                         o->round_launch);
-        r.per_round = o->round_launch == OMAP_LAUNCH_PER_ROUND;
+        if (o->round_launch == OMAP_LAUNCH_ASYNC && dense)
+            return fail(OMAP_ERR_INVALID_ARG, "the asynchronous launch needs the active schedule");
+        r.per_round = o->round_launch != OMAP_LAUNCH_PERSISTENT;
+        r.async = o->round_launch == OMAP_LAUNCH_ASYNC;
+        if (o->async_budget_us != 0) {
+            if (o->async_budget_us < 10)
+                return fail(OMAP_ERR_INVALID_ARG, "async_budget_us must be 0 or >= 10 (got %d)", o->async_budget_us);
+            r.budget_us = o->async_budget_us;
+        }
     }
     if (!sweep_supported(r.T, r.C))
         return fail(OMAP_ERR_INVALID_ARG,
@@ -290,7 +301,7 @@ class Solver {
 
     MazeDev* d_mazes = nullptr;
     int32_t* d_tile_maze = nullptr;
-    int32_t* d_list[2] = {nullptr, nullptr};
+    int32_t* d_list[2] = {nullptr, nullptr};  // scheduled (tile id, slot) pairs by round mod 2
     int32_t* d_count = nullptr;               // [3] list counts by round mod 3
     int32_t* d_flags[2] = {nullptr, nullptr};
     int32_t* d_sched = nullptr;               // [3][cap_slots] scheduled tiles by round mod 3
@@ -300,6 +311,12 @@ class Solver {
     unsigned int* d_bar = nullptr;            // [2] grid barrier of the persistent launch
     int32_t* d_rounds_done = nullptr;
     int pgrid = 0;                            // blocks of the persistent launch (0 = unavailable)
+    // asynchronous launch: work queue (allocated only in that mode)
+    AsyncQueue q{};
+    uint32_t* d_qctl = nullptr;               // head, tail, pending, done, error, gathered count
+    unsigned long long* d_qtmp = nullptr;     // compaction buffer (ring size)
+    int agrid = 0;                            // blocks of an asynchronous launch
+    unsigned long long wall_khz = 0;          // device wall-clock rate
     int64_t *d_visits = nullptr, *d_cell_visits = nullptr;
     unsigned long long* d_total_cells = nullptr;
     int32_t* d_bad_slot = nullptr;            // per slot: sources found on obstacles
@@ -369,8 +386,8 @@ class Solver {
         free_tiles[0] = cap_tiles;
         OK_TRY(dalloc(&d_mazes, cap_slots));
         OK_TRY(dalloc(&d_tile_maze, cap_tiles));
-        OK_TRY(dalloc(&d_list[0], cap_tiles));
-        OK_TRY(dalloc(&d_list[1], cap_tiles));
+        OK_TRY(dalloc(&d_list[0], 2 * (size_t)cap_tiles));   // (tile id, slot) pairs
+        OK_TRY(dalloc(&d_list[1], 2 * (size_t)cap_tiles));
         OK_TRY(dalloc(&d_count, 3));
         OK_TRY(dalloc(&d_flags[0], cap_tiles));
         OK_TRY(dalloc(&d_flags[1], cap_tiles));
@@ -417,6 +434,29 @@ class Solver {
         HIP_TRY(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
         const int per_cu = sweep_persistent_blocks_per_cu(opt.T, opt.C);
         pgrid = (coop && per_cu > 0) ? std::max(1, std::min(cus * per_cu, need)) : 0;
+        if (opt.async) {
+            const int64_t waves = (int64_t)cus * std::min(8, sweep_async_waves_per_cu(opt.T, opt.C));
+            uint64_t ring = 1024;
+            while (ring < 2 * ((uint64_t)cap_tiles + (uint64_t)waves)) ring <<= 1;
+            OK_TRY(dalloc(&q.ring, ring));
+            OK_TRY(dalloc(&d_qtmp, ring));
+            OK_TRY(dalloc(&q.state, cap_tiles));
+            OK_TRY(dalloc(&d_qctl, 8));
+            q.ring_mask = (uint32_t)(ring - 1);
+            q.head = d_qctl;
+            q.tail = d_qctl + 1;
+            q.pending = reinterpret_cast<int32_t*>(d_qctl + 2);
+            q.done = reinterpret_cast<int32_t*>(d_qctl + 3);
+            q.error = reinterpret_cast<int32_t*>(d_qctl + 4);
+            HIP_TRY(hipMemsetAsync(q.ring, 0, sizeof(unsigned long long) * ring, stream));
+            HIP_TRY(hipMemsetAsync(q.state, 0, sizeof(int32_t) * cap_tiles, stream));
+            HIP_TRY(hipMemsetAsync(d_qctl, 0, 8 * sizeof(uint32_t), stream));
+            int khz = 0;
+            HIP_TRY(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+            wall_khz = (unsigned long long)std::max(khz, 1);
+            q.budget = wall_khz * (unsigned long long)opt.budget_us / 1000ull;
+            agrid = (int)std::max<int64_t>(1, std::min<int64_t>(waves / kWavesPerBlock, need));
+        }
         HIP_TRY(hipStreamSynchronize(stream));
         return OMAP_OK;
     }
@@ -454,6 +494,8 @@ class Solver {
         a.tile_rows = opt.TH;
         a.tile_cols = opt.TW;
         a.dense = opt.dense;
+        a.async = opt.async;
+        a.q = q;
         return a;
     }
 
@@ -665,7 +707,56 @@ class Solver {
         HIP_TRY(hipMemsetAsync(d_flags[1], 0, sizeof(int32_t) * std::max(tile_hwm, 1), stream));
         HIP_TRY(hipMemsetAsync(d_sched, 0, 3 * sizeof(int32_t) * cap_slots, stream));
         HIP_TRY(hipMemsetAsync(d_dchg, 0, 3 * sizeof(int32_t) * cap_slots, stream));
+        if (opt.async) HIP_TRY(hipMemsetAsync(d_qctl, 0, 8 * sizeof(uint32_t), stream));
         return OMAP_OK;
+    }
+
+    // Asynchronous launches until no tile needs a visit.  A launch that used
+    // up its time budget leaves the unvisited entries in the ring; they are
+    // moved to its start and the next launch continues from them.
+    omap_status_t run_async() {
+        const RoundArgs a = round_args();
+        for (;;) {
+            std::pair<hipEvent_t, hipEvent_t> ev{};
+            if (prof) {
+                HIP_TRY(hipEventCreate(&ev.first));
+                HIP_TRY(hipEventCreate(&ev.second));
+                HIP_TRY(hipEventRecord(ev.first, stream));
+            }
+            HIP_TRY(launch_sweep_async(opt.T, opt.C, a, agrid, stream));
+            if (prof) {
+                HIP_TRY(hipEventRecord(ev.second, stream));
+                prof_events.push_back(ev);
+            }
+            HIP_TRY(hipMemcpyAsync(h_pinned, d_qctl, 8 * sizeof(uint32_t), hipMemcpyDeviceToHost, stream));
+            HIP_TRY(hipStreamSynchronize(stream));
+            const int32_t pending = (int32_t)h_pinned[2], error = (int32_t)h_pinned[4];
+            uint32_t n = 0;
+            if (error == 0 && pending != 0) {
+                // paused: gather the queued entries (every pending tile has one)
+                HIP_TRY(launch_queue_compact(q, d_qtmp, d_qctl + 5, stream));
+                HIP_TRY(hipMemcpyAsync(h_pinned, d_qctl + 5, sizeof(uint32_t), hipMemcpyDeviceToHost, stream));
+                HIP_TRY(hipStreamSynchronize(stream));
+                n = (uint32_t)h_pinned[0];
+            }
+            if (error != 0 || (pending != 0 && n != (uint32_t)pending)) {
+                // cannot happen with the ring sized as it is; leave a clean queue
+                HIP_TRY(hipMemsetAsync(q.ring, 0, sizeof(unsigned long long) * (q.ring_mask + 1ull), stream));
+                HIP_TRY(hipMemsetAsync(q.state, 0, sizeof(int32_t) * cap_tiles, stream));
+                HIP_TRY(hipMemsetAsync(d_qctl, 0, 8 * sizeof(uint32_t), stream));
+                HIP_TRY(hipStreamSynchronize(stream));
+                return fail(OMAP_ERR_HIP, "asynchronous launch: inconsistent work queue (error %d, pending %d, queued %u)",
+                            error, pending, n);
+            }
+            if (pending == 0) return OMAP_OK;
+            if (n > 0)
+                HIP_TRY(hipMemcpyAsync(q.ring, d_qtmp, sizeof(unsigned long long) * n, hipMemcpyDeviceToDevice,
+                                       stream));
+            h_pinned[8] = 0;
+            h_pinned[9] = (int32_t)n;
+            HIP_TRY(hipMemcpyAsync(d_qctl, h_pinned + 8, 2 * sizeof(uint32_t), hipMemcpyHostToDevice, stream));
+            HIP_TRY(hipStreamSynchronize(stream));
+        }
     }
 
     // One round: one sweep launch.
@@ -748,6 +839,7 @@ class Solver {
 
     // Rounds until no tile is scheduled (every started maze converged).
     omap_status_t run_to_convergence() {
+        if (opt.async) return run_async();
         if (use_persistent()) {
             for (;;) {
                 int32_t ran = 0, n = 0;
@@ -780,7 +872,7 @@ class Solver {
             lo = std::min(lo, slots[k].tile_base);
             hi = std::max(hi, slots[k].tile_base + slots[k].n_tiles);
         }
-        HIP_TRY(launch_reduce(d_mazes, d_tile_maze, lo, hi, d_sel, opt.TH, opt.TW, parity, d_min,
+        HIP_TRY(launch_reduce(d_mazes, d_tile_maze, d_touched, lo, hi, d_sel, opt.TH, opt.TW, parity, d_min,
                               d_reached, stream));
         std::vector<unsigned long long> reached(cap_slots);
         HIP_TRY(hipMemcpyAsync(mins.data(), d_min, sizeof(int32_t) * cap_slots, hipMemcpyDeviceToHost, stream));
@@ -1187,7 +1279,9 @@ omap_status_t omap_resolve_options(const omap_options* options, omap_options* re
     resolved->schedule = r.dense ? OMAP_SCHEDULE_DENSE : OMAP_SCHEDULE_ACTIVE;
     resolved->check_interval = r.check;
     resolved->lane_columns = r.C;
-    resolved->round_launch = r.per_round ? OMAP_LAUNCH_PER_ROUND : OMAP_LAUNCH_PERSISTENT;
+    resolved->round_launch =
+        r.async ? OMAP_LAUNCH_ASYNC : (r.per_round ? OMAP_LAUNCH_PER_ROUND : OMAP_LAUNCH_PERSISTENT);
+    resolved->async_budget_us = r.budget_us;
     return OMAP_OK;
 }
 
@@ -1446,6 +1540,7 @@ omap_status_t omap_engine_create(omap_engine_t* out, int64_t memory_budget_bytes
         return fail(OMAP_ERR_INVALID_ARG, "need out, budget >= 1 MiB and max_slots >= 1");
     Options o;
     OK_TRY(resolve_options(opts, &o));
+    o.async = 0;   // the engine advances mazes by whole rounds
     std::unique_ptr<omap_engine_s> e(new omap_engine_s());
     if (!e->mem.init((size_t)memory_budget_bytes))
         return fail(OMAP_ERR_OUT_OF_MEMORY, "engine budget of %lld bytes", (long long)memory_budget_bytes);

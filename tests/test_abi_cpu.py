@@ -74,7 +74,7 @@ def test_plan_create_validation(args, status):
 
 def test_plan_create_null_out_and_bad_options():
     assert omap.STATUS[_create(5, 5, FAKE, [[0, 0]], [], out=False)] == "OMAP_ERR_INVALID_ARG"
-    for bad in (omap.Options(3, 0, 0, 0, 0), omap.Options(0, 3, 0, 0, 0), omap.Options(0, 0, 7, 0, 0), omap.Options(0, 0, 0, 0, 0, 5),
+    for bad in (omap.Options(3, 0, 0, 0, 0), omap.Options(0, 3, 0, 0, 0), omap.Options(0, 0, 7, 0, 0), omap.Options(0, 0, 0, 0, 0, 5), omap.Options(0, 0, 1, 0, 0, 2),
                 omap.Options(16, 8, 0, 0, 0), omap.Options(0, 0, 0, -1, 0), omap.Options(0, 0, 0, 0, 3),
                 omap.Options(24, 0, 0, 0, 4), omap.Options(32, 16, 0, 0, 2)):
         assert omap.STATUS[_create(5, 5, FAKE, [[0, 0]], [], opts=bad)] == "OMAP_ERR_INVALID_ARG"
@@ -111,12 +111,18 @@ def test_batch_validation_names_the_maze():
 def test_resolve_options_fills_defaults():
     d = omap.resolve_options()
     assert d == {"temporal_depth": 16, "tile_rows": 16, "schedule": omap.SCHEDULE_ACTIVE,
-                 "check_interval": 0, "lane_columns": 2, "round_launch": omap.LAUNCH_PER_ROUND}
+                 "check_interval": 0, "lane_columns": 2, "round_launch": omap.LAUNCH_PER_ROUND,
+                 "async_budget_us": 50000}
     d = omap.resolve_options(schedule=omap.SCHEDULE_DENSE)
     assert (d["lane_columns"], d["tile_rows"], d["temporal_depth"]) == (4, 256, 16)
     d = omap.resolve_options(temporal_depth=32, round_launch=omap.LAUNCH_PERSISTENT)
     assert (d["tile_rows"], d["lane_columns"], d["round_launch"]) == (32, 2, omap.LAUNCH_PERSISTENT)
     with pytest.raises(omap.OmapError):
         omap.resolve_options(temporal_depth=32, lane_columns=4)
+    with pytest.raises(omap.OmapError):
+        omap.resolve_options(round_launch=omap.LAUNCH_ASYNC, schedule=omap.SCHEDULE_DENSE)
+    with pytest.raises(omap.OmapError):
+        omap.resolve_options(round_launch=omap.LAUNCH_ASYNC, async_budget_us=5)
+    assert omap.resolve_options(round_launch=omap.LAUNCH_ASYNC, async_budget_us=200)["async_budget_us"] == 200
     L = omap.lib()
     assert omap.STATUS[L.omap_resolve_options(None, None)] == "OMAP_ERR_INVALID_ARG"

@@ -30,14 +30,15 @@ def _batch_mazes(n, seed, hmax=300):
     return ms
 
 
-@pytest.mark.parametrize("T,tile_rows,schedule", [(16, 64, 0), (8, 16, 0), (4, 8, 1), (12, 24, 0)])
-def test_batch_matches_oracle(T, tile_rows, schedule):
+@pytest.mark.parametrize("T,tile_rows,schedule,launch", [(16, 64, 0, 0), (8, 16, 0, 0), (4, 8, 1, 0), (12, 24, 0, 0),
+                                                        (16, 16, 0, 2), (8, 8, 0, 2)])
+def test_batch_matches_oracle(T, tile_rows, schedule, launch):
     import paper_2004_00540_amd as omap
-    ms = _batch_mazes(24, 50 + T)
+    ms = _batch_mazes(24, 50 + T + launch)
     rng = np.random.default_rng(T)
     layers = [int(x) if x >= 0 else -1 for x in rng.integers(-20, 60, len(ms))]
     with omap.Batch([(to_dev(m.occ), m.sources, m.targets) for m in ms], temporal_depth=T,
-                    tile_rows=tile_rows, schedule=schedule) as b:
+                    tile_rows=tile_rows, schedule=schedule, round_launch=launch) as b:
         infos = b.propagate(layers)
         acts = [b.activity(i).cpu().numpy() for i in range(len(ms))]
         ln, off, cells = (t.cpu().numpy() for t in b.paths())

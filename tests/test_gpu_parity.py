@@ -140,11 +140,35 @@ def test_config2_full_size():
     assert_same(m, got, oracle_solution(m, 1000, closed_form=True), "config2 L=1000 dense")
 
 
-@pytest.mark.parametrize("launch", [0, 1])
+@pytest.mark.parametrize("launch", [0, 1, 2])
 def test_launch_modes_identical_bits(launch):
     for i, (T, C) in enumerate([(16, 2), (16, 4), (8, 2), (32, 2)]):
         m = workloads.random_maze(400, 700, 0.33, 2 + i, 30, 6060 + i)
-        for sched in (0, 1):
+        for sched in ((0,) if launch == 2 else (0, 1)):
             for L in (-1, 40):
+                print(f"launch={launch} T={T} C={C} sched={sched} L={L}", flush=True)
                 got = run_plan(m, L, temporal_depth=T, lane_columns=C, schedule=sched, round_launch=launch)
                 assert_same(m, got, oracle_solution(m, L), f"launch={launch} T={T} C={C} sched={sched} L={L}")
+
+
+@pytest.mark.parametrize("T,C", [(v[0], v[1]) for v in VARIANTS])
+def test_async_launch_every_variant(T, C):
+    """The work-queue launch (in-place tile updates in any order) reaches the
+    oracle's bits with every kernel variant, on mazes of several shapes."""
+    for k, (H, W, p) in enumerate([(130, 517, 0.3), (333, 64, 0.2), (1, 900, 0.0), (257, 255, 0.38)]):
+        m = workloads.random_maze(H, W, p, 3, 20, 9100 + 17 * T + C + k)
+        for L in (-1, 25):
+            got = run_plan(m, L, temporal_depth=T, lane_columns=C, round_launch=2)
+            assert_same(m, got, oracle_solution(m, L), f"async T={T} C={C} {H}x{W} L={L}")
+
+
+def test_async_launch_pauses_and_resumes():
+    """A tiny time budget makes every launch pause with tiles still queued; the
+    queued tiles are gathered and the next launch continues from them."""
+    m = workloads.random_maze(700, 900, 0.3, 4, 40, 9200)
+    ref = oracle_solution(m, -1)
+    for budget in (10, 200):
+        got = run_plan(m, -1, round_launch=2, async_budget_us=budget)
+        assert_same(m, got, ref, f"async budget {budget} us")
+    got = run_plan(m, 60, round_launch=2, async_budget_us=50)
+    assert_same(m, got, oracle_solution(m, 60), "async budget 50 us, L=60")
