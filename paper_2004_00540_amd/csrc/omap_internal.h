@@ -10,6 +10,10 @@ constexpr int kLanes = 64;                          // CDNA wavefront
 constexpr int kWavesPerBlock = 4;
 constexpr int kBlockThreads = kLanes * kWavesPerBlock;
 constexpr uint32_t kObstacleBit = 0x80000000u;      // in-register obstacle marker
+// Visit counters are kept in kSpread copies (a block adds to copy blockIdx mod
+// kSpread) so that concurrent waves do not serialise on one address; readers
+// sum the copies.
+constexpr int kSpread = 16;
 
 // Maze state on the device.  Activity rows are `pitch` int32 apart (pitch a
 // multiple of 64, so rows are 256-byte aligned); the obstacle mask has one bit
@@ -58,16 +62,17 @@ struct RoundArgs {
     int32_t* count_out;           // their number (dense: 1 = some tile changed)
     int32_t* flags_out;           // 1 = already scheduled for round r+1
     int32_t* count_clear;         // count of round r+2, zeroed by round r
-    int32_t* sched_out;           // per slot: tiles scheduled for round r+1
+    int32_t* sched_out;           // per slot: tiles scheduled for round r+1 (kept only with
+                                  // more than one slot; with one slot it equals *count_out)
     int32_t* sched_clear;         // per slot: scheduled counts of round r+2, zeroed by round r
     int32_t* dchg_prev;           // dense, per slot: changed in round r-1 (visit in round r)
     int32_t* dchg_cur;            // dense, per slot: changed in round r
     int32_t* dchg_clear;          // dense, per slot: flags of round r+1, zeroed by round r
     int32_t* maze_last_round;     // per slot: last round with a tile visited
     uint8_t* touched;             // per tile id: written since its maze's buffers were last cleared
-    int64_t* maze_visits;         // per slot: tile visits
-    int64_t* maze_cell_visits;    // per slot: interior cells of visited tiles
-    unsigned long long* total_cells;  // all slots: interior cells of visited tiles
+    int64_t* maze_visits;         // [slot][kSpread]: tile visits
+    int64_t* maze_cell_visits;    // [slot][kSpread]: interior cells of visited tiles
+    unsigned long long* total_cells;  // [kSpread], all slots: interior cells of visited tiles
     int32_t n_slots;
     int32_t round_id;             // r (wraps; only differences are used)
     int32_t parity;               // activity buffer read in round r (r mod 2)

@@ -108,7 +108,7 @@ __device__ __forceinline__ void schedule_tile(const RoundArgs& a, const MazeDev&
         const int k = atomicAdd(a.count_out, 1);
         a.list_out[2 * k] = g;
         a.list_out[2 * k + 1] = slot;
-        atomicAdd(&a.sched_out[slot], 1);
+        if (a.n_slots > 1) atomicAdd(&a.sched_out[slot], 1);
     }
 }
 
@@ -129,7 +129,7 @@ __device__ __forceinline__ void schedule_neighbourhood(const RoundArgs& a, const
     int base = 0;
     if (lane == 0) {
         base = atomicAdd(a.count_out, n);
-        atomicAdd(&a.sched_out[slot], n);
+        if (a.n_slots > 1) atomicAdd(&a.sched_out[slot], n);
     }
     base = __builtin_amdgcn_readfirstlane(base);
     if (won) {
@@ -199,25 +199,28 @@ __global__ void k_seed(RoundArgs a, int32_t slot, const int32_t* __restrict__ sr
 // (P+1) mod 3.  Stage s writes its output row straight into stage s+1's slot
 // P, whose previous content (row i-3 of that stage) is dead, so no register
 // copies are needed.
-template <int T, int P, int C>
-__device__ __forceinline__ void sweep_row(uint32_t (&st)[T][3][C], uint32_t (&out)[C]) {
+// With GUARD, stages above smax are skipped (see sweep_tile).
+template <int T, int P, int C, bool GUARD>
+__device__ __forceinline__ void sweep_row(uint32_t (&st)[T][3][C], uint32_t (&out)[C], int smax) {
     constexpr int PA = (P + 1) % 3, PB = (P + 2) % 3;
 #pragma unroll
     for (int s = 0; s < T; ++s) {
-        const uint32_t* a = st[s][PA];   // row above the centre
-        const uint32_t* b = st[s][PB];   // centre row
-        const uint32_t* c = st[s][P];    // row below the centre
-        int v[C];
+        if (!GUARD || s <= smax) {
+            const uint32_t* a = st[s][PA];   // row above the centre
+            const uint32_t* b = st[s][PB];   // centre row
+            const uint32_t* c = st[s][P];    // row below the centre
+            int v[C];
 #pragma unroll
-        for (int j = 0; j < C; ++j) v[j] = max3i((int)a[j], (int)b[j], (int)c[j]);
-        const int left = from_left_lane(v[C - 1]);
-        const int right = from_right_lane(v[0]);
-        uint32_t* o = (s + 1 < T) ? st[s + 1 < T ? s + 1 : s][P] : out;
+            for (int j = 0; j < C; ++j) v[j] = max3i((int)a[j], (int)b[j], (int)c[j]);
+            const int left = from_left_lane(v[C - 1]);
+            const int right = from_right_lane(v[0]);
+            uint32_t* o = (s + 1 < T) ? st[s + 1 < T ? s + 1 : s][P] : out;
 #pragma unroll
-        for (int j = 0; j < C; ++j) {
-            const int l = j == 0 ? left : v[j - 1];
-            const int r = j == C - 1 ? right : v[j + 1];
-            o[j] = max(b[j], sat_dec((uint32_t)max3i(l, v[j], r)));
+            for (int j = 0; j < C; ++j) {
+                const int l = j == 0 ? left : v[j - 1];
+                const int r = j == C - 1 ? right : v[j + 1];
+                o[j] = max(b[j], sat_dec((uint32_t)max3i(l, v[j], r)));
+            }
         }
     }
 }
@@ -261,11 +264,11 @@ __device__ __forceinline__ void load_row(const MazeDev& md, const int32_t* Vin, 
 // earlier; it is decoded into stage 0's slot P (cells outside the grid become
 // exactly 0x80000000) and the same registers then receive the load of row
 // R + 3, whose latency overlaps the T-stage arithmetic of the next rows.
-template <int T, int P, int C>
+template <int T, int P, int C, bool GUARD>
 __device__ __forceinline__ void sweep_iter(uint32_t (&st)[T][3][C], typename LaneVec<C>::type& v,
                                            uint32_t& w, const MazeDev& md,
                                            const int32_t* Vin, int32_t* Vout, int R, int r0, int r_end,
-                                           int col, bool col_ok, bool inner,
+                                           int col, bool col_ok, bool inner, int smax,
                                            uint64_t& sum_in, uint64_t& sum_out) {
     const bool ok = R >= 0 && R < md.H && col_ok;
     const uint32_t keep = ok ? 0xffffffffu : 0u;
@@ -280,8 +283,8 @@ __device__ __forceinline__ void sweep_iter(uint32_t (&st)[T][3][C], typename Lan
         for (int j = 0; j < C; ++j) t += c[j] & 0x7fffffffu;
         sum_in += t;
     }
-    uint32_t out[C];
-    sweep_row<T, P, C>(st, out);
+    uint32_t out[C] = {};   // left 0 when the last stage is skipped (its row is not stored then)
+    sweep_row<T, P, C, GUARD>(st, out, smax);
     const int Ro = R - T;
     if (inner && Ro >= r0 && Ro < r_end) {
         typename LaneVec<C>::type o;
@@ -329,11 +332,30 @@ __device__ bool sweep_tile(const MazeDev& md, int ty, int tx, int tile_rows, int
     load_row<C>(md, Vin, r0 - T, col, col_ok, v0, w0);
     load_row<C>(md, Vin, r0 - T + 1, col, col_ok, v1, w1);
     load_row<C>(md, Vin, r0 - T + 2, col, col_ok, v2, w2);
-    for (int i = 0; i < n_iter; i += 3) {
+    // Stage s at step i (input row r0 - T + i) emits row r0 - T + i - 1 - s
+    // after s + 1 layers; the stored rows [r0, r_end) after T layers need
+    // exactly the emissions with i >= 2s + 2 (each of which reads only
+    // emissions of stage s - 1 with i - 2 >= 2(s - 1) + 2).  So during the
+    // first 2T steps, stages s > i/2 - 1 are skipped: the top of the tile's
+    // trapezoid, a third of the work of a tile with as many rows as layers.
+    constexpr int kWarm = 3 * ((2 * T + 2) / 3);   // >= 2T, a multiple of 3
+    int i = 0;
+    for (; i < kWarm; i += 3) {
         const int R = r0 - T + i;
-        sweep_iter<T, 0, C>(st, v0, w0, md, Vin, Vout, R, r0, r_end, col, col_ok, inner, sum_in, sum_out);
-        sweep_iter<T, 1, C>(st, v1, w1, md, Vin, Vout, R + 1, r0, r_end, col, col_ok, inner, sum_in, sum_out);
-        sweep_iter<T, 2, C>(st, v2, w2, md, Vin, Vout, R + 2, r0, r_end, col, col_ok, inner, sum_in, sum_out);
+        sweep_iter<T, 0, C, true>(st, v0, w0, md, Vin, Vout, R, r0, r_end, col, col_ok, inner, (i >> 1) - 1,
+                                  sum_in, sum_out);
+        sweep_iter<T, 1, C, true>(st, v1, w1, md, Vin, Vout, R + 1, r0, r_end, col, col_ok, inner,
+                                  ((i + 1) >> 1) - 1, sum_in, sum_out);
+        sweep_iter<T, 2, C, true>(st, v2, w2, md, Vin, Vout, R + 2, r0, r_end, col, col_ok, inner,
+                                  ((i + 2) >> 1) - 1, sum_in, sum_out);
+    }
+    for (; i < n_iter; i += 3) {
+        const int R = r0 - T + i;
+        sweep_iter<T, 0, C, false>(st, v0, w0, md, Vin, Vout, R, r0, r_end, col, col_ok, inner, 0, sum_in, sum_out);
+        sweep_iter<T, 1, C, false>(st, v1, w1, md, Vin, Vout, R + 1, r0, r_end, col, col_ok, inner, 0, sum_in,
+                                   sum_out);
+        sweep_iter<T, 2, C, false>(st, v2, w2, md, Vin, Vout, R + 2, r0, r_end, col, col_ok, inner, 0, sum_in,
+                                   sum_out);
     }
     return __ballot(sum_in != sum_out) != 0;
 }
@@ -343,8 +365,10 @@ __device__ bool sweep_tile(const MazeDev& md, int ty, int tx, int tile_rows, int
 __global__ void k_slot_reset(RoundArgs a, int32_t slot) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     a.maze_last_round[slot] = a.round_id - 1;
-    a.maze_visits[slot] = 0;
-    a.maze_cell_visits[slot] = 0;
+    for (int k = 0; k < kSpread; ++k) {
+        a.maze_visits[slot * kSpread + k] = 0;
+        a.maze_cell_visits[slot * kSpread + k] = 0;
+    }
     if (a.dense) a.dchg_prev[slot] = 1;
 }
 
@@ -401,9 +425,10 @@ __device__ __forceinline__ void sweep_round(const RoundArgs& a) {
         if (lane == 0) {
             const unsigned long long cells =
                 (unsigned long long)tile_cells(md, ty, tx, a.tile_rows, a.tile_cols);
-            atomicAdd(reinterpret_cast<unsigned long long*>(&a.maze_visits[slot]), 1ull);
-            atomicAdd(reinterpret_cast<unsigned long long*>(&a.maze_cell_visits[slot]), cells);
-            atomicAdd(a.total_cells, cells);
+            const int sp = blockIdx.x & (kSpread - 1);
+            atomicAdd(reinterpret_cast<unsigned long long*>(&a.maze_visits[slot * kSpread + sp]), 1ull);
+            atomicAdd(reinterpret_cast<unsigned long long*>(&a.maze_cell_visits[slot * kSpread + sp]), cells);
+            atomicAdd(a.total_cells + sp, cells);
             if (a.maze_last_round[slot] != a.round_id) a.maze_last_round[slot] = a.round_id;
             a.touched[g] = 1;
         }
@@ -563,15 +588,19 @@ __global__ __launch_bounds__(kBlockThreads) void k_sweep_async(RoundArgs a) {
         if (lane == 0) {
             const unsigned long long cells =
                 (unsigned long long)tile_cells(md, ty, tx, a.tile_rows, a.tile_cols);
-            atomicAdd(reinterpret_cast<unsigned long long*>(&a.maze_visits[slot]), 1ull);
-            atomicAdd(reinterpret_cast<unsigned long long*>(&a.maze_cell_visits[slot]), cells);
-            atomicAdd(a.total_cells, cells);
+            const int sp = blockIdx.x & (kSpread - 1);
+            atomicAdd(reinterpret_cast<unsigned long long*>(&a.maze_visits[slot * kSpread + sp]), 1ull);
+            atomicAdd(reinterpret_cast<unsigned long long*>(&a.maze_cell_visits[slot * kSpread + sp]), cells);
+            atomicAdd(a.total_cells + sp, cells);
             a.touched[g] = 1;
         }
-        if (sweep_tile<T, C, true>(md, ty, tx, a.tile_rows, a.parity)) {
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-            queue_mark_neighbourhood(q, md, slot, ty, tx);
-        }
+        const bool changed = sweep_tile<T, C, true>(md, ty, tx, a.tile_rows, a.parity);
+        // Every visit publishes its stores before it ends, changed or not: a
+        // store left dirty in this XCD's L2 could otherwise be written back
+        // after a later visit (on another XCD) stored larger values, and
+        // overwrite them.
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        if (changed) queue_mark_neighbourhood(q, md, slot, ty, tx);
         if (lane == 0) {
             const int old = atomicCAS(&q.state[g], 2, 0);
             if (old == 2) {

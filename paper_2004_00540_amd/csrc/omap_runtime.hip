@@ -401,9 +401,9 @@ class Solver {
         HIP_TRY(hipHostMalloc((void**)&h_bad, sizeof(int32_t) * cap_slots, hipHostMallocDefault));
         h_mazes.assign(cap_slots, MazeDev());
         h_tile_maze.assign(cap_tiles, -1);
-        OK_TRY(dalloc(&d_visits, cap_slots));
-        OK_TRY(dalloc(&d_cell_visits, cap_slots));
-        OK_TRY(dalloc(&d_total_cells, 1));
+        OK_TRY(dalloc(&d_visits, (size_t)cap_slots * kSpread));
+        OK_TRY(dalloc(&d_cell_visits, (size_t)cap_slots * kSpread));
+        OK_TRY(dalloc(&d_total_cells, kSpread));
         OK_TRY(dalloc(&d_min, cap_slots));
         OK_TRY(dalloc(&d_reached, cap_slots));
         OK_TRY(dalloc(&d_bad, 1));
@@ -419,9 +419,9 @@ class Solver {
         HIP_TRY(hipMemsetAsync(d_touched, 0, cap_tiles, stream));
         HIP_TRY(hipMemsetAsync(d_bar, 0, 2 * sizeof(unsigned int), stream));
         HIP_TRY(hipMemsetAsync(d_bad_slot, 0, sizeof(int32_t) * cap_slots, stream));
-        HIP_TRY(hipMemsetAsync(d_visits, 0, sizeof(int64_t) * cap_slots, stream));
-        HIP_TRY(hipMemsetAsync(d_cell_visits, 0, sizeof(int64_t) * cap_slots, stream));
-        HIP_TRY(hipMemsetAsync(d_total_cells, 0, sizeof(unsigned long long), stream));
+        HIP_TRY(hipMemsetAsync(d_visits, 0, sizeof(int64_t) * cap_slots * kSpread, stream));
+        HIP_TRY(hipMemsetAsync(d_cell_visits, 0, sizeof(int64_t) * cap_slots * kSpread, stream));
+        HIP_TRY(hipMemsetAsync(d_total_cells, 0, sizeof(unsigned long long) * kSpread, stream));
         int dev = 0;
         HIP_TRY(hipGetDevice(&dev));
         int cus = 0;
@@ -913,10 +913,16 @@ class Solver {
         OK_TRY(ensure_finalized(k));
         int64_t v[3] = {0, 0, 0};
         int32_t last = 0;
+        int64_t vis[kSpread], cvis[kSpread];
         HIP_TRY(hipMemcpyAsync(&last, d_last_round + k, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
-        HIP_TRY(hipMemcpyAsync(&v[1], d_visits + k, sizeof(int64_t), hipMemcpyDeviceToHost, stream));
-        HIP_TRY(hipMemcpyAsync(&v[2], d_cell_visits + k, sizeof(int64_t), hipMemcpyDeviceToHost, stream));
+        HIP_TRY(hipMemcpyAsync(vis, d_visits + (size_t)k * kSpread, sizeof vis, hipMemcpyDeviceToHost, stream));
+        HIP_TRY(hipMemcpyAsync(cvis, d_cell_visits + (size_t)k * kSpread, sizeof cvis, hipMemcpyDeviceToHost,
+                               stream));
         HIP_TRY(hipStreamSynchronize(stream));
+        for (int j = 0; j < kSpread; ++j) {
+            v[1] += vis[j];
+            v[2] += cvis[j];
+        }
         const Slot& s = slots[k];
         v[0] = (int64_t)(int32_t)(last - (int32_t)s.first_round) + 1;   // rounds the maze was visited
         if (v[0] < 0) v[0] = 0;
@@ -1057,6 +1063,16 @@ class Solver {
         return OMAP_OK;
     }
 
+    // Sum of the visit-cell counter copies (synchronous).
+    omap_status_t total_cells(unsigned long long* out) {
+        unsigned long long c[kSpread];
+        HIP_TRY(hipMemcpyAsync(c, d_total_cells, sizeof c, hipMemcpyDeviceToHost, stream));
+        HIP_TRY(hipStreamSynchronize(stream));
+        *out = 0;
+        for (int j = 0; j < kSpread; ++j) *out += c[j];
+        return OMAP_OK;
+    }
+
     omap_status_t profile(bool on) {
         if (on) {
             for (auto& e : prof_events) {
@@ -1066,8 +1082,7 @@ class Solver {
             prof_events.clear();
             prof_launches = 0;
             prof_ms = 0;
-            HIP_TRY(hipMemcpyAsync(&prof_cells0, d_total_cells, sizeof prof_cells0, hipMemcpyDeviceToHost, stream));
-            HIP_TRY(hipStreamSynchronize(stream));
+            OK_TRY(total_cells(&prof_cells0));
         }
         prof = on;
         return OMAP_OK;
@@ -1085,7 +1100,7 @@ class Solver {
         }
         prof_events.clear();
         unsigned long long cells = 0;
-        HIP_TRY(hipMemcpy(&cells, d_total_cells, sizeof cells, hipMemcpyDeviceToHost));
+        OK_TRY(total_cells(&cells));
         if (launches) *launches = prof_launches;
         if (ms) *ms = prof_ms;
         if (cell_updates) *cell_updates = (int64_t)(cells - prof_cells0) * opt.T;
@@ -1204,8 +1219,10 @@ static omap_status_t engine_retire(omap_engine_s* e) {
     // (dense schedule).
     Solver& sv = e->solver;
     const int64_t r = sv.next_round;
-    const int32_t* src = sv.opt.dense ? sv.d_dchg + (size_t)((r + 2) % 3) * sv.cap_slots
-                                      : sv.d_sched + (size_t)(r % 3) * sv.cap_slots;
+    // (with one slot the kernels keep only the list count, which is that slot's)
+    const int32_t* src = sv.opt.dense     ? sv.d_dchg + (size_t)((r + 2) % 3) * sv.cap_slots
+                         : sv.cap_slots > 1 ? sv.d_sched + (size_t)(r % 3) * sv.cap_slots
+                                            : sv.d_count + r % 3;
     std::vector<int32_t> pending(sv.cap_slots);
     HIP_TRY(hipMemcpyAsync(pending.data(), src, sizeof(int32_t) * pending.size(), hipMemcpyDeviceToHost,
                            sv.stream));
