@@ -30,6 +30,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0                  # MI355X HBM3E
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sweep_c3_traffic.json")
+KERNEL_SOURCES = ("omap_sweep.h", "omap_sweep_variant.hip", "omap_internal.h")
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12   # 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz, 32-bit ops
 BYTES_PER_CELL_UPDATE = 8.125          # int32 read + int32 write + 1 mask bit
 
@@ -86,6 +88,30 @@ def cpu_baseline(m, budget_s: float = 12.0):
         "cpu_model": model, "host_cores": cores,
         "walk_paths_per_s": round(len(tgt) / max(t_walk, 1e-9), 1),
     }
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2004_00540_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload: str, options: dict):
+    """HBM bytes per sweep launch from the committed hardware-counter summary
+    (FETCH_SIZE + WRITE_SIZE, calibrated against a plain copy), or None when
+    the counters were taken on other kernel sources or another configuration."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_sha256") != kernel_source_hash() or t.get("workload") != workload \
+            or t.get("options") != options:
+        return None
+    return t.get("bytes_per_launch")
 
 
 def copy_probe(args):
@@ -171,6 +197,7 @@ def bench_plain(args):
     plan.close()
 
     step_s = wall
+    resolved = omap.resolve_options(**opts)
     gcups = N * S_J / step_s / 1e9
     alg_bytes = prof["cell_updates"] * BYTES_PER_CELL_UPDATE
     kern_s = prof["ms"] / 1e3
@@ -184,7 +211,7 @@ def bench_plain(args):
         "vs_baseline": None, "dtype": "int32", "data": "synthetic",
         "config": {"workload": m.name, "cells": N, "sources": len(m.sources), "targets": nt,
                    "layers_run_time": L_star, "effective_layers": S_J,
-                   "options": omap.resolve_options(**opts)},
+                   "options": resolved},
         "paths_per_s": round(nt / step_s, 1),
         "path_cells": int(cells0.numel()),
         "phase_ms": {"ingest": round(t_load, 3), "propagate": round(t_prop, 3), "extract": round(t_ext, 3)},
@@ -194,7 +221,9 @@ def bench_plain(args):
                          "cell_updates": prof["cell_updates"],
                          "dense_cell_updates": N * S_J},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None},
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic(m.name, resolved),
+                     "algorithmic_bytes_per_launch": round(alg_bytes / max(prof["launches"], 1))},
         "roofline_alu": {"bound": "alu", "achieved": round(alu_tops, 2), "peak": round(VALU_PEAK_TOPS, 1),
                          "unit": "Tops/s", "frac": round(alu_tops / VALU_PEAK_TOPS, 4),
                          "ops_per_cell_update": ops_per_cell},

@@ -86,8 +86,9 @@ typedef struct omap_options {
     int32_t schedule;        /* OMAP_SCHEDULE_ACTIVE or OMAP_SCHEDULE_DENSE                 */
     int32_t check_interval;  /* rounds between host reads of the convergence count;        */
                              /* 0 = adaptive                                                */
-    int32_t lane_columns;    /* columns each lane owns (tile strip = 64 x this): 2 or 4;   */
-                             /* 0 = default (active: 2; dense: 4)                          */
+    int32_t lane_columns;    /* columns each lane owns (tile strip = 64 x this): 1, 2 or   */
+                             /* 4 (1: temporal_depth 4..16); 0 = default (active: 2;       */
+                             /* dense: 4)                                                  */
     int32_t round_launch;    /* OMAP_LAUNCH_PER_ROUND (default): one launch per round;     */
                              /* OMAP_LAUNCH_PERSISTENT: one cooperative launch runs rounds */
                              /* until convergence, separated by a device-wide barrier      */

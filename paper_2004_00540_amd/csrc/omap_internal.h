@@ -79,8 +79,10 @@ struct RoundArgs {
     int32_t tile_rows;            // interior rows per tile
     int32_t tile_cols;            // interior columns per tile (64*C - 2T)
     int32_t dense;                // 1 = dense schedule
+    int32_t wave_stride;          // waves in the launch (set by the launch wrapper)
     int32_t async;                // 1 = seeds go to the asynchronous work queue
     AsyncQueue q;
+    MazeDev md0;                  // copy of mazes[0] when n_slots == 1 (saves a dependent load)
 };
 
 // Arguments of a persistent launch running rounds r0, r0+1, ... : the
@@ -99,6 +101,20 @@ struct PersistentArgs {
     unsigned int* bar_gen;
     int32_t* rounds_done;         // rounds actually run
 };
+
+// Sweep variants (layers per visit T, columns per lane C); each is compiled in
+// its own translation unit (omap_sweep_variant.hip with OMAP_T, OMAP_C).
+#define OMAP_SWEEP_VARIANTS(X) \
+    X(4, 4) X(8, 4) X(12, 4) X(16, 4) X(4, 2) X(8, 2) X(12, 2) X(16, 2) X(24, 2) X(32, 2) \
+    X(4, 1) X(8, 1) X(12, 1) X(16, 1)
+
+#define X(t, c)                                                                                       \
+    hipError_t launch_sweep_T##t##_C##c(const RoundArgs& a, int32_t grid, hipStream_t s);             \
+    hipError_t launch_sweep_persistent_T##t##_C##c(const PersistentArgs& p, int32_t grid, hipStream_t s); \
+    hipError_t launch_sweep_async_T##t##_C##c(const RoundArgs& a, int32_t grid, hipStream_t s);       \
+    int sweep_blocks_per_cu_T##t##_C##c(int kind);
+OMAP_SWEEP_VARIANTS(X)
+#undef X
 
 // ---- launch wrappers (omap_kernels.hip) -------------------------------------
 hipError_t launch_pack_mask(const uint8_t* occ, int32_t H, int32_t W, uint32_t* mask,

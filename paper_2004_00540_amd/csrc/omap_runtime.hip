@@ -85,8 +85,8 @@ static omap_status_t resolve_options(const omap_options* o, Options* out) {
     int th = 0;
     if (o) {
         if (o->lane_columns != 0) {
-            if (o->lane_columns != 2 && o->lane_columns != 4)
-                return fail(OMAP_ERR_INVALID_ARG, "lane_columns must be 2 or 4 (got %d)", o->lane_columns);
+            if (o->lane_columns != 1 && o->lane_columns != 2 && o->lane_columns != 4)
+                return fail(OMAP_ERR_INVALID_ARG, "lane_columns must be 1, 2 or 4 (got %d)", o->lane_columns);
             r.C = o->lane_columns;
         }
         if (o->temporal_depth != 0) r.T = o->temporal_depth;
@@ -119,6 +119,7 @@ static omap_status_t resolve_options(const omap_options* o, Options* out) {
         return fail(OMAP_ERR_INVALID_ARG,
                     "temporal_depth %d is not available with %d columns per lane "
                     "(4, 8, 12, 16; with 2 columns also 24, 32)", r.T, r.C);
+    // (with one column per lane the strip is 64 columns: 64 - 2T interior columns)
     r.TH = th ? th : (dense ? 256 : std::max(16, r.T));
     if (r.TH < r.T)
         return fail(OMAP_ERR_INVALID_ARG, "tile_rows (%d) must be >= temporal_depth (%d)", r.TH, r.T);
@@ -496,6 +497,7 @@ class Solver {
         a.dense = opt.dense;
         a.async = opt.async;
         a.q = q;
+        a.md0 = h_mazes.empty() ? MazeDev() : h_mazes[0];
         return a;
     }
 

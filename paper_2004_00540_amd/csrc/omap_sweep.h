@@ -1,0 +1,566 @@
+// Tile-sweep device code of the oMAP planner for gfx950 (CDNA4, wave64),
+// compiled once per (layers per visit, columns per lane) variant by
+// omap_sweep_variant.hip and included by omap_kernels.hip for the shared
+// helpers (seeding uses the same scheduling functions).
+//
+// The network of the paper (Sec. Methods, "Activity Map Generation"; Fig. net)
+// applies L identical layers  A <- ReLU(maxpool3x3(A) + I_e + I_s)  starting
+// from A_0 = I_s.  The kernels run the same layers in an integer encoding with
+// a per-layer decrement: V_0 = K at the sources and 0 elsewhere, and
+//     V'(x) = 0                                   x an obstacle
+//     V'(x) = max(V(x), max over the 3x3 window of V - 1)   otherwise
+// With K = L + 1 the fixpoint of this update equals A_L exactly (both are
+// max(0, L + 1 - d(x)) with d the 8-neighbour step distance to the nearest
+// source), it is reached after at most L sweeps, and further sweeps leave it
+// unchanged.  Because the update is monotone and bounded by that fixpoint, any
+// schedule of tile updates that keeps visiting tiles whose neighbourhood
+// changed reaches the same bits; the tests compare against the paper's literal
+// layers.  With K = 2^31 - 1 the fixpoint is K - d and the run-time determined
+// layer count L* is K minus the smallest positive value.
+//
+// In registers an obstacle is the value 0x80000000 (the sign bit).  Signed
+// max-pooling ignores it; the update  max_u32(V, sat_sub_u32(m, 1))  keeps it
+// (0x80000000 is above any activity as unsigned) and clamps free cells at 0,
+// so one unsigned max and one saturating subtract implement decrement, ReLU and
+// obstacle masking together.
+
+#pragma once
+
+#include "omap_internal.h"
+
+namespace omap {
+
+// ---------------------------------------------------------------------------
+// helpers
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ int max3i(int a, int b, int c) { return max(max(a, b), c); }
+
+__device__ __forceinline__ uint32_t sat_dec(uint32_t x) {
+    return __builtin_elementwise_sub_sat(x, 1u);
+}
+
+// Lane l receives lane l-1's value (DPP wave_shr:1).  Lane 0 has no source
+// and reads 0; the kernels only use that lane's result inside the halo.
+__device__ __forceinline__ int from_left_lane(int v) {
+    return __builtin_amdgcn_mov_dpp(v, 0x138, 0xF, 0xF, true);
+}
+
+// Lane l receives lane l+1's value (DPP wave_shl:1); lane 63 reads 0.
+__device__ __forceinline__ int from_right_lane(int v) {
+    return __builtin_amdgcn_mov_dpp(v, 0x130, 0xF, 0xF, true);
+}
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & (kLanes - 1); }
+
+__device__ __forceinline__ int64_t tile_cells(const MazeDev& md, int ty, int tx, int tile_rows,
+                                              int tile_cols) {
+    return (int64_t)min(tile_rows, md.H - ty * tile_rows) * min(tile_cols, md.W - tx * tile_cols);
+}
+
+// Append tile (ty, tx) of `slot` to a.list_out unless it is already there
+// (flag exchange) and count it in the slot's scheduled tiles.  One lane.
+__device__ __forceinline__ void schedule_tile(const RoundArgs& a, const MazeDev& md, int slot, int ty,
+                                              int tx) {
+    const int g = md.tile_base + ty * md.tiles_x + tx;
+    if (atomicExch(&a.flags_out[g], 1) == 0) {
+        const int k = atomicAdd(a.count_out, 1);
+        a.list_out[2 * k] = g;
+        a.list_out[2 * k + 1] = slot;
+        if (a.n_slots > 1) atomicAdd(&a.sched_out[slot], 1);
+    }
+}
+
+// The same for the 3x3 tiles around (ty, tx), from a whole wave: lanes 0..8
+// claim one tile each, then a single atomic reserves the list entries of all
+// the lanes that won their claim.
+__device__ __forceinline__ void schedule_neighbourhood(const RoundArgs& a, const MazeDev& md, int slot,
+                                                       int ty, int tx) {
+    const int lane = lane_id();
+    const int ny = ty + lane / 3 - 1, nx = tx + lane % 3 - 1;
+    const int g = md.tile_base + ny * md.tiles_x + nx;
+    bool won = false;
+    if (lane < 9 && ny >= 0 && ny < md.tiles_y && nx >= 0 && nx < md.tiles_x)
+        won = atomicExch(&a.flags_out[g], 1) == 0;
+    const uint64_t mask = __ballot(won);
+    if (mask == 0) return;
+    const int n = __popcll(mask);
+    int base = 0;
+    if (lane == 0) {
+        base = atomicAdd(a.count_out, n);
+        if (a.n_slots > 1) atomicAdd(&a.sched_out[slot], n);
+    }
+    base = __builtin_amdgcn_readfirstlane(base);
+    if (won) {
+        const int k = base + __popcll(mask & ((1ull << lane) - 1));
+        a.list_out[2 * k] = g;
+        a.list_out[2 * k + 1] = slot;
+    }
+}
+
+// Pushes one tile, already counted as pending, onto the asynchronous work
+// queue (see k_sweep_async).  One lane.
+__device__ __forceinline__ void queue_push(const AsyncQueue& q, int g, int slot) {
+    const uint32_t k = atomicAdd(q.tail, 1u);
+    const unsigned long long e = ((unsigned long long)(uint32_t)slot << 32) | (uint32_t)(g + 1);
+    if (atomicCAS(q.ring + (k & q.ring_mask), 0ull, e) != 0ull) atomicAdd(q.error, 1);
+}
+
+// ---------------------------------------------------------------------------
+// the sweep: T layers per tile visit, one wave per tile
+// ---------------------------------------------------------------------------
+//
+// A tile is `rows` x TW interior cells (TW = 256 - 2T) at (r0, c0).  The wave
+// streams the 256-column strip [c0 - T, c0 - T + 256) from row r0 - T down to
+// row r0 + rows + T - 1; lane l holds columns c0 - T + 4l .. +3.  Stage s of
+// a T-stage register pipeline applies layer s+1 to the rows stage s-1 emits,
+// one row behind it, keeping its last two input rows in registers.  Cells
+// within s of the strip's edges after s layers are wrong (their neighbours
+// were not loaded), and that region is exactly the halo; the interior is exact
+// after T layers (trapezoidal temporal blocking).  Out-of-grid positions load
+// as obstacles, which is the zero padding of the paper's pooling.
+
+// One row step of the pipeline (C columns per lane).  Stage s keeps its last
+// three input rows in st[s][0..2]; on the step with P = i mod 3 the newest row
+// (i) sits in slot P, row i-1 in slot (P+2) mod 3 and row i-2 in slot
+// (P+1) mod 3.  Stage s writes its output row straight into stage s+1's slot
+// P, whose previous content (row i-3 of that stage) is dead, so no register
+// copies are needed.
+// With GUARD, stages above smax are skipped (see sweep_tile).
+template <int T, int P, int C, bool GUARD>
+__device__ __forceinline__ void sweep_row(uint32_t (&st)[T][3][C], uint32_t (&out)[C], int smax) {
+    constexpr int PA = (P + 1) % 3, PB = (P + 2) % 3;
+#pragma unroll
+    for (int s = 0; s < T; ++s) {
+        if (!GUARD || s <= smax) {
+            const uint32_t* a = st[s][PA];   // row above the centre
+            const uint32_t* b = st[s][PB];   // centre row
+            const uint32_t* c = st[s][P];    // row below the centre
+            int v[C];
+#pragma unroll
+            for (int j = 0; j < C; ++j) v[j] = max3i((int)a[j], (int)b[j], (int)c[j]);
+            const int left = from_left_lane(v[C - 1]);
+            const int right = from_right_lane(v[0]);
+            uint32_t* o = (s + 1 < T) ? st[s + 1 < T ? s + 1 : s][P] : out;
+#pragma unroll
+            for (int j = 0; j < C; ++j) {
+                const int l = j == 0 ? left : v[j - 1];
+                const int r = j == C - 1 ? right : v[j + 1];
+                o[j] = max(b[j], sat_dec((uint32_t)max3i(l, v[j], r)));
+            }
+        }
+    }
+}
+
+// Global-memory views of the activity and mask buffers (lets the compiler use
+// global_load / global_store instead of flat accesses).
+typedef int v4i32 __attribute__((ext_vector_type(4)));
+typedef int v2i32 __attribute__((ext_vector_type(2)));
+typedef int v1i32 __attribute__((ext_vector_type(1)));
+template <int C> struct LaneVec;
+template <> struct LaneVec<4> { typedef v4i32 type; };
+template <> struct LaneVec<2> { typedef v2i32 type; };
+template <> struct LaneVec<1> { typedef v1i32 type; };
+typedef const __attribute__((address_space(1))) uint32_t gconst_u32;
+
+template <int C>
+__device__ __forceinline__ typename LaneVec<C>::type gload(const int32_t* p) {
+    typedef typename LaneVec<C>::type V;
+    return *(const __attribute__((address_space(1))) V*)p;
+}
+
+template <int C>
+__device__ __forceinline__ void gstore(int32_t* p, typename LaneVec<C>::type v) {
+    typedef typename LaneVec<C>::type V;
+    *(__attribute__((address_space(1))) V*)p = v;
+}
+
+// Issues the loads of row R of the strip: C activity values and the mask word
+// holding their bits.  Rows and columns outside the grid are clamped to a valid
+// address (the loads are unconditional, so they can stay in flight); the decode
+// in sweep_iter turns them into obstacles.
+template <int C>
+__device__ __forceinline__ void load_row(const MazeDev& md, const int32_t* Vin, int R,
+                                         int col, bool col_ok, typename LaneVec<C>::type& v,
+                                         uint32_t& w) {
+    const int Rc = min(max(R, 0), md.H - 1);
+    const int cc = col_ok ? col : 0;
+    v = gload<C>(Vin + (int64_t)Rc * md.pitch + cc);
+    w = *(gconst_u32*)(md.mask + (int64_t)Rc * md.mpitch + (cc >> 5));
+}
+
+// One row of the tile.  (v, w) holds row R, loaded one group (three rows)
+// earlier; it is decoded into stage 0's slot P (cells outside the grid become
+// exactly 0x80000000) and the same registers then receive the load of row
+// R + 3, whose latency overlaps the T-stage arithmetic of the next rows.
+template <int T, int P, int C, bool GUARD>
+__device__ __forceinline__ void sweep_iter(uint32_t (&st)[T][3][C], typename LaneVec<C>::type& v,
+                                           uint32_t& w, const MazeDev& md,
+                                           const int32_t* Vin, int32_t* Vout, int R, int r0, int r_end,
+                                           int col, bool col_ok, bool inner, int smax,
+                                           uint64_t& sum_in, uint64_t& sum_out) {
+    const bool ok = R >= 0 && R < md.H && col_ok;
+    const uint32_t keep = ok ? 0xffffffffu : 0u;
+    const uint32_t bits = ok ? (w >> (col & 31)) : 0xFu;   // outside the grid: obstacle
+    uint32_t* c = st[0][P];
+#pragma unroll
+    for (int j = 0; j < C; ++j) c[j] = ((uint32_t)v[j] & keep) | (((bits >> j) & 1u) << 31);
+    load_row<C>(md, Vin, R + 3, col, col_ok, v, w);
+    if (inner && R >= r0 && R < r_end) {
+        uint64_t t = 0;
+#pragma unroll
+        for (int j = 0; j < C; ++j) t += c[j] & 0x7fffffffu;
+        sum_in += t;
+    }
+    uint32_t out[C] = {};   // left 0 when the last stage is skipped (its row is not stored then)
+    sweep_row<T, P, C, GUARD>(st, out, smax);
+    const int Ro = R - T;
+    if (inner && Ro >= r0 && Ro < r_end) {
+        typename LaneVec<C>::type o;
+        uint64_t t = 0;
+#pragma unroll
+        for (int j = 0; j < C; ++j) {
+            o[j] = (int)(out[j] & 0x7fffffffu);
+            t += (uint32_t)o[j];
+        }
+        gstore<C>(Vout + (int64_t)Ro * md.pitch + col, o);
+        sum_out += t;
+    }
+}
+
+// Returns true (wave-uniform) if any interior cell of the tile changed.  The
+// wave streams the strip of 64*C columns starting T columns left of the tile.
+// In place (IN_PLACE) the tile reads and writes buffer `parity`: a row is
+// stored only after it and the T rows below it were loaded, so the visit never
+// reads its own output.
+template <int T, int C, bool IN_PLACE = false>
+__device__ bool sweep_tile(const MazeDev& md, int ty, int tx, int tile_rows, int parity) {
+    constexpr int TW = kLanes * C - 2 * T;
+    constexpr int HALO_LANES = T / C;
+    const int lane = lane_id();
+    const int r0 = ty * tile_rows;
+    const int r_end = min(r0 + tile_rows, md.H);
+    const int col = tx * TW - T + C * lane;
+    const bool col_ok = col >= 0 && col < md.pitch;
+    const bool inner = lane >= HALO_LANES && lane < kLanes - HALO_LANES && col < md.W;
+    int32_t* const Vin = parity ? md.V[1] : md.V[0];
+    int32_t* const Vout = IN_PLACE ? Vin : (parity ? md.V[0] : md.V[1]);
+
+    uint32_t st[T][3][C];
+#pragma unroll
+    for (int s = 0; s < T; ++s)
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+            for (int j = 0; j < C; ++j) st[s][k][j] = kObstacleBit;
+
+    uint64_t sum_in = 0, sum_out = 0;
+    const int n_iter = (r_end - r0) + 2 * T;   // rows r0-T .. r_end+T-1
+    typename LaneVec<C>::type v0, v1, v2;
+    uint32_t w0, w1, w2;
+    load_row<C>(md, Vin, r0 - T, col, col_ok, v0, w0);
+    load_row<C>(md, Vin, r0 - T + 1, col, col_ok, v1, w1);
+    load_row<C>(md, Vin, r0 - T + 2, col, col_ok, v2, w2);
+    // Stage s at step i (input row r0 - T + i) emits row r0 - T + i - 1 - s
+    // after s + 1 layers; the stored rows [r0, r_end) after T layers need
+    // exactly the emissions with i >= 2s + 2 (each of which reads only
+    // emissions of stage s - 1 with i - 2 >= 2(s - 1) + 2).  So during the
+    // first 2T steps, stages s > i/2 - 1 are skipped: the top of the tile's
+    // trapezoid, a third of the work of a tile with as many rows as layers.
+    constexpr int kWarm = 3 * ((2 * T + 2) / 3);   // >= 2T, a multiple of 3
+    int i = 0;
+#pragma unroll 1
+    for (; i < kWarm; i += 3) {
+        const int R = r0 - T + i;
+        sweep_iter<T, 0, C, true>(st, v0, w0, md, Vin, Vout, R, r0, r_end, col, col_ok, inner, (i >> 1) - 1,
+                                  sum_in, sum_out);
+        sweep_iter<T, 1, C, true>(st, v1, w1, md, Vin, Vout, R + 1, r0, r_end, col, col_ok, inner,
+                                  ((i + 1) >> 1) - 1, sum_in, sum_out);
+        sweep_iter<T, 2, C, true>(st, v2, w2, md, Vin, Vout, R + 2, r0, r_end, col, col_ok, inner,
+                                  ((i + 2) >> 1) - 1, sum_in, sum_out);
+    }
+#pragma unroll 1
+    for (; i < n_iter; i += 3) {
+        const int R = r0 - T + i;
+        sweep_iter<T, 0, C, false>(st, v0, w0, md, Vin, Vout, R, r0, r_end, col, col_ok, inner, 0, sum_in, sum_out);
+        sweep_iter<T, 1, C, false>(st, v1, w1, md, Vin, Vout, R + 1, r0, r_end, col, col_ok, inner, 0, sum_in,
+                                   sum_out);
+        sweep_iter<T, 2, C, false>(st, v2, w2, md, Vin, Vout, R + 2, r0, r_end, col, col_ok, inner, 0, sum_in,
+                                   sum_out);
+    }
+    return __ballot(sum_in != sum_out) != 0;
+}
+
+// Loads of scheduling data that another block may have written in an earlier
+// round of the same (persistent) launch: agent-scope atomic loads bypass the
+// per-CU caches.
+__device__ __forceinline__ int32_t load_shared(const int32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// The same for an 8-byte-aligned pair of int32 (low word first).
+__device__ __forceinline__ uint64_t load_shared64(const int32_t* p) {
+    return __hip_atomic_load(reinterpret_cast<const uint64_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Round r: every scheduled tile gets T layers.  Active schedule: the tiles of
+// a.list_in; a changed tile schedules itself and its 8 neighbour tiles for
+// round r+1.  Dense schedule: every tile of each maze that changed in round
+// r-1; a changed tile flags its maze for round r+1.  Block 0 also clears the
+// buffers round r+1 will fill.
+template <int T, int C>
+__device__ __forceinline__ void sweep_round(const RoundArgs& a) {
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = lane_id();
+    const int stride = a.wave_stride;
+    int i = blockIdx.x * kWavesPerBlock + wave;
+    // The first list entry is loaded before the count, so both round trips
+    // overlap (the entry is in bounds for any i below the tile id space, and
+    // used only if i < n).
+    uint64_t e = 0;
+    if (!a.dense && i < a.n_tile_ids) e = load_shared64(a.list_in + 2 * i);
+    const int n = a.dense ? a.n_tile_ids : __builtin_amdgcn_readfirstlane(load_shared(a.count_in));
+    if (blockIdx.x == 0) {
+        if (threadIdx.x == 0) *a.count_clear = 0;
+        for (int m = threadIdx.x; m < a.n_slots; m += kBlockThreads) {
+            a.sched_clear[m] = 0;
+            a.dchg_clear[m] = 0;
+        }
+    }
+    for (; i < n; i += stride) {
+        int g, slot;
+        if (a.dense) {
+            g = i;
+            slot = a.tile_maze[g];
+            if (slot < 0 || __builtin_amdgcn_readfirstlane(load_shared(a.dchg_prev + slot)) == 0) continue;
+        } else {
+            g = __builtin_amdgcn_readfirstlane((int)(uint32_t)e);
+            slot = __builtin_amdgcn_readfirstlane((int)(uint32_t)(e >> 32));
+            if (i + stride < n) e = load_shared64(a.list_in + 2 * (i + stride));
+            if (lane == 0) a.flags_in[g] = 0;
+        }
+        const MazeDev md = a.n_slots == 1 ? a.md0 : a.mazes[slot];
+        const int lt = g - md.tile_base;
+        const int ty = lt / md.tiles_x;
+        const int tx = lt - ty * md.tiles_x;
+        if (lane == 0) {
+            const unsigned long long cells =
+                (unsigned long long)tile_cells(md, ty, tx, a.tile_rows, a.tile_cols);
+            const int sp = blockIdx.x & (kSpread - 1);
+            atomicAdd(reinterpret_cast<unsigned long long*>(&a.maze_visits[slot * kSpread + sp]), 1ull);
+            atomicAdd(reinterpret_cast<unsigned long long*>(&a.maze_cell_visits[slot * kSpread + sp]), cells);
+            atomicAdd(a.total_cells + sp, cells);
+            if (a.maze_last_round[slot] != a.round_id) a.maze_last_round[slot] = a.round_id;
+            a.touched[g] = 1;
+        }
+        if (sweep_tile<T, C>(md, ty, tx, a.tile_rows, a.parity)) {
+            if (a.dense) {
+                if (lane == 0) {
+                    a.dchg_cur[slot] = 1;
+                    *a.count_out = 1;
+                }
+            } else {
+                schedule_neighbourhood(a, md, slot, ty, tx);
+            }
+        }
+    }
+}
+
+template <int T, int C>
+__global__ __launch_bounds__(kBlockThreads) void k_sweep(RoundArgs a) {
+    sweep_round<T, C>(a);
+}
+
+// Device-wide barrier of a cooperative launch (all blocks resident): the last
+// block to arrive resets the counter and advances the generation; the others
+// wait for the generation to change.  Fences on both sides publish this
+// block's writes and drop stale lines from the CU's caches.
+__device__ __forceinline__ void grid_barrier(unsigned int* count, unsigned int* gen) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned int g = __hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __threadfence();
+        if (atomicAdd(count, 1u) == gridDim.x - 1) {
+            __hip_atomic_store(count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __threadfence();
+            atomicAdd(gen, 1u);
+        } else {
+            while (__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g)
+                __builtin_amdgcn_s_sleep(1);
+        }
+    }
+    __syncthreads();
+    __threadfence();
+}
+
+// Up to p.max_rounds rounds in one cooperative launch, stopping after the
+// first round that schedules nothing (every resident maze converged).  The
+// stop test reads the round's final count after the barrier, so every block
+// takes the same decision.
+template <int T, int C>
+__global__ __launch_bounds__(kBlockThreads) void k_sweep_persistent(PersistentArgs p) {
+    int k = 0;
+    for (; k < p.max_rounds; ++k) {
+        RoundArgs a = p.base;
+        const int r = p.r0_mod6 + k;
+        const int r2 = r & 1, r3 = r % 3, n3 = (r3 + 1) % 3, nn3 = (r3 + 2) % 3;
+        const size_t cs = (size_t)p.base.n_slots;
+        a.list_in = p.list[r2];
+        a.count_in = p.count + r3;
+        a.flags_in = p.flags[r2];
+        a.list_out = p.list[r2 ^ 1];
+        a.count_out = p.count + n3;
+        a.flags_out = p.flags[r2 ^ 1];
+        a.count_clear = p.count + nn3;
+        a.sched_out = p.sched + n3 * cs;
+        a.sched_clear = p.sched + nn3 * cs;
+        a.dchg_prev = p.dchg + nn3 * cs;
+        a.dchg_cur = p.dchg + r3 * cs;
+        a.dchg_clear = p.dchg + n3 * cs;
+        a.round_id = p.base.round_id + k;
+        a.parity = r2;
+        sweep_round<T, C>(a);
+        grid_barrier(p.bar_count, p.bar_gen);
+        if (load_shared(a.count_out) == 0) {
+            ++k;
+            break;
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) *p.rounds_done = k;
+}
+
+// ---------------------------------------------------------------------------
+// asynchronous launch: a work queue instead of rounds
+// ---------------------------------------------------------------------------
+//
+// Tiles are visited in place, in any order, by waves that take them from a
+// ring of (slot, tile) entries.  A tile whose visit changed its interior marks
+// itself and its 8 neighbour tiles as needing a visit: an idle tile is pushed,
+// a tile being visited is flagged and pushed again when its visit ends (the
+// values that visit read may predate the change).  Because the update is
+// monotone and bounded by its fixpoint, values read while a neighbour is being
+// written are lower bounds, every visit only raises values, and the launch
+// reaches the same fixpoint bits as the round schedules once no tile needs a
+// visit.  Agent-scope release / acquire fences order a tile's stores before
+// the marks it makes and a visit's loads after the mark that queued it.
+
+// Marks `slot`'s tiles around (ty, tx) (lanes 0..8, one tile each); idle tiles
+// are counted as pending and pushed with one reservation for the whole wave.
+__device__ __forceinline__ void queue_mark_neighbourhood(const AsyncQueue& q, const MazeDev& md, int slot,
+                                                         int ty, int tx) {
+    const int lane = lane_id();
+    const int ny = ty + lane / 3 - 1, nx = tx + lane % 3 - 1;
+    const int g = md.tile_base + ny * md.tiles_x + nx;
+    bool won = false;
+    if (lane < 9 && ny >= 0 && ny < md.tiles_y && nx >= 0 && nx < md.tiles_x)
+        won = atomicOr(&q.state[g], 1) == 0;
+    const uint64_t mask = __ballot(won);
+    if (mask == 0) return;
+    const int n = __popcll(mask);
+    uint32_t base = 0;
+    if (lane == 0) {
+        // pending is raised before the entries can be taken: the second
+        // atomic's operand depends on the first one's result (p >= 0 always)
+        const int p = atomicAdd(q.pending, n);
+        base = atomicAdd(q.tail, (uint32_t)n + (uint32_t)(p < 0));
+    }
+    base = __builtin_amdgcn_readfirstlane(base);
+    if (won) {
+        const uint32_t k = base + (uint32_t)__popcll(mask & ((1ull << lane) - 1));
+        const unsigned long long e = ((unsigned long long)(uint32_t)slot << 32) | (uint32_t)(g + 1);
+        if (atomicCAS(q.ring + (k & q.ring_mask), 0ull, e) != 0ull) atomicAdd(q.error, 1);
+    }
+}
+
+template <int T, int C>
+__global__ __launch_bounds__(kBlockThreads) void k_sweep_async(RoundArgs a) {
+    const AsyncQueue& q = a.q;
+    const int lane = lane_id();
+    const unsigned long long t0 = wall_clock64();
+    for (;;) {
+        if (wall_clock64() - t0 > q.budget) break;          // pause: the host relaunches
+        uint32_t ticket = 0;
+        if (lane == 0) ticket = atomicAdd(q.head, 1u);
+        ticket = __builtin_amdgcn_readfirstlane(ticket);
+        unsigned long long* ep = q.ring + (ticket & q.ring_mask);
+        unsigned long long e = 0;
+        for (int poll = 0;; ++poll) {
+            e = __hip_atomic_load(ep, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            e = ((unsigned long long)__builtin_amdgcn_readfirstlane((uint32_t)(e >> 32)) << 32) |
+                __builtin_amdgcn_readfirstlane((uint32_t)e);
+            if (e != 0) break;
+            if ((poll & 7) == 7 && (__builtin_amdgcn_readfirstlane(load_shared(q.done)) != 0 ||
+                                    wall_clock64() - t0 > q.budget))
+                break;
+            __builtin_amdgcn_s_sleep(32);
+        }
+        if (e == 0) break;   // converged, or paused with this ticket unfilled
+        const int g = (int)(uint32_t)e - 1;
+        const int slot = (int)(e >> 32);
+        if (lane == 0) {
+            __hip_atomic_store(ep, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            atomicExch(&q.state[g], 2);                      // being visited; clears "needs a visit"
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        const MazeDev md = a.n_slots == 1 ? a.md0 : a.mazes[slot];
+        const int lt = g - md.tile_base;
+        const int ty = lt / md.tiles_x;
+        const int tx = lt - ty * md.tiles_x;
+        if (lane == 0) {
+            const unsigned long long cells =
+                (unsigned long long)tile_cells(md, ty, tx, a.tile_rows, a.tile_cols);
+            const int sp = blockIdx.x & (kSpread - 1);
+            atomicAdd(reinterpret_cast<unsigned long long*>(&a.maze_visits[slot * kSpread + sp]), 1ull);
+            atomicAdd(reinterpret_cast<unsigned long long*>(&a.maze_cell_visits[slot * kSpread + sp]), cells);
+            atomicAdd(a.total_cells + sp, cells);
+            a.touched[g] = 1;
+        }
+        const bool changed = sweep_tile<T, C, true>(md, ty, tx, a.tile_rows, a.parity);
+        // Every visit publishes its stores before it ends, changed or not: a
+        // store left dirty in this XCD's L2 could otherwise be written back
+        // after a later visit (on another XCD) stored larger values, and
+        // overwrite them.
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        if (changed) queue_mark_neighbourhood(q, md, slot, ty, tx);
+        if (lane == 0) {
+            const int old = atomicCAS(&q.state[g], 2, 0);
+            if (old == 2) {
+                if (atomicSub(q.pending, 1) == 1) __hip_atomic_store(q.done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            } else {
+                // marked while being visited: needs another visit (still pending)
+                atomicExch(&q.state[g], 1);
+                queue_push(q, g, slot);
+            }
+        }
+    }
+}
+
+// Launch functions of one variant (defined in its own translation unit).
+#define OMAP_DEFINE_SWEEP_VARIANT(t, c) OMAP_DEFINE_SWEEP_VARIANT_(t, c)
+#define OMAP_DEFINE_SWEEP_VARIANT_(t, c)                                                              \
+    hipError_t launch_sweep_T##t##_C##c(const RoundArgs& a, int32_t grid, hipStream_t s) {            \
+        RoundArgs b = a;                                                                              \
+        b.wave_stride = grid * kWavesPerBlock;                                                        \
+        hipLaunchKernelGGL((k_sweep<t, c>), dim3(grid), dim3(kBlockThreads), 0, s, b);               \
+        return hipGetLastError();                                                                     \
+    }                                                                                                 \
+    hipError_t launch_sweep_persistent_T##t##_C##c(const PersistentArgs& p, int32_t grid, hipStream_t s) { \
+        PersistentArgs q = p;                                                                         \
+        q.base.wave_stride = grid * kWavesPerBlock;                                                   \
+        void* args[] = {&q};                                                                          \
+        return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_sweep_persistent<t, c>),   \
+                                          dim3(grid), dim3(kBlockThreads), args, 0, s);               \
+    }                                                                                                 \
+    hipError_t launch_sweep_async_T##t##_C##c(const RoundArgs& a, int32_t grid, hipStream_t s) {      \
+        hipLaunchKernelGGL((k_sweep_async<t, c>), dim3(grid), dim3(kBlockThreads), 0, s, a);         \
+        return hipGetLastError();                                                                     \
+    }                                                                                                 \
+    int sweep_blocks_per_cu_T##t##_C##c(int kind) {                                                   \
+        int blocks = 0;                                                                               \
+        hipError_t e = kind == 0   ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_sweep<t, c>, kBlockThreads, 0) \
+                       : kind == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_sweep_persistent<t, c>, kBlockThreads, 0) \
+                                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_sweep_async<t, c>, kBlockThreads, 0); \
+        return e == hipSuccess ? blocks : 0;                                                          \
+    }
+
+}  // namespace omap

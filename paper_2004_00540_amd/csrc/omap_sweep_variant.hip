@@ -1,0 +1,14 @@
+// One tile-sweep variant: the kernels of omap_sweep.h instantiated for
+// OMAP_T layers per visit and OMAP_C columns per lane, and their launch
+// functions (the build compiles this file once per variant, in parallel).
+#include "omap_sweep.h"
+
+#if !defined(OMAP_T) || !defined(OMAP_C)
+#error "define OMAP_T and OMAP_C"
+#endif
+
+namespace omap {
+
+OMAP_DEFINE_SWEEP_VARIANT(OMAP_T, OMAP_C)
+
+}  // namespace omap

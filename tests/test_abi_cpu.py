@@ -76,7 +76,7 @@ def test_plan_create_null_out_and_bad_options():
     assert omap.STATUS[_create(5, 5, FAKE, [[0, 0]], [], out=False)] == "OMAP_ERR_INVALID_ARG"
     for bad in (omap.Options(3, 0, 0, 0, 0), omap.Options(0, 3, 0, 0, 0), omap.Options(0, 0, 7, 0, 0), omap.Options(0, 0, 0, 0, 0, 5), omap.Options(0, 0, 1, 0, 0, 2),
                 omap.Options(16, 8, 0, 0, 0), omap.Options(0, 0, 0, -1, 0), omap.Options(0, 0, 0, 0, 3),
-                omap.Options(24, 0, 0, 0, 4), omap.Options(32, 16, 0, 0, 2)):
+                omap.Options(24, 0, 0, 0, 4), omap.Options(32, 16, 0, 0, 2), omap.Options(24, 0, 0, 0, 1)):
         assert omap.STATUS[_create(5, 5, FAKE, [[0, 0]], [], opts=bad)] == "OMAP_ERR_INVALID_ARG"
 
 
@@ -126,3 +126,19 @@ def test_resolve_options_fills_defaults():
     assert omap.resolve_options(round_launch=omap.LAUNCH_ASYNC, async_budget_us=200)["async_budget_us"] == 200
     L = omap.lib()
     assert omap.STATUS[L.omap_resolve_options(None, None)] == "OMAP_ERR_INVALID_ARG"
+
+
+def test_build_lists_every_sweep_variant_once():
+    """The build compiles one object per sweep variant listed in the internal
+    header; the list has no duplicates and covers the documented options."""
+    import importlib.util
+    spec = importlib.util.spec_from_file_location(
+        "omap_build", os.path.join(ROOT, "paper_2004_00540_amd", "build.py"))
+    b = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(b)
+    v = b.variants()
+    assert len(v) == len(set(v))
+    for T in (4, 8, 12, 16):
+        for C in (1, 2, 4):
+            assert (T, C) in v
+    assert (24, 2) in v and (32, 2) in v

@@ -27,7 +27,7 @@ def test_selftest():
     omap.selftest()
 
 
-VARIANTS = [(T, 4) for T in ALL_T] + [(T, 2) for T in (4, 8, 12, 16, 24, 32)]
+VARIANTS = [(T, 4) for T in ALL_T] + [(T, 2) for T in (4, 8, 12, 16, 24, 32)] + [(T, 1) for T in ALL_T]
 
 
 @pytest.mark.parametrize("T,C", VARIANTS)
