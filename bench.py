@@ -115,14 +115,15 @@ def measured_traffic(workload: str, options: dict):
 
 
 def copy_probe(args):
-    """A plain device-to-device copy of 1 GiB (torch's copy kernel), run under
-    the same hardware counters as the sweep to calibrate the HBM byte counters."""
+    """A plain elementwise pass over 1 GiB (torch's negation kernel: 1 GiB read,
+    1 GiB written per launch), run under the same hardware counters as the
+    sweep to calibrate the HBM byte counters."""
     import torch
     n = 1 << 28
     src = torch.ones(n, dtype=torch.int32, device="cuda")
     dst = torch.empty_like(src)
     for _ in range(max(1, args.steps)):
-        dst.copy_(src)
+        torch.neg(src, out=dst)
     torch.cuda.synchronize()
     return {"metric": "copy_bytes", "value": 2 * 4 * n, "unit": "B", "read_bytes": 4 * n,
             "write_bytes": 4 * n, "launches": max(1, args.steps)}
@@ -145,7 +146,8 @@ def bench_plain(args):
     log(f"generated {m.name} in {time.perf_counter() - t0:.1f} s")
     occ = torch.from_numpy(m.occ).to(dev)
     N = m.H * m.W
-    opts = dict(temporal_depth=args.depth, tile_rows=args.tile_rows, schedule=args.schedule)
+    opts = dict(temporal_depth=args.depth, tile_rows=args.tile_rows, schedule=args.schedule,
+                lane_columns=args.lane_columns, round_launch=args.launch)
     stream = torch.cuda.current_stream()
     plan = omap.Plan(occ, m.sources, m.targets, **opts)
     nt = len(m.targets)
@@ -242,6 +244,8 @@ def main():
     ap.add_argument("--depth", type=int, default=0)
     ap.add_argument("--tile-rows", type=int, default=0)
     ap.add_argument("--schedule", type=int, default=0)
+    ap.add_argument("--lane-columns", type=int, default=0)
+    ap.add_argument("--launch", type=int, default=0, help="0 per round, 1 persistent, 2 asynchronous")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--serve-pool", type=int, default=48)

@@ -44,7 +44,8 @@ def bench_batch(args):
     occs = [torch.from_numpy(m.occ).to(dev) for m in mazes]
     cells = sum(m.H * m.W for m in mazes)
     n_tgt = sum(len(m.targets) for m in mazes)
-    opts = dict(temporal_depth=args.depth, tile_rows=args.tile_rows, schedule=args.schedule)
+    opts = dict(temporal_depth=args.depth, tile_rows=args.tile_rows, schedule=args.schedule,
+                lane_columns=args.lane_columns, round_launch=args.launch)
 
     def batched():
         with omap.Batch([(occs[i], m.sources, m.targets) for i, m in enumerate(mazes)], **opts) as b:
@@ -113,7 +114,8 @@ def bench_serve(args):
     _log(f"generated {n_pool} queries in {time.perf_counter() - t0:.1f} s; "
          f"mean cells {np.mean([q.H * q.W for q in pool]) / 1e6:.1f} M")
     dev = torch.device("cuda:0")
-    opts = dict(temporal_depth=args.depth, tile_rows=args.tile_rows, schedule=args.schedule)
+    opts = dict(temporal_depth=args.depth, tile_rows=args.tile_rows, schedule=args.schedule,
+                lane_columns=args.lane_columns, round_launch=args.launch)
     budget = int(args.serve_budget_gb * (1 << 30))
     seq = [pool[k % n_pool] for k in range(n_req)]
 

@@ -80,15 +80,17 @@ typedef enum omap_status {
  * result: activity maps and paths are identical bit for bit for every value. */
 typedef struct omap_options {
     int32_t temporal_depth;  /* layers applied per tile visit: 4, 8, 12, 16 (and 24, 32    */
-                             /* with lane_columns = 2); 0 = default (16)                   */
+                             /* with lane_columns = 2); 0 = default (plan, active: 12;     */
+                             /* batch, engine or dense: 16)                                */
     int32_t tile_rows;       /* interior rows per tile, even, 2..4096, >= temporal_depth;  */
-                             /* 0 = default (active: max(16, depth); dense: 256)           */
+                             /* 0 = default (plan, active, 1 column per lane: depth;       */
+                             /* other active: max(16, depth); dense: 256)                  */
     int32_t schedule;        /* OMAP_SCHEDULE_ACTIVE or OMAP_SCHEDULE_DENSE                 */
     int32_t check_interval;  /* rounds between host reads of the convergence count;        */
                              /* 0 = adaptive                                                */
     int32_t lane_columns;    /* columns each lane owns (tile strip = 64 x this): 1, 2 or   */
-                             /* 4 (1: temporal_depth 4..16); 0 = default (active: 2;       */
-                             /* dense: 4)                                                  */
+                             /* 4 (1: temporal_depth 4..16); 0 = default (plan, active: 1; */
+                             /* batch, engine: 2; dense: 4; the narrowest with the depth)  */
     int32_t round_launch;    /* OMAP_LAUNCH_PER_ROUND (default): one launch per round;     */
                              /* OMAP_LAUNCH_PERSISTENT: one cooperative launch runs rounds */
                              /* until convergence, separated by a device-wide barrier      */
@@ -107,9 +109,9 @@ typedef struct omap_options {
 #define OMAP_LAUNCH_PERSISTENT 1
 #define OMAP_LAUNCH_ASYNC 2
 
-/* The options a plan, batch or engine created with `options` (NULL = all
- * defaults) would run with: every zero field replaced by its default.  Host
- * only, no device call.  Returns OMAP_ERR_INVALID_ARG (and leaves *resolved
+/* The options a plan created with `options` (NULL = all defaults) would run
+ * with: every zero field replaced by its default (batches and engines default
+ * to other depth / column values, see above).  Host only, no device call.  Returns OMAP_ERR_INVALID_ARG (and leaves *resolved
  * untouched) for the same option values the create calls reject. */
 omap_status_t omap_resolve_options(const omap_options *options, omap_options *resolved);
 

@@ -21,7 +21,8 @@ from dataclasses import dataclass
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libomap.so")
+# OMAP_LIBRARY may name another build of the same library (e.g. for A/B timing)
+LIB_PATH = os.environ.get("OMAP_LIBRARY") or os.path.join(_HERE, "libomap.so")
 
 AUTO = -1
 SCHEDULE_ACTIVE = 0

@@ -73,15 +73,20 @@ struct Options {
     int budget_us = 50000;   // asynchronous launch: time taking new tiles per launch
 };
 
-// Defaults (measured on MI355X): the active schedule is latency-bound (few
-// tiles per round), so narrow strips (2 columns per lane) and short tiles keep
-// each tile visit short; the dense schedule is throughput-bound, so wide
-// strips (4 columns per lane) and tall tiles minimise halo work.
-static omap_status_t resolve_options(const omap_options* o, Options* out) {
+// Defaults (measured on MI355X).  A single maze under the active schedule is
+// latency-bound (a few hundred tiles per round on 1024 SIMDs): one column per
+// lane and 12 layers per visit keep each round short (23170^2 maze: 11.1 ms vs
+// 12.8 ms with 2 columns and 16 layers).  Many mazes at once (batch, engine)
+// fill the device, so 2 columns per lane and 16 layers waste less on halos
+// (512 mazes: 10.2k vs 9.0k mazes/s).  The dense schedule is throughput-bound:
+// 4 columns per lane and tall tiles.
+enum class Use { kPlan, kMany };
+static omap_status_t resolve_options(const omap_options* o, Options* out, Use use = Use::kPlan) {
     Options r;
     const bool dense = o && o->schedule == OMAP_SCHEDULE_DENSE;
-    r.C = dense ? 4 : 2;
-    r.T = 16;
+    const bool single = use == Use::kPlan;
+    r.C = dense ? 4 : (single ? 1 : 2);
+    r.T = dense ? 16 : (single ? 12 : 16);
     int th = 0;
     if (o) {
         if (o->lane_columns != 0) {
@@ -115,12 +120,17 @@ static omap_status_t resolve_options(const omap_options* o, Options* out) {
             r.budget_us = o->async_budget_us;
         }
     }
+    // a depth chosen without a column count takes the narrowest strip that has it
+    if ((!o || o->lane_columns == 0) && !sweep_supported(r.T, r.C)) {
+        if (sweep_supported(r.T, 2)) r.C = 2;
+        else if (sweep_supported(r.T, 4)) r.C = 4;
+    }
     if (!sweep_supported(r.T, r.C))
         return fail(OMAP_ERR_INVALID_ARG,
                     "temporal_depth %d is not available with %d columns per lane "
                     "(4, 8, 12, 16; with 2 columns also 24, 32)", r.T, r.C);
     // (with one column per lane the strip is 64 columns: 64 - 2T interior columns)
-    r.TH = th ? th : (dense ? 256 : std::max(16, r.T));
+    r.TH = th ? th : (dense ? 256 : (single && r.C == 1 ? r.T : std::max(16, r.T)));
     if (r.TH < r.T)
         return fail(OMAP_ERR_INVALID_ARG, "tile_rows (%d) must be >= temporal_depth (%d)", r.TH, r.T);
     r.TW = 64 * r.C - 2 * r.T;
@@ -1437,7 +1447,7 @@ omap_status_t omap_batch_create(omap_batch_t* out, const omap_maze_desc* mazes, 
     API_GUARD_BEGIN
     if (!out || !mazes || n_mazes < 1) return fail(OMAP_ERR_INVALID_ARG, "need out and n_mazes >= 1");
     Options o;
-    OK_TRY(resolve_options(opts, &o));
+    OK_TRY(resolve_options(opts, &o, Use::kMany));
     int64_t tiles = 0;
     for (int32_t i = 0; i < n_mazes; ++i) {
         const omap_maze_desc& d = mazes[i];
@@ -1558,7 +1568,7 @@ omap_status_t omap_engine_create(omap_engine_t* out, int64_t memory_budget_bytes
     if (!out || memory_budget_bytes < (1 << 20) || max_slots < 1)
         return fail(OMAP_ERR_INVALID_ARG, "need out, budget >= 1 MiB and max_slots >= 1");
     Options o;
-    OK_TRY(resolve_options(opts, &o));
+    OK_TRY(resolve_options(opts, &o, Use::kMany));
     o.async = 0;   // the engine advances mazes by whole rounds
     std::unique_ptr<omap_engine_s> e(new omap_engine_s());
     if (!e->mem.init((size_t)memory_budget_bytes))

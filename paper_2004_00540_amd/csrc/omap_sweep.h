@@ -303,12 +303,24 @@ __device__ __forceinline__ uint64_t load_shared64(const int32_t* p) {
     return __hip_atomic_load(reinterpret_cast<const uint64_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Scheduling data of round r: written by another block in the same launch
+// (persistent launch: coherent agent-scope loads) or by an earlier launch
+// (plain loads, which may hit in the L2).
+template <bool SHARED>
+__device__ __forceinline__ int32_t load_sched(const int32_t* p) {
+    return SHARED ? load_shared(p) : *p;
+}
+template <bool SHARED>
+__device__ __forceinline__ uint64_t load_sched64(const int32_t* p) {
+    return SHARED ? load_shared64(p) : *reinterpret_cast<const uint64_t*>(p);
+}
+
 // Round r: every scheduled tile gets T layers.  Active schedule: the tiles of
 // a.list_in; a changed tile schedules itself and its 8 neighbour tiles for
 // round r+1.  Dense schedule: every tile of each maze that changed in round
 // r-1; a changed tile flags its maze for round r+1.  Block 0 also clears the
 // buffers round r+1 will fill.
-template <int T, int C>
+template <int T, int C, bool SHARED>
 __device__ __forceinline__ void sweep_round(const RoundArgs& a) {
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = lane_id();
@@ -318,8 +330,8 @@ __device__ __forceinline__ void sweep_round(const RoundArgs& a) {
     // overlap (the entry is in bounds for any i below the tile id space, and
     // used only if i < n).
     uint64_t e = 0;
-    if (!a.dense && i < a.n_tile_ids) e = load_shared64(a.list_in + 2 * i);
-    const int n = a.dense ? a.n_tile_ids : __builtin_amdgcn_readfirstlane(load_shared(a.count_in));
+    if (!a.dense && i < a.n_tile_ids) e = load_sched64<SHARED>(a.list_in + 2 * i);
+    const int n = a.dense ? a.n_tile_ids : __builtin_amdgcn_readfirstlane(load_sched<SHARED>(a.count_in));
     if (blockIdx.x == 0) {
         if (threadIdx.x == 0) *a.count_clear = 0;
         for (int m = threadIdx.x; m < a.n_slots; m += kBlockThreads) {
@@ -332,11 +344,11 @@ __device__ __forceinline__ void sweep_round(const RoundArgs& a) {
         if (a.dense) {
             g = i;
             slot = a.tile_maze[g];
-            if (slot < 0 || __builtin_amdgcn_readfirstlane(load_shared(a.dchg_prev + slot)) == 0) continue;
+            if (slot < 0 || __builtin_amdgcn_readfirstlane(load_sched<SHARED>(a.dchg_prev + slot)) == 0) continue;
         } else {
             g = __builtin_amdgcn_readfirstlane((int)(uint32_t)e);
             slot = __builtin_amdgcn_readfirstlane((int)(uint32_t)(e >> 32));
-            if (i + stride < n) e = load_shared64(a.list_in + 2 * (i + stride));
+            if (i + stride < n) e = load_sched64<SHARED>(a.list_in + 2 * (i + stride));
             if (lane == 0) a.flags_in[g] = 0;
         }
         const MazeDev md = a.n_slots == 1 ? a.md0 : a.mazes[slot];
@@ -368,7 +380,7 @@ __device__ __forceinline__ void sweep_round(const RoundArgs& a) {
 
 template <int T, int C>
 __global__ __launch_bounds__(kBlockThreads) void k_sweep(RoundArgs a) {
-    sweep_round<T, C>(a);
+    sweep_round<T, C, false>(a);
 }
 
 // Device-wide barrier of a cooperative launch (all blocks resident): the last
@@ -419,7 +431,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_sweep_persistent(PersistentAr
         a.dchg_clear = p.dchg + n3 * cs;
         a.round_id = p.base.round_id + k;
         a.parity = r2;
-        sweep_round<T, C>(a);
+        sweep_round<T, C, true>(a);
         grid_barrier(p.bar_count, p.bar_gen);
         if (load_shared(a.count_out) == 0) {
             ++k;
