@@ -57,7 +57,7 @@ def cpu_info():
     return model, cores
 
 
-def cpu_baseline(m, budget_s: float = 12.0):
+def cpu_baseline(m, budget_s: float = 15.0):
     """The CPU oracle (literal network + simple path walk) on a bounded sample of
     the same maze: a full-width band of rows, a fixed number of layers chosen so
     the run takes about `budget_s` seconds on all host cores."""
@@ -70,10 +70,11 @@ def cpu_baseline(m, budget_s: float = 12.0):
     rng = np.random.default_rng(0)
     src = free[rng.integers(0, len(free), 16)].astype(np.int32)
     tgt = free[rng.integers(0, len(free), 256)].astype(np.int32)
+    oracle.layers(band, src, 4, threads=threads)          # warm the threads and pages
     t0 = time.perf_counter()
-    oracle.layers(band, src, 4, threads=threads)
-    t_probe = max(time.perf_counter() - t0, 1e-3) / 4
-    L = int(max(8, min(4096, budget_s / t_probe)))
+    oracle.layers(band, src, 32, threads=threads)
+    t_probe = max(time.perf_counter() - t0, 1e-3) / 32
+    L = int(max(8, min(8192, budget_s / t_probe)))
     t0 = time.perf_counter()
     A, _ = oracle.layers(band, src, L, threads=threads)
     t_layers = time.perf_counter() - t0
@@ -247,7 +248,7 @@ def main():
     ap.add_argument("--lane-columns", type=int, default=0)
     ap.add_argument("--launch", type=int, default=0, help="0 per round, 1 persistent, 2 asynchronous")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--serve-pool", type=int, default=48)
     ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--serve-budget-gb", type=float, default=64.0)

@@ -109,9 +109,11 @@ struct PersistentArgs {
     X(4, 1) X(8, 1) X(12, 1) X(16, 1)
 
 #define X(t, c)                                                                                       \
-    hipError_t launch_sweep_T##t##_C##c(const RoundArgs& a, int32_t grid, hipStream_t s);             \
+    hipError_t launch_sweep_T##t##_C##c(const RoundArgs& a, int32_t grid, hipStream_t s, hipEvent_t e0, \
+                                        hipEvent_t e1);                                               \
     hipError_t launch_sweep_persistent_T##t##_C##c(const PersistentArgs& p, int32_t grid, hipStream_t s); \
-    hipError_t launch_sweep_async_T##t##_C##c(const RoundArgs& a, int32_t grid, hipStream_t s);       \
+    hipError_t launch_sweep_async_T##t##_C##c(const RoundArgs& a, int32_t grid, hipStream_t s, hipEvent_t e0, \
+                                              hipEvent_t e1);                                         \
     int sweep_blocks_per_cu_T##t##_C##c(int kind);
 OMAP_SWEEP_VARIANTS(X)
 #undef X
@@ -128,7 +130,10 @@ hipError_t launch_seed(const RoundArgs& a, int32_t slot, const int32_t* src_rc, 
 hipError_t launch_check_sources(const uint32_t* mask, int32_t mpitch, const int32_t* src_rc,
                                 int32_t n_src, int32_t* bad_count, hipStream_t s);
 bool sweep_supported(int T, int C);
-hipError_t launch_sweep(int T, int C, const RoundArgs& a, int32_t grid, hipStream_t s);
+// e0 / e1 (optional, both or neither): events that record the kernel's own
+// start and end (hipExtLaunchKernel), for profiling.
+hipError_t launch_sweep(int T, int C, const RoundArgs& a, int32_t grid, hipStream_t s,
+                        hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 // Cooperative launch of up to p.max_rounds rounds (grid must fit co-resident).
 hipError_t launch_sweep_persistent(int T, int C, const PersistentArgs& p, int32_t grid, hipStream_t s);
 int sweep_persistent_blocks_per_cu(int T, int C);
@@ -137,7 +142,8 @@ int sweep_persistent_blocks_per_cu(int T, int C);
 // Asynchronous launch: waves take tiles from a.q until no tile needs a visit
 // (*a.q.done = 1) or the time budget is spent (tiles still queued stay in the
 // ring; launch_queue_compact then moves them to the ring's start).
-hipError_t launch_sweep_async(int T, int C, const RoundArgs& a, int32_t grid, hipStream_t s);
+hipError_t launch_sweep_async(int T, int C, const RoundArgs& a, int32_t grid, hipStream_t s,
+                              hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 hipError_t launch_queue_compact(const AsyncQueue& q, unsigned long long* tmp, uint32_t* tmp_count, hipStream_t s);
 int sweep_async_waves_per_cu(int T, int C);
 hipError_t launch_slot_reset(const RoundArgs& a, int32_t slot, hipStream_t s);

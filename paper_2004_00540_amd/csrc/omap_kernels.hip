@@ -258,9 +258,18 @@ __device__ __forceinline__ int dir_dc(int k) {
 // selects the largest value and, among equal values, the smallest k, which is
 // the first maximal neighbour in the fixed order.  Window cells outside the
 // grid read as -1, below every in-grid value.
-constexpr int kWinRows = 32;
-constexpr int kWinCols = 48;                   // 12 chunks of 4 columns
-constexpr int kWinSteps = 15;                  // the window reaches >= 15 cells from its start in every direction
+#ifndef OMAP_WALK_ROWS
+#define OMAP_WALK_ROWS 32
+#define OMAP_WALK_COLS 48
+#endif
+constexpr int kWinRows = OMAP_WALK_ROWS;
+constexpr int kWinCols = OMAP_WALK_COLS;       // a multiple of 4 (chunks of 4 columns)
+constexpr int kWinSteps = kWinRows / 2 - 1;    // steps per window
+// After k < kWinSteps steps from (kWinSteps, c - C0) with c - C0 in
+// [kWinSteps + 1, kWinSteps + 4], the 8 neighbours lie in rows 0 .. 2 kWinSteps
+// and columns 1 .. 2 kWinSteps + 4.
+static_assert(kWinRows >= 2 * kWinSteps + 1 && kWinCols >= 2 * kWinSteps + 5 && kWinCols % 4 == 0, "walk window");
+static_assert((kWinRows * kWinCols / 4) % kLanes == 0, "walk window chunks per lane");
 constexpr int kWinChunks = kWinRows * kWinCols / 4;
 constexpr int kWalkWaves = 4;
 // (dr + 1) | (dc + 1) << 2 of neighbour k in bits 4k..4k+3
@@ -299,8 +308,7 @@ __global__ __launch_bounds__(kLanes * kWalkWaves) void k_walk(
     if (lane == 0) cells[o] = r * md.W + c;
     ++o;
     for (int s = 0; s < steps;) {
-        // window rows r-15 .. r+16, columns C0 .. C0+47 with C0 = 4*floor((c-16)/4):
-        // after k <= 14 steps the 8 neighbours lie in rows 0..30, columns 1..34
+        // window rows r - kWinSteps .., columns C0 .. with C0 = 4 floor((c - kWinSteps - 1) / 4)
         const int R0 = r - kWinSteps, C0 = (c - (kWinSteps + 1)) & ~3;
 #pragma unroll
         for (int k = 0; k < kWinChunks / kLanes; ++k) {
@@ -589,9 +597,10 @@ hipError_t launch_slot_reset(const RoundArgs& a, int32_t slot, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_sweep(int T, int C, const RoundArgs& a, int32_t grid, hipStream_t s) {
+hipError_t launch_sweep(int T, int C, const RoundArgs& a, int32_t grid, hipStream_t s, hipEvent_t e0,
+                        hipEvent_t e1) {
 #define X(t, c) \
-    if (T == t && C == c) return launch_sweep_T##t##_C##c(a, grid, s);
+    if (T == t && C == c) return launch_sweep_T##t##_C##c(a, grid, s, e0, e1);
     OMAP_SWEEP_VARIANTS(X)
 #undef X
     return hipErrorInvalidValue;
@@ -605,9 +614,10 @@ hipError_t launch_sweep_persistent(int T, int C, const PersistentArgs& p, int32_
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_sweep_async(int T, int C, const RoundArgs& a, int32_t grid, hipStream_t s) {
+hipError_t launch_sweep_async(int T, int C, const RoundArgs& a, int32_t grid, hipStream_t s, hipEvent_t e0,
+                              hipEvent_t e1) {
 #define X(t, c) \
-    if (T == t && C == c) return launch_sweep_async_T##t##_C##c(a, grid, s);
+    if (T == t && C == c) return launch_sweep_async_T##t##_C##c(a, grid, s, e0, e1);
     OMAP_SWEEP_VARIANTS(X)
 #undef X
     return hipErrorInvalidValue;

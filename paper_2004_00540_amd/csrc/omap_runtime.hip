@@ -733,13 +733,9 @@ class Solver {
             if (prof) {
                 HIP_TRY(hipEventCreate(&ev.first));
                 HIP_TRY(hipEventCreate(&ev.second));
-                HIP_TRY(hipEventRecord(ev.first, stream));
             }
-            HIP_TRY(launch_sweep_async(opt.T, opt.C, a, agrid, stream));
-            if (prof) {
-                HIP_TRY(hipEventRecord(ev.second, stream));
-                prof_events.push_back(ev);
-            }
+            HIP_TRY(launch_sweep_async(opt.T, opt.C, a, agrid, stream, ev.first, ev.second));
+            if (prof) prof_events.push_back(ev);
             HIP_TRY(hipMemcpyAsync(h_pinned, d_qctl, 8 * sizeof(uint32_t), hipMemcpyDeviceToHost, stream));
             HIP_TRY(hipStreamSynchronize(stream));
             const int32_t pending = (int32_t)h_pinned[2], error = (int32_t)h_pinned[4];
@@ -776,11 +772,10 @@ class Solver {
         const RoundArgs a = round_args();
         if (prof) {
             std::pair<hipEvent_t, hipEvent_t> ev;
+            // the events record the kernel's own start and end timestamps
             HIP_TRY(hipEventCreate(&ev.first));
             HIP_TRY(hipEventCreate(&ev.second));
-            HIP_TRY(hipEventRecord(ev.first, stream));
-            HIP_TRY(launch_sweep(opt.T, opt.C, a, grid, stream));
-            HIP_TRY(hipEventRecord(ev.second, stream));
+            HIP_TRY(launch_sweep(opt.T, opt.C, a, grid, stream, ev.first, ev.second));
             prof_events.push_back(ev);
         } else {
             HIP_TRY(launch_sweep(opt.T, opt.C, a, grid, stream));

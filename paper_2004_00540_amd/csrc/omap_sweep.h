@@ -28,6 +28,8 @@
 
 #include "omap_internal.h"
 
+#include <hip/hip_ext.h>
+
 namespace omap {
 
 // ---------------------------------------------------------------------------
@@ -550,10 +552,14 @@ __global__ __launch_bounds__(kBlockThreads) void k_sweep_async(RoundArgs a) {
 // Launch functions of one variant (defined in its own translation unit).
 #define OMAP_DEFINE_SWEEP_VARIANT(t, c) OMAP_DEFINE_SWEEP_VARIANT_(t, c)
 #define OMAP_DEFINE_SWEEP_VARIANT_(t, c)                                                              \
-    hipError_t launch_sweep_T##t##_C##c(const RoundArgs& a, int32_t grid, hipStream_t s) {            \
+    hipError_t launch_sweep_T##t##_C##c(const RoundArgs& a, int32_t grid, hipStream_t s, hipEvent_t e0, \
+                                        hipEvent_t e1) {                                              \
         RoundArgs b = a;                                                                              \
         b.wave_stride = grid * kWavesPerBlock;                                                        \
-        hipLaunchKernelGGL((k_sweep<t, c>), dim3(grid), dim3(kBlockThreads), 0, s, b);               \
+        if (e0 != nullptr)                                                                            \
+            hipExtLaunchKernelGGL((k_sweep<t, c>), dim3(grid), dim3(kBlockThreads), 0, s, e0, e1, 0, b); \
+        else                                                                                          \
+            hipLaunchKernelGGL((k_sweep<t, c>), dim3(grid), dim3(kBlockThreads), 0, s, b);           \
         return hipGetLastError();                                                                     \
     }                                                                                                 \
     hipError_t launch_sweep_persistent_T##t##_C##c(const PersistentArgs& p, int32_t grid, hipStream_t s) { \
@@ -563,8 +569,12 @@ __global__ __launch_bounds__(kBlockThreads) void k_sweep_async(RoundArgs a) {
         return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_sweep_persistent<t, c>),   \
                                           dim3(grid), dim3(kBlockThreads), args, 0, s);               \
     }                                                                                                 \
-    hipError_t launch_sweep_async_T##t##_C##c(const RoundArgs& a, int32_t grid, hipStream_t s) {      \
-        hipLaunchKernelGGL((k_sweep_async<t, c>), dim3(grid), dim3(kBlockThreads), 0, s, a);         \
+    hipError_t launch_sweep_async_T##t##_C##c(const RoundArgs& a, int32_t grid, hipStream_t s, hipEvent_t e0, \
+                                              hipEvent_t e1) {                                        \
+        if (e0 != nullptr)                                                                            \
+            hipExtLaunchKernelGGL((k_sweep_async<t, c>), dim3(grid), dim3(kBlockThreads), 0, s, e0, e1, 0, a); \
+        else                                                                                          \
+            hipLaunchKernelGGL((k_sweep_async<t, c>), dim3(grid), dim3(kBlockThreads), 0, s, a);     \
         return hipGetLastError();                                                                     \
     }                                                                                                 \
     int sweep_blocks_per_cu_T##t##_C##c(int kind) {                                                   \
