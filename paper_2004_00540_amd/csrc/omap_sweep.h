@@ -73,33 +73,6 @@ __device__ __forceinline__ void schedule_tile(const RoundArgs& a, const MazeDev&
     }
 }
 
-// The same for the 3x3 tiles around (ty, tx), from a whole wave: lanes 0..8
-// claim one tile each, then a single atomic reserves the list entries of all
-// the lanes that won their claim.
-__device__ __forceinline__ void schedule_neighbourhood(const RoundArgs& a, const MazeDev& md, int slot,
-                                                       int ty, int tx) {
-    const int lane = lane_id();
-    const int ny = ty + lane / 3 - 1, nx = tx + lane % 3 - 1;
-    const int g = md.tile_base + ny * md.tiles_x + nx;
-    bool won = false;
-    if (lane < 9 && ny >= 0 && ny < md.tiles_y && nx >= 0 && nx < md.tiles_x)
-        won = atomicExch(&a.flags_out[g], 1) == 0;
-    const uint64_t mask = __ballot(won);
-    if (mask == 0) return;
-    const int n = __popcll(mask);
-    int base = 0;
-    if (lane == 0) {
-        base = atomicAdd(a.count_out, n);
-        if (a.n_slots > 1) atomicAdd(&a.sched_out[slot], n);
-    }
-    base = __builtin_amdgcn_readfirstlane(base);
-    if (won) {
-        const int k = base + __popcll(mask & ((1ull << lane) - 1));
-        a.list_out[2 * k] = g;
-        a.list_out[2 * k + 1] = slot;
-    }
-}
-
 // Pushes one tile, already counted as pending, onto the asynchronous work
 // queue (see k_sweep_async).  One lane.
 __device__ __forceinline__ void queue_push(const AsyncQueue& q, int g, int slot) {
@@ -322,6 +295,26 @@ __device__ __forceinline__ uint64_t load_sched64(const int32_t* p) {
 // round r+1.  Dense schedule: every tile of each maze that changed in round
 // r-1; a changed tile flags its maze for round r+1.  Block 0 also clears the
 // buffers round r+1 will fill.
+// Tile g of slot: visit counters, then T layers.  Returns true (wave-uniform)
+// if the interior changed; md, ty, tx describe the tile.
+template <int T, int C>
+__device__ __forceinline__ bool visit_tile(const RoundArgs& a, int g, int slot, MazeDev& md, int& ty, int& tx) {
+    md = a.n_slots == 1 ? a.md0 : a.mazes[slot];
+    const int lt = g - md.tile_base;
+    ty = lt / md.tiles_x;
+    tx = lt - ty * md.tiles_x;
+    if (lane_id() == 0) {
+        const unsigned long long cells = (unsigned long long)tile_cells(md, ty, tx, a.tile_rows, a.tile_cols);
+        const int sp = blockIdx.x & (kSpread - 1);
+        atomicAdd(reinterpret_cast<unsigned long long*>(&a.maze_visits[slot * kSpread + sp]), 1ull);
+        atomicAdd(reinterpret_cast<unsigned long long*>(&a.maze_cell_visits[slot * kSpread + sp]), cells);
+        atomicAdd(a.total_cells + sp, cells);
+        if (a.maze_last_round[slot] != a.round_id) a.maze_last_round[slot] = a.round_id;
+        a.touched[g] = 1;
+    }
+    return sweep_tile<T, C>(md, ty, tx, a.tile_rows, a.parity);
+}
+
 template <int T, int C, bool SHARED>
 __device__ __forceinline__ void sweep_round(const RoundArgs& a) {
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -341,41 +334,65 @@ __device__ __forceinline__ void sweep_round(const RoundArgs& a) {
             a.dchg_clear[m] = 0;
         }
     }
-    for (; i < n; i += stride) {
-        int g, slot;
-        if (a.dense) {
-            g = i;
-            slot = a.tile_maze[g];
+    if (a.dense) {
+        for (; i < n; i += stride) {
+            const int slot = a.tile_maze[i];
             if (slot < 0 || __builtin_amdgcn_readfirstlane(load_sched<SHARED>(a.dchg_prev + slot)) == 0) continue;
-        } else {
-            g = __builtin_amdgcn_readfirstlane((int)(uint32_t)e);
+            MazeDev md;
+            int ty, tx;
+            if (visit_tile<T, C>(a, i, slot, md, ty, tx) && lane == 0) {
+                a.dchg_cur[slot] = 1;
+                *a.count_out = 1;
+            }
+        }
+        return;
+    }
+    // Active schedule.  The waves of a block take list entries ib .. ib+3
+    // together, so that the tiles their changed tiles claim for the next
+    // round are reserved with one atomic per block (same-address atomics
+    // serialise device-wide).
+    __shared__ int s_cnt[2][kWavesPerBlock];
+    __shared__ int s_base[2];
+    int par = 0;
+    for (int ib = blockIdx.x * kWavesPerBlock; ib < n; ib += stride, par ^= 1) {
+        i = ib + wave;
+        int slot = 0, gn = 0;
+        bool won = false;
+        if (i < n) {
+            const int g = __builtin_amdgcn_readfirstlane((int)(uint32_t)e);
             slot = __builtin_amdgcn_readfirstlane((int)(uint32_t)(e >> 32));
             if (i + stride < n) e = load_sched64<SHARED>(a.list_in + 2 * (i + stride));
             if (lane == 0) a.flags_in[g] = 0;
-        }
-        const MazeDev md = a.n_slots == 1 ? a.md0 : a.mazes[slot];
-        const int lt = g - md.tile_base;
-        const int ty = lt / md.tiles_x;
-        const int tx = lt - ty * md.tiles_x;
-        if (lane == 0) {
-            const unsigned long long cells =
-                (unsigned long long)tile_cells(md, ty, tx, a.tile_rows, a.tile_cols);
-            const int sp = blockIdx.x & (kSpread - 1);
-            atomicAdd(reinterpret_cast<unsigned long long*>(&a.maze_visits[slot * kSpread + sp]), 1ull);
-            atomicAdd(reinterpret_cast<unsigned long long*>(&a.maze_cell_visits[slot * kSpread + sp]), cells);
-            atomicAdd(a.total_cells + sp, cells);
-            if (a.maze_last_round[slot] != a.round_id) a.maze_last_round[slot] = a.round_id;
-            a.touched[g] = 1;
-        }
-        if (sweep_tile<T, C>(md, ty, tx, a.tile_rows, a.parity)) {
-            if (a.dense) {
-                if (lane == 0) {
-                    a.dchg_cur[slot] = 1;
-                    *a.count_out = 1;
-                }
-            } else {
-                schedule_neighbourhood(a, md, slot, ty, tx);
+            MazeDev md;
+            int ty, tx;
+            if (visit_tile<T, C>(a, g, slot, md, ty, tx)) {
+                // lanes 0..8 claim the 3x3 tiles around (ty, tx) for the next round
+                const int ny = ty + lane / 3 - 1, nx = tx + lane % 3 - 1;
+                gn = md.tile_base + ny * md.tiles_x + nx;
+                if (lane < 9 && ny >= 0 && ny < md.tiles_y && nx >= 0 && nx < md.tiles_x)
+                    won = atomicExch(&a.flags_out[gn], 1) == 0;
             }
+        }
+        const uint64_t wmask = __ballot(won);
+        const int nwon = __popcll(wmask);
+        if (lane == 0) s_cnt[par][wave] = nwon;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int t = 0;
+#pragma unroll
+            for (int w = 0; w < kWavesPerBlock; ++w) t += s_cnt[par][w];
+            s_base[par] = t > 0 ? atomicAdd(a.count_out, t) : 0;
+        }
+        __syncthreads();
+        if (nwon > 0) {
+            int base = s_base[par];
+            for (int w = 0; w < wave; ++w) base += s_cnt[par][w];
+            if (won) {
+                const int k = base + __popcll(wmask & ((1ull << lane) - 1));
+                a.list_out[2 * k] = gn;
+                a.list_out[2 * k + 1] = slot;
+            }
+            if (a.n_slots > 1 && lane == 0) atomicAdd(&a.sched_out[slot], nwon);
         }
     }
 }
