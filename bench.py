@@ -57,7 +57,7 @@ def cpu_info():
     return model, cores
 
 
-def cpu_baseline(m, budget_s: float = 15.0):
+def cpu_baseline(m, budget_s: float = 25.0):
     """The CPU oracle (literal network + simple path walk) on a bounded sample of
     the same maze: a full-width band of rows, a fixed number of layers chosen so
     the run takes about `budget_s` seconds on all host cores."""
@@ -248,7 +248,7 @@ def main():
     ap.add_argument("--lane-columns", type=int, default=0)
     ap.add_argument("--launch", type=int, default=0, help="0 per round, 1 persistent, 2 asynchronous")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--cpu-budget", type=float, default=25.0)
     ap.add_argument("--serve-pool", type=int, default=48)
     ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--serve-budget-gb", type=float, default=64.0)

@@ -205,7 +205,7 @@ PAPER_CASES = [
 def bench_paper(args):
     """Empty n x n maps run for exactly L layers (the paper's output A_L), one
     source in the corner (the paper's worst case) or k seeded random sources;
-    timed with the dense and the active schedule."""
+    timed with the dense, the active and the bit-sliced schedule."""
     import torch
     import paper_2004_00540_amd as omap
     import workloads
@@ -221,7 +221,8 @@ def bench_paper(args):
             src = np.unique(np.stack([rc // n, rc % n], 1).astype(np.int32), axis=0)
         row = {"case": name, "n": n, "layers": L, "sources": int(len(src)),
                "paper_s": round(paper_s, 4), "paper_hw": hw}
-        for sched, label in ((omap.SCHEDULE_DENSE, "dense"), (omap.SCHEDULE_ACTIVE, "active")):
+        for sched, label in ((omap.SCHEDULE_DENSE, "dense"), (omap.SCHEDULE_ACTIVE, "active"),
+                             (omap.SCHEDULE_BITS, "bits")):
             with omap.Plan(occ, src, None, schedule=sched, temporal_depth=args.depth,
                            tile_rows=args.tile_rows) as plan:
                 plan.propagate(L)

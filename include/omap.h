@@ -75,6 +75,9 @@ typedef enum omap_status {
 /* Schedules of tile visits (see omap_options.schedule). */
 #define OMAP_SCHEDULE_ACTIVE 0   /* visit a tile only while it or a neighbour changed */
 #define OMAP_SCHEDULE_DENSE 1    /* visit every tile of a maze until the maze stops changing */
+#define OMAP_SCHEDULE_BITS 2     /* active schedule on a bit-packed reached set instead of      */
+                                 /* int32 activity: same results; temporal_depth 8 or 16,      */
+                                 /* one launch per round, lane_columns 0                       */
 
 /* Execution options.  Zero-initialised = tuned defaults.  No option changes a
  * result: activity maps and paths are identical bit for bit for every value. */

@@ -27,6 +27,7 @@ LIB_PATH = os.environ.get("OMAP_LIBRARY") or os.path.join(_HERE, "libomap.so")
 AUTO = -1
 SCHEDULE_ACTIVE = 0
 SCHEDULE_DENSE = 1
+SCHEDULE_BITS = 2
 QUERY_QUEUED, QUERY_RUNNING, QUERY_DONE, QUERY_FAILED = 0, 1, 2, 3
 
 STATUS = {

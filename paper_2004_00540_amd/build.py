@@ -40,6 +40,13 @@ def variants() -> list:
     return [(int(t), int(c)) for t, c in re.findall(r"X\((\d+),\s*(\d+)\)", body)]
 
 
+def bits_variants() -> list:
+    """Layers per visit of the bit-sliced variants, as listed in omap_internal.h."""
+    text = open(os.path.join(CSRC, "omap_internal.h")).read()
+    line = text[text.index("#define OMAP_BITS_VARIANTS(X)"):].split("\n", 1)[0]
+    return [int(t) for t in re.findall(r"X\((\d+)\)", line)]
+
+
 def _compile_jobs(build_dir):
     jobs = []
     for src in SOURCES:
@@ -48,6 +55,9 @@ def _compile_jobs(build_dir):
     for t, c in variants():
         obj = os.path.join(build_dir, f"sweep_T{t}_C{c}.o")
         jobs.append(([f"-DOMAP_T={t}", f"-DOMAP_C={c}", os.path.join(CSRC, "omap_sweep_variant.hip")], obj))
+    for t in bits_variants():
+        obj = os.path.join(build_dir, f"bits_T{t}.o")
+        jobs.append(([f"-DOMAP_BITS_T={t}", os.path.join(CSRC, "omap_bits_variant.hip")], obj))
     return jobs
 
 

@@ -14,6 +14,9 @@ constexpr uint32_t kObstacleBit = 0x80000000u;      // in-register obstacle mark
 // kSpread) so that concurrent waves do not serialise on one address; readers
 // sum the copies.
 constexpr int kSpread = 16;
+// Interior columns of a bit-sliced tile: 64 lanes x 32 bits minus one halo
+// word on each side.
+constexpr int kBitsTileColumns = (kLanes - 2) * 32;
 
 // Maze state on the device.  Activity rows are `pitch` int32 apart (pitch a
 // multiple of 64, so rows are 256-byte aligned); the obstacle mask has one bit
@@ -28,6 +31,8 @@ struct MazeDev {
     int32_t K;              // source level of the encoding
     int32_t* V[2];          // activity ping-pong
     const uint32_t* mask;
+    uint32_t* R[2];         // bit-sliced schedule: reached-set planes (mask layout), else null
+    int32_t round0;         // bit-sliced schedule: index of the maze's first round
 };
 
 // Work queue of the asynchronous launch.  A tile id is in the ring at most
@@ -118,6 +123,15 @@ struct PersistentArgs {
 OMAP_SWEEP_VARIANTS(X)
 #undef X
 
+// Bit-sliced variants (layers per visit); omap_bits_variant.hip with OMAP_BITS_T.
+#define OMAP_BITS_VARIANTS(X) X(8) X(16)
+
+#define X(t)                                                                                          \
+    hipError_t launch_bits_T##t(const RoundArgs& a, int32_t grid, hipStream_t s, hipEvent_t e0, hipEvent_t e1); \
+    int bits_blocks_per_cu_T##t();
+OMAP_BITS_VARIANTS(X)
+#undef X
+
 // ---- launch wrappers (omap_kernels.hip) -------------------------------------
 hipError_t launch_pack_mask(const uint8_t* occ, int32_t H, int32_t W, uint32_t* mask,
                             int32_t mpitch, hipStream_t s);
@@ -144,6 +158,10 @@ int sweep_persistent_blocks_per_cu(int T, int C);
 // ring; launch_queue_compact then moves them to the ring's start).
 hipError_t launch_sweep_async(int T, int C, const RoundArgs& a, int32_t grid, hipStream_t s,
                               hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+bool bits_supported(int T);
+int bits_max_waves_per_cu(int T);
+hipError_t launch_bits(int T, const RoundArgs& a, int32_t grid, hipStream_t s, hipEvent_t e0 = nullptr,
+                       hipEvent_t e1 = nullptr);
 hipError_t launch_queue_compact(const AsyncQueue& q, unsigned long long* tmp, uint32_t* tmp_count, hipStream_t s);
 int sweep_async_waves_per_cu(int T, int C);
 hipError_t launch_slot_reset(const RoundArgs& a, int32_t slot, hipStream_t s);

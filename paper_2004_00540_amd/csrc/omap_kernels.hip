@@ -69,6 +69,11 @@ __global__ void k_seed(RoundArgs a, int32_t slot, const int32_t* __restrict__ sr
     const int64_t x = (int64_t)r * md.pitch + c;
     md.V[0][x] = md.K;
     md.V[1][x] = md.K;
+    if (md.R[0] != nullptr) {   // bit-sliced schedule: the source is in R_0 (both planes)
+        const int64_t wx = (int64_t)r * md.mpitch + (c >> 5);
+        atomicOr(&md.R[0][wx], 1u << (c & 31));
+        atomicOr(&md.R[1][wx], 1u << (c & 31));
+    }
     const int ty = r / a.tile_rows, tx = c / a.tile_cols;
     a.touched[md.tile_base + ty * md.tiles_x + tx] = 1;
     if (!schedule) return;
@@ -641,6 +646,28 @@ int sweep_max_waves_per_cu(int T, int C) {
 int sweep_async_waves_per_cu(int T, int C) {
     const int b = sweep_blocks_per_cu(T, C, 2);
     return (b > 1 ? b : 1) * kWavesPerBlock;
+}
+
+bool bits_supported(int T) {
+#define X(t) if (T == t) return true;
+    OMAP_BITS_VARIANTS(X)
+#undef X
+    return false;
+}
+
+int bits_max_waves_per_cu(int T) {
+    int b = 0;
+#define X(t) if (T == t) b = bits_blocks_per_cu_T##t();
+    OMAP_BITS_VARIANTS(X)
+#undef X
+    return (b > 1 ? b : 1) * kWavesPerBlock;
+}
+
+hipError_t launch_bits(int T, const RoundArgs& a, int32_t grid, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+#define X(t) if (T == t) return launch_bits_T##t(a, grid, s, e0, e1);
+    OMAP_BITS_VARIANTS(X)
+#undef X
+    return hipErrorInvalidValue;
 }
 
 bool sweep_supported(int T, int C) {

@@ -70,6 +70,7 @@ struct Options {
     int check = 0;       // 0 = adaptive
     int per_round = 1;   // 0 = one persistent launch instead of one launch per round
     int async = 0;       // 1 = asynchronous work-queue launch (active schedule only)
+    int bits = 0;        // 1 = bit-sliced reached-set schedule (C unused; TW = 1984)
     int budget_us = 50000;   // asynchronous launch: time taking new tiles per launch
 };
 
@@ -84,6 +85,7 @@ enum class Use { kPlan, kMany };
 static omap_status_t resolve_options(const omap_options* o, Options* out, Use use = Use::kPlan) {
     Options r;
     const bool dense = o && o->schedule == OMAP_SCHEDULE_DENSE;
+    const bool bits = o && o->schedule == OMAP_SCHEDULE_BITS;
     const bool single = use == Use::kPlan;
     r.C = dense ? 4 : (single ? 1 : 2);
     r.T = dense ? 16 : (single ? 12 : 16);
@@ -101,8 +103,9 @@ static omap_status_t resolve_options(const omap_options* o, Options* out, Use us
                             o->tile_rows);
             th = o->tile_rows;
         }
-        if (o->schedule != OMAP_SCHEDULE_ACTIVE && o->schedule != OMAP_SCHEDULE_DENSE)
-            return fail(OMAP_ERR_INVALID_ARG, "schedule must be ACTIVE or DENSE (got %d)", o->schedule);
+        if (o->schedule != OMAP_SCHEDULE_ACTIVE && o->schedule != OMAP_SCHEDULE_DENSE &&
+            o->schedule != OMAP_SCHEDULE_BITS)
+            return fail(OMAP_ERR_INVALID_ARG, "schedule must be ACTIVE, DENSE or BITS (got %d)", o->schedule);
         r.dense = dense;
         if (o->check_interval < 0) return fail(OMAP_ERR_INVALID_ARG, "check_interval < 0");
         r.check = o->check_interval;
@@ -119,6 +122,25 @@ static omap_status_t resolve_options(const omap_options* o, Options* out, Use us
                 return fail(OMAP_ERR_INVALID_ARG, "async_budget_us must be 0 or >= 10 (got %d)", o->async_budget_us);
             r.budget_us = o->async_budget_us;
         }
+    }
+    if (bits) {
+        // bit-sliced: 32 columns per lane, one halo word per side; rounds only
+        if (o->round_launch != OMAP_LAUNCH_PER_ROUND)
+            return fail(OMAP_ERR_INVALID_ARG, "the bit-sliced schedule runs one launch per round");
+        if (o->lane_columns != 0) return fail(OMAP_ERR_INVALID_ARG, "lane_columns must be 0 with the bit-sliced schedule");
+        r.bits = 1;
+        r.dense = 0;
+        r.C = 32;
+        if (o->temporal_depth == 0) r.T = 16;
+        if (!bits_supported(r.T))
+            return fail(OMAP_ERR_INVALID_ARG, "temporal_depth %d is not available with the bit-sliced schedule (8, 16)",
+                        r.T);
+        r.TH = th ? th : std::max(16, r.T);
+        if (r.TH < r.T)
+            return fail(OMAP_ERR_INVALID_ARG, "tile_rows (%d) must be >= temporal_depth (%d)", r.TH, r.T);
+        r.TW = kBitsTileColumns;
+        *out = r;
+        return OMAP_OK;
     }
     // a depth chosen without a column count takes the narrowest strip that has it
     if ((!o || o->lane_columns == 0) && !sweep_supported(r.T, r.C)) {
@@ -237,6 +259,7 @@ class ArenaMemory : public DeviceMemory {
 struct Geometry {
     int32_t H, W, pitch, mpitch, tiles_x, tiles_y;
     int64_t v_bytes, m_bytes;
+    bool bits;                  // reached-set planes (m_bytes each) are needed
 };
 
 static Geometry make_geometry(int32_t H, int32_t W, const Options& o) {
@@ -249,12 +272,13 @@ static Geometry make_geometry(int32_t H, int32_t W, const Options& o) {
     g.tiles_y = (H + o.TH - 1) / o.TH;
     g.v_bytes = (int64_t)g.pitch * H * 4;
     g.m_bytes = (int64_t)g.mpitch * H * 4;
+    g.bits = o.bits != 0;
     return g;
 }
 
 static int64_t maze_device_bytes(int32_t H, int32_t W, const Options& o) {
     const Geometry g = make_geometry(H, W, o);
-    return 2 * g.v_bytes + g.m_bytes + 4096;
+    return 2 * g.v_bytes + (g.bits ? 3 : 1) * g.m_bytes + 4096;
 }
 
 static omap_status_t validate_problem(int32_t H, int32_t W, const void* occ,
@@ -289,6 +313,7 @@ struct Slot {
     int32_t tile_base = 0, n_tiles = 0;
     int32_t* V[2] = {nullptr, nullptr};
     uint32_t* mask = nullptr;
+    uint32_t* R[2] = {nullptr, nullptr};   // bit-sliced schedule only
     int32_t* d_src = nullptr;
     std::vector<int32_t> src, tgt;
     int32_t K = 0;
@@ -437,13 +462,13 @@ class Solver {
         HIP_TRY(hipGetDevice(&dev));
         int cus = 0;
         HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-        const int waves = sweep_max_waves_per_cu(opt.T, opt.C);
+        const int waves = opt.bits ? bits_max_waves_per_cu(opt.T) : sweep_max_waves_per_cu(opt.T, opt.C);
         grid = std::max(1, cus * std::max(1, waves / kWavesPerBlock));
         const int need = (cap_tiles + kWavesPerBlock - 1) / kWavesPerBlock;
         grid = std::max(1, std::min(grid, need));
         int coop = 0;
         HIP_TRY(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
-        const int per_cu = sweep_persistent_blocks_per_cu(opt.T, opt.C);
+        const int per_cu = opt.bits ? 0 : sweep_persistent_blocks_per_cu(opt.T, opt.C);
         pgrid = (coop && per_cu > 0) ? std::max(1, std::min(cus * per_cu, need)) : 0;
         if (opt.async) {
             const int64_t waves = (int64_t)cus * std::min(8, sweep_async_waves_per_cu(opt.T, opt.C));
@@ -516,7 +541,10 @@ class Solver {
         mem->release(s.V[1]);
         mem->release(s.mask);
         mem->release(s.d_src);
+        if (s.R[0]) mem->release(s.R[0]);
+        if (s.R[1]) mem->release(s.R[1]);
         s.V[0] = s.V[1] = nullptr;
+        s.R[0] = s.R[1] = nullptr;
         s.mask = nullptr;
         s.d_src = nullptr;
     }
@@ -537,6 +565,9 @@ class Solver {
         md.V[0] = s.V[0];
         md.V[1] = s.V[1];
         md.mask = s.mask;
+        md.R[0] = s.R[0];
+        md.R[1] = s.R[1];
+        md.round0 = (int32_t)s.first_round;
         HIP_TRY(hipMemcpyAsync(d_mazes + k, &md, sizeof md, hipMemcpyHostToDevice, stream));
         return OMAP_OK;
     }
@@ -649,7 +680,11 @@ class Solver {
         s.V[0] = static_cast<int32_t*>(mem->alloc(s.g.v_bytes));
         s.V[1] = static_cast<int32_t*>(mem->alloc(s.g.v_bytes));
         s.mask = static_cast<uint32_t*>(mem->alloc(s.g.m_bytes));
-        if (!s.V[0] || !s.V[1] || !s.mask) {
+        if (s.g.bits) {
+            s.R[0] = static_cast<uint32_t*>(mem->alloc(s.g.m_bytes));
+            s.R[1] = static_cast<uint32_t*>(mem->alloc(s.g.m_bytes));
+        }
+        if (!s.V[0] || !s.V[1] || !s.mask || (s.g.bits && (!s.R[0] || !s.R[1]))) {
             remove(k);
             return fail(OMAP_ERR_OUT_OF_MEMORY, "activity and mask buffers for %d x %d", H, W);
         }
@@ -693,7 +728,12 @@ class Solver {
             return fail(OMAP_ERR_TOO_LARGE, "L + 1 = %lld does not fit int32 activity", (long long)(L + 1));
         s.L_req = L;
         s.K = L < 0 ? 0x7fffffff : (int32_t)(L + 1);
+        s.first_round = next_round;
         OK_TRY(upload_desc(k));
+        if (s.g.bits) {   // R_0 = the sources, set by the seeds below
+            HIP_TRY(launch_fill(reinterpret_cast<int32_t*>(s.R[0]), s.g.m_bytes / 4, 0, stream));
+            HIP_TRY(launch_fill(reinterpret_cast<int32_t*>(s.R[1]), s.g.m_bytes / 4, 0, stream));
+        }
         const RoundArgs a = round_args(true);
         if (s.cleared) {
             HIP_TRY(launch_clear_touched(a, k, s.n_tiles, stream));
@@ -775,8 +815,11 @@ class Solver {
             // the events record the kernel's own start and end timestamps
             HIP_TRY(hipEventCreate(&ev.first));
             HIP_TRY(hipEventCreate(&ev.second));
-            HIP_TRY(launch_sweep(opt.T, opt.C, a, grid, stream, ev.first, ev.second));
+            if (opt.bits) HIP_TRY(launch_bits(opt.T, a, grid, stream, ev.first, ev.second));
+            else HIP_TRY(launch_sweep(opt.T, opt.C, a, grid, stream, ev.first, ev.second));
             prof_events.push_back(ev);
+        } else if (opt.bits) {
+            HIP_TRY(launch_bits(opt.T, a, grid, stream));
         } else {
             HIP_TRY(launch_sweep(opt.T, opt.C, a, grid, stream));
         }
@@ -1300,9 +1343,9 @@ omap_status_t omap_resolve_options(const omap_options* options, omap_options* re
     OK_TRY(resolve_options(options, &r));
     resolved->temporal_depth = r.T;
     resolved->tile_rows = r.TH;
-    resolved->schedule = r.dense ? OMAP_SCHEDULE_DENSE : OMAP_SCHEDULE_ACTIVE;
+    resolved->schedule = r.bits ? OMAP_SCHEDULE_BITS : (r.dense ? OMAP_SCHEDULE_DENSE : OMAP_SCHEDULE_ACTIVE);
     resolved->check_interval = r.check;
-    resolved->lane_columns = r.C;
+    resolved->lane_columns = r.bits ? 0 : r.C;
     resolved->round_launch =
         r.async ? OMAP_LAUNCH_ASYNC : (r.per_round ? OMAP_LAUNCH_PER_ROUND : OMAP_LAUNCH_PERSISTENT);
     resolved->async_budget_us = r.budget_us;

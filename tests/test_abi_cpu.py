@@ -126,6 +126,12 @@ def test_resolve_options_fills_defaults():
     with pytest.raises(omap.OmapError):
         omap.resolve_options(round_launch=omap.LAUNCH_ASYNC, async_budget_us=5)
     assert omap.resolve_options(round_launch=omap.LAUNCH_ASYNC, async_budget_us=200)["async_budget_us"] == 200
+    d = omap.resolve_options(schedule=omap.SCHEDULE_BITS)
+    assert (d["schedule"], d["temporal_depth"], d["tile_rows"], d["lane_columns"]) == (omap.SCHEDULE_BITS, 16, 16, 0)
+    for bad in (dict(temporal_depth=12), dict(lane_columns=2), dict(round_launch=omap.LAUNCH_ASYNC),
+                dict(round_launch=omap.LAUNCH_PERSISTENT), dict(temporal_depth=16, tile_rows=8)):
+        with pytest.raises(omap.OmapError):
+            omap.resolve_options(schedule=omap.SCHEDULE_BITS, **bad)
     L = omap.lib()
     assert omap.STATUS[L.omap_resolve_options(None, None)] == "OMAP_ERR_INVALID_ARG"
 
