@@ -8,7 +8,8 @@
 // one bit per cell: R_0 = sources and R_{n+1} = free AND dilate3x3(R_n), so a
 // layer costs a few bitwise operations per 32 cells and about 3 bits of
 // traffic per cell (R in, free mask, R out) instead of 8.125 bytes.  A cell
-// entering R at layer n gets V = K - n written once (4 B per reached cell);
+// entering R at layer n gets V = K - n written once (4 B per reached cell, in
+// activity buffer 0);
 // V is then exactly what the integer sweeps produce, and everything after
 // propagation (run-time L, copy-out, paths) is shared.
 //
@@ -55,14 +56,14 @@ __device__ __forceinline__ void bits_row(uint32_t (&r)[T][3], uint32_t (&f)[T][3
 }
 
 // Writes V = K - n for the bits of `m` (interior cells of row `row`, word
-// `word`) that entered R at layer n.
+// `word`) that entered R at layer n, into activity buffer 0 (the one the
+// runtime reads for this schedule).
 __device__ __forceinline__ void bits_write_v(const MazeDev& md, int row, int word, uint32_t m, int32_t val) {
+    int32_t* const v = md.V[0] + (int64_t)row * md.pitch + word * 32;
     while (m != 0) {
         const int b = __builtin_ctz(m);
         m &= m - 1;
-        const int64_t x = (int64_t)row * md.pitch + word * 32 + b;
-        md.V[0][x] = val;
-        md.V[1][x] = val;
+        v[b] = val;
     }
 }
 

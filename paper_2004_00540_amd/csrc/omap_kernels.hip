@@ -35,12 +35,15 @@ __global__ void k_pack_mask(const uint8_t* __restrict__ occ, int32_t H, int32_t 
     }
 }
 
-__global__ void k_fill(int32_t* __restrict__ p, int64_t n4, int32_t value) {
+// p[0 .. n) := value (int4 stores, then the last n mod 4 elements).
+__global__ void k_fill(int32_t* __restrict__ p, int64_t n, int32_t value) {
+    const int64_t n4 = n / 4;
     int4 v = make_int4(value, value, value, value);
     int4* q = reinterpret_cast<int4*>(p);
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4;
          i += (int64_t)gridDim.x * blockDim.x)
         q[i] = v;
+    if (blockIdx.x == 0 && threadIdx.x < (unsigned)(n - 4 * n4)) p[4 * n4 + threadIdx.x] = value;
 }
 
 __global__ void k_check_sources(const uint32_t* __restrict__ mask, int32_t mpitch,
@@ -578,8 +581,9 @@ hipError_t launch_pack_mask(const uint8_t* occ, int32_t H, int32_t W, uint32_t* 
 }
 
 hipError_t launch_fill(int32_t* p, int64_t n_elems, int32_t value, hipStream_t s) {
-    const int64_t n4 = n_elems / 4;   // callers pass multiples of 4
-    hipLaunchKernelGGL(k_fill, dim3(grid_for(n4, 256, 65536)), dim3(256), 0, s, p, n4, value);
+    if (n_elems <= 0) return hipSuccess;
+    const int64_t n4 = n_elems / 4;
+    hipLaunchKernelGGL(k_fill, dim3(grid_for(n4 > 0 ? n4 : 1, 256, 65536)), dim3(256), 0, s, p, n_elems, value);
     return hipGetLastError();
 }
 

@@ -875,6 +875,11 @@ class Solver {
 
     bool use_persistent() const { return pgrid > 0 && !opt.per_round; }
 
+    // Activity buffer holding the latest values: the round parity, except for
+    // the bit-sliced schedule, which writes each reached cell's value once,
+    // into buffer 0.
+    int vparity() const { return opt.bits ? 0 : parity; }
+
     // `rounds` rounds (fewer if everything converges first with the
     // persistent launch).
     omap_status_t run_rounds(int32_t rounds) {
@@ -922,7 +927,7 @@ class Solver {
             lo = std::min(lo, slots[k].tile_base);
             hi = std::max(hi, slots[k].tile_base + slots[k].n_tiles);
         }
-        HIP_TRY(launch_reduce(d_mazes, d_tile_maze, d_touched, lo, hi, d_sel, opt.TH, opt.TW, parity, d_min,
+        HIP_TRY(launch_reduce(d_mazes, d_tile_maze, d_touched, lo, hi, d_sel, opt.TH, opt.TW, vparity(), d_min,
                               d_reached, stream));
         std::vector<unsigned long long> reached(cap_slots);
         HIP_TRY(hipMemcpyAsync(mins.data(), d_min, sizeof(int32_t) * cap_slots, hipMemcpyDeviceToHost, stream));
@@ -1055,9 +1060,9 @@ class Solver {
                                            hipMemcpyHostToDevice, stream));
                 }
                 if (mode == 2)
-                    HIP_TRY(launch_walk_euclid(false, d_mazes, d.tslot, d.trc, n, parity, d.len, nullptr, nullptr, stream));
+                    HIP_TRY(launch_walk_euclid(false, d_mazes, d.tslot, d.trc, n, vparity(), d.len, nullptr, nullptr, stream));
                 else
-                    HIP_TRY(launch_path_lengths(d_mazes, d.tslot, d.trc, n, parity, d.len, stream));
+                    HIP_TRY(launch_path_lengths(d_mazes, d.tslot, d.trc, n, vparity(), d.len, stream));
             }
             HIP_TRY(launch_scan_offsets(d.len, n, d.off, stream));
             return OMAP_OK;
@@ -1085,11 +1090,11 @@ class Solver {
             if (host_out) walk_dst = reinterpret_cast<int32_t*>(q.end);
         }
         if (mode == 2)
-            HIP_TRY(launch_walk_euclid(true, d_mazes, q.tslot, q.trc, n, parity, q.len, q.off, walk_dst, stream));
+            HIP_TRY(launch_walk_euclid(true, d_mazes, q.tslot, q.trc, n, vparity(), q.len, q.off, walk_dst, stream));
         else if (mode == 1)
-            HIP_TRY(launch_walk_random(d_mazes, q.tslot, q.trc, q.tlocal, n, parity, seed, q.len, q.off, walk_dst, stream));
+            HIP_TRY(launch_walk_random(d_mazes, q.tslot, q.trc, q.tlocal, n, vparity(), seed, q.len, q.off, walk_dst, stream));
         else
-            HIP_TRY(launch_walk(d_mazes, q.tslot, q.trc, n, parity, q.len, q.off, walk_dst, stream));
+            HIP_TRY(launch_walk(d_mazes, q.tslot, q.trc, n, vparity(), q.len, q.off, walk_dst, stream));
         const hipMemcpyKind kind = host_out ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
         if (src_out)
             HIP_TRY(launch_source_index(d_mazes, q.tslot, n, q.len, q.off, walk_dst, q.ss, q.sbase, q.scount,
@@ -1109,7 +1114,7 @@ class Solver {
         if (!s.started) return fail(OMAP_ERR_NOT_PROPAGATED, "maze %d has not been propagated", k);
         OK_TRY(ensure_finalized(k));
         const int64_t off = (int64_t)s.K - s.layers - 1;
-        HIP_TRY(launch_activity(d_mazes, k, s.g.H, s.g.W, parity, (int32_t)off, dst, dpitch, stream));
+        HIP_TRY(launch_activity(d_mazes, k, s.g.H, s.g.W, vparity(), (int32_t)off, dst, dpitch, stream));
         return OMAP_OK;
     }
 
