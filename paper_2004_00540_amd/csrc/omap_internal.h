@@ -139,8 +139,9 @@ hipError_t launch_fill(int32_t* p, int64_t n_elems, int32_t value, hipStream_t s
 // Seed slot's sources (V := K) and schedule their tiles into a.list_out /
 // a.count_out / a.flags_out / a.sched_out (the runtime points these at the
 // round about to run).
-hipError_t launch_seed(const RoundArgs& a, int32_t slot, const int32_t* src_rc, int32_t n_src,
-                       int32_t* bad_count, hipStream_t s);
+// (src_slot: per-source slots, or nullptr for `slot`)
+hipError_t launch_seed(const RoundArgs& a, int32_t slot, const int32_t* src_rc, const int32_t* src_slot,
+                       int32_t n_src, int32_t* bad_count, hipStream_t s);
 hipError_t launch_check_sources(const uint32_t* mask, int32_t mpitch, const int32_t* src_rc,
                                 int32_t n_src, int32_t* bad_count, hipStream_t s);
 bool sweep_supported(int T, int C);
@@ -164,7 +165,18 @@ hipError_t launch_bits(int T, const RoundArgs& a, int32_t grid, hipStream_t s, h
                        hipEvent_t e1 = nullptr);
 hipError_t launch_queue_compact(const AsyncQueue& q, unsigned long long* tmp, uint32_t* tmp_count, hipStream_t s);
 int sweep_async_waves_per_cu(int T, int C);
-hipError_t launch_slot_reset(const RoundArgs& a, int32_t slot, hipStream_t s);
+hipError_t launch_slot_reset(const RoundArgs& a, const int32_t* slots, int32_t n, hipStream_t s);
+
+// Packing of several mazes' occupancy in one launch.
+struct PackJob {
+    const uint8_t* occ;
+    uint32_t* mask;
+    int32_t H, W, mpitch;
+    int64_t word_begin;   // first word of this maze in the concatenation
+};
+hipError_t launch_pack_mask_many(const PackJob* jobs, int32_t n_jobs, int64_t total_words, hipStream_t s);
+hipError_t launch_check_sources_many(const MazeDev* mazes, const int32_t* src_rc, const int32_t* src_slot,
+                                     int32_t n, int32_t* bad, hipStream_t s);
 // Smallest positive activity and reached count of the touched tiles in
 // [tile_begin, tile_end) of the selected slots.
 hipError_t launch_reduce(const MazeDev* mazes, const int32_t* tile_maze, const uint8_t* touched,
@@ -191,9 +203,11 @@ hipError_t launch_activity(const MazeDev* mazes, int32_t slot, int32_t H, int32_
                            int32_t parity, int32_t offset, int32_t* dst, int64_t dpitch,
                            hipStream_t s);
 hipError_t launch_selftest(int32_t* out, hipStream_t s);
-// Zeroes both activity buffers over the interiors of slot's touched tiles and
-// clears their touched flags.
-hipError_t launch_clear_touched(const RoundArgs& a, int32_t slot, int32_t n_tiles, hipStream_t s);
+// Zeroes both activity buffers (and bit planes) over the interiors of the
+// touched tiles among tile ids [tile_begin, +n_tiles) of the selected mazes
+// (sel == nullptr: all) and clears their touched flags.
+hipError_t launch_clear_touched(const RoundArgs& a, int32_t tile_begin, int32_t n_tiles, const int32_t* sel,
+                                hipStream_t s);
 int sweep_max_waves_per_cu(int T, int C);
 
 }  // namespace omap

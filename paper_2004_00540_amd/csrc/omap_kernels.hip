@@ -58,10 +58,12 @@ __global__ void k_check_sources(const uint32_t* __restrict__ mask, int32_t mpitc
 
 // Seed V := K at the sources (both buffers) and, when `schedule` is set,
 // schedule the tiles whose interior or halo holds a source.
-__global__ void k_seed(RoundArgs a, int32_t slot, const int32_t* __restrict__ src, int32_t n,
-                       int32_t schedule, int32_t* __restrict__ bad) {
+__global__ void k_seed(RoundArgs a, int32_t slot0, const int32_t* __restrict__ src,
+                       const int32_t* __restrict__ src_slot, int32_t n, int32_t schedule,
+                       int32_t* __restrict__ bad) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    const int slot = src_slot != nullptr ? src_slot[i] : slot0;
     const MazeDev md = a.mazes[slot];
     const int32_t r = src[2 * i], c = src[2 * i + 1];
     const uint32_t w = md.mask[(int64_t)r * md.mpitch + (c >> 5)];
@@ -93,10 +95,13 @@ __global__ void k_seed(RoundArgs a, int32_t slot, const int32_t* __restrict__ sr
         }
 }
 
-// Marks `slot` for its first round: counters cleared, last round = r - 1; in
-// the dense schedule the maze is flagged as changed so round r visits it.
-__global__ void k_slot_reset(RoundArgs a, int32_t slot) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// Marks each of slots[0..n) for its first round: counters cleared, last round
+// = r - 1; in the dense schedule the maze is flagged as changed so round r
+// visits it.
+__global__ void k_slot_reset(RoundArgs a, const int32_t* __restrict__ slots, int32_t n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int slot = slots[i];
     a.maze_last_round[slot] = a.round_id - 1;
     for (int k = 0; k < kSpread; ++k) {
         a.maze_visits[slot * kSpread + k] = 0;
@@ -136,17 +141,23 @@ __global__ __launch_bounds__(1024) void k_queue_gather(AsyncQueue q, unsigned lo
     if (threadIdx.x == 0) *count = base_s;
 }
 
-// One wave per tile of `slot`: zero the interior of touched tiles in both
-// activity buffers (everything else is still 0 from the last full clear).
-__global__ __launch_bounds__(kBlockThreads) void k_clear_touched(RoundArgs a, int32_t slot,
-                                                                 int32_t n_tiles) {
+// One wave per tile id in [tile_begin, tile_begin + n_tiles) whose maze is
+// selected (sel == nullptr: every maze): zero the interior of touched tiles in
+// both activity buffers (and, for the bit-sliced schedule, the interior words
+// of both reached-set planes), and clear their touched flags.
+__global__ __launch_bounds__(kBlockThreads) void k_clear_touched(RoundArgs a, int32_t tile_begin,
+                                                                 int32_t n_tiles,
+                                                                 const int32_t* __restrict__ sel) {
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int t = blockIdx.x * kWavesPerBlock + wave;
     if (t >= n_tiles) return;
-    const MazeDev md = a.mazes[slot];
-    const int g = md.tile_base + t;
+    const int g = tile_begin + t;
     if (!a.touched[g]) return;
-    const int ty = t / md.tiles_x, tx = t - ty * md.tiles_x;
+    const int slot = a.tile_maze[g];
+    if (slot < 0 || (sel != nullptr && sel[slot] == 0)) return;
+    const MazeDev md = a.mazes[slot];
+    const int lt = g - md.tile_base;
+    const int ty = lt / md.tiles_x, tx = lt - ty * md.tiles_x;
     const int r0 = ty * a.tile_rows, c0 = tx * a.tile_cols;
     const int rows = min(a.tile_rows, md.H - r0), cols = min(a.tile_cols, md.W - c0);
     for (int k = lane_id(); k < rows * cols; k += kLanes) {
@@ -154,7 +165,54 @@ __global__ __launch_bounds__(kBlockThreads) void k_clear_touched(RoundArgs a, in
         md.V[0][x] = 0;
         md.V[1][x] = 0;
     }
+    if (md.R[0] != nullptr) {   // bit tiles: 62 interior words per row
+        const int w0 = c0 / 32, nw = min((cols + 31) / 32, md.mpitch - w0);
+        for (int k = lane_id(); k < rows * nw; k += kLanes) {
+            const int64_t x = (int64_t)(r0 + k / nw) * md.mpitch + w0 + k % nw;
+            md.R[0][x] = 0;
+            md.R[1][x] = 0;
+        }
+    }
     if (lane_id() == 0) a.touched[g] = 0;
+}
+
+// Packs the occupancy of several mazes (job j: words [word_begin[j],
+// word_begin[j+1]) of the concatenated masks); one thread per mask word.
+__global__ void k_pack_mask_many(const PackJob* __restrict__ jobs, int32_t n_jobs, int64_t total_words) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total_words;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        int lo = 0, hi = n_jobs - 1;   // last job with word_begin <= i
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (jobs[mid].word_begin <= i) lo = mid;
+            else hi = mid - 1;
+        }
+        const PackJob jb = jobs[lo];
+        const int64_t wi = i - jb.word_begin;
+        const int32_t r = (int32_t)(wi / jb.mpitch);
+        const int32_t w = (int32_t)(wi - (int64_t)r * jb.mpitch);
+        const int32_t c0 = w * 32;
+        const uint8_t* row = jb.occ + (int64_t)r * jb.W;
+        uint32_t word = 0;
+        for (int b = 0; b < 32; ++b) {
+            const int32_t c = c0 + b;
+            const uint32_t bit = (c >= jb.W) ? 1u : (row[c] != 0 ? 1u : 0u);
+            word |= bit << b;
+        }
+        jb.mask[wi] = word;
+    }
+}
+
+// Sources of several mazes on obstacles: bad[slot] counts them.
+__global__ void k_check_sources_many(const MazeDev* __restrict__ mazes, const int32_t* __restrict__ src,
+                                     const int32_t* __restrict__ src_slot, int32_t n, int32_t* __restrict__ bad) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int slot = src_slot[i];
+    const MazeDev md = mazes[slot];
+    const int32_t r = src[2 * i], c = src[2 * i + 1];
+    const uint32_t w = md.mask[(int64_t)r * md.mpitch + (c >> 5)];
+    if ((w >> (c & 31)) & 1u) atomicAdd(&bad[slot], 1);
 }
 
 // ---------------------------------------------------------------------------
@@ -594,15 +652,32 @@ hipError_t launch_check_sources(const uint32_t* mask, int32_t mpitch, const int3
     return hipGetLastError();
 }
 
-hipError_t launch_seed(const RoundArgs& a, int32_t slot, const int32_t* src_rc, int32_t n_src,
-                       int32_t* bad_count, hipStream_t s) {
-    hipLaunchKernelGGL(k_seed, dim3(grid_for(n_src, 256)), dim3(256), 0, s, a, slot, src_rc, n_src,
+hipError_t launch_seed(const RoundArgs& a, int32_t slot, const int32_t* src_rc, const int32_t* src_slot,
+                       int32_t n_src, int32_t* bad_count, hipStream_t s) {
+    if (n_src <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_seed, dim3(grid_for(n_src, 256)), dim3(256), 0, s, a, slot, src_rc, src_slot, n_src,
                        a.dense ? 0 : 1, bad_count);
     return hipGetLastError();
 }
 
-hipError_t launch_slot_reset(const RoundArgs& a, int32_t slot, hipStream_t s) {
-    hipLaunchKernelGGL(k_slot_reset, dim3(1), dim3(64), 0, s, a, slot);
+hipError_t launch_slot_reset(const RoundArgs& a, const int32_t* slots, int32_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_slot_reset, dim3(grid_for(n, 64)), dim3(64), 0, s, a, slots, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_mask_many(const PackJob* jobs, int32_t n_jobs, int64_t total_words, hipStream_t s) {
+    if (n_jobs <= 0 || total_words <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pack_mask_many, dim3(grid_for(total_words, 256, 65536)), dim3(256), 0, s, jobs, n_jobs,
+                       total_words);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_sources_many(const MazeDev* mazes, const int32_t* src_rc, const int32_t* src_slot,
+                                     int32_t n, int32_t* bad, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_check_sources_many, dim3(grid_for(n, 256)), dim3(256), 0, s, mazes, src_rc, src_slot, n,
+                       bad);
     return hipGetLastError();
 }
 
@@ -756,10 +831,11 @@ hipError_t launch_activity(const MazeDev* mazes, int32_t slot, int32_t H, int32_
     return hipGetLastError();
 }
 
-hipError_t launch_clear_touched(const RoundArgs& a, int32_t slot, int32_t n_tiles, hipStream_t s) {
+hipError_t launch_clear_touched(const RoundArgs& a, int32_t tile_begin, int32_t n_tiles, const int32_t* sel,
+                                hipStream_t s) {
     if (n_tiles <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_clear_touched, dim3((n_tiles + kWavesPerBlock - 1) / kWavesPerBlock),
-                       dim3(kBlockThreads), 0, s, a, slot, n_tiles);
+                       dim3(kBlockThreads), 0, s, a, tile_begin, n_tiles, sel);
     return hipGetLastError();
 }
 

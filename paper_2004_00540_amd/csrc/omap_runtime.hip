@@ -194,6 +194,7 @@ class ArenaMemory : public DeviceMemory {
     ~ArenaMemory() override {
         if (base_) (void)hipFree(base_);
     }
+    void* base() const { return base_; }
     bool init(size_t bytes) {
         bytes = (bytes + 255) & ~size_t(255);
         if (hipMalloc(&base_, bytes) != hipSuccess) {
@@ -366,6 +367,10 @@ class Solver {
     int32_t* h_pinned = nullptr;              // 64 int32 of pinned host scratch
     void* d_scratch = nullptr;                // grow-only path scratch
     size_t scratch_bytes = 0;
+    int32_t* d_start_ = nullptr;              // grow-only staging of start_many
+    size_t start_cap_ = 0;
+    std::vector<int32_t> start_stage_;        // host copy of the last staging upload
+    std::vector<char> add_stage_;             // host copy of add_many's upload
 
     int64_t next_round = 0;                   // index of the next round to run
     int parity = 0;                           // next_round mod 2: activity buffer holding the latest values
@@ -390,6 +395,9 @@ class Solver {
         if (d_scratch) (void)hipFree(d_scratch);
         d_scratch = nullptr;
         scratch_bytes = 0;
+        if (d_start_) (void)hipFree(d_start_);
+        d_start_ = nullptr;
+        start_cap_ = 0;
         if (h_pinned) (void)hipHostFree(h_pinned);
         h_pinned = nullptr;
         if (h_bad) (void)hipHostFree(h_bad);
@@ -552,6 +560,13 @@ class Solver {
     // Copies slot k's descriptor to the device (stream-ordered; the host
     // mirror outlives the copy).
     omap_status_t upload_desc(int32_t k) {
+        set_desc(k);
+        HIP_TRY(hipMemcpyAsync(d_mazes + k, &h_mazes[k], sizeof(MazeDev), hipMemcpyHostToDevice, stream));
+        return OMAP_OK;
+    }
+
+    // Host mirror of slot k's descriptor.
+    void set_desc(int32_t k) {
         const Slot& s = slots[k];
         MazeDev& md = h_mazes[k];
         md.H = s.g.H;
@@ -568,7 +583,23 @@ class Solver {
         md.R[0] = s.R[0];
         md.R[1] = s.R[1];
         md.round0 = (int32_t)s.first_round;
-        HIP_TRY(hipMemcpyAsync(d_mazes + k, &md, sizeof md, hipMemcpyHostToDevice, stream));
+    }
+
+    // Grow-only device staging of start_many (synchronizes only to grow).
+    omap_status_t start_scratch(size_t n_int32, int32_t** out) {
+        if (n_int32 > start_cap_) {
+            HIP_TRY(hipStreamSynchronize(stream));
+            if (d_start_) (void)hipFree(d_start_);
+            d_start_ = nullptr;
+            start_cap_ = 0;
+            const size_t want = std::max<size_t>(n_int32, 1024);
+            HIP_TRY(hipMalloc(&d_start_, want * sizeof(int32_t)));
+            start_cap_ = want;
+        } else {
+            // the previous start's upload may still be in flight from start_stage_
+            HIP_TRY(hipStreamSynchronize(stream));
+        }
+        *out = d_start_;
         return OMAP_OK;
     }
 
@@ -705,6 +736,75 @@ class Solver {
         return OMAP_OK;
     }
 
+    // Add n mazes at once (batch creation): buffers and tile ids per maze on
+    // the host side, then one copy each of the tile table, the descriptors and
+    // the packing jobs and sources, one packing launch and one source check
+    // for all of them.  The source verdicts are read by commit().
+    omap_status_t add_many(const omap_maze_desc* d, int32_t n, std::vector<int32_t>* out_slots) {
+        std::vector<PackJob> jobs;
+        std::vector<int32_t> src_rc, src_slot;
+        int64_t words = 0;
+        for (int32_t i = 0; i < n; ++i) {
+            OK_TRY(validate_problem(d[i].height, d[i].width, d[i].occupancy_dev, d[i].sources_host, d[i].n_sources,
+                                    d[i].targets_host, d[i].n_targets));
+            const int32_t k = free_slot_index();
+            if (k < 0) return fail(OMAP_ERR_OUT_OF_MEMORY, "no free maze slot (capacity %d)", cap_slots);
+            Slot& s = slots[k];
+            s = Slot();
+            s.g = make_geometry(d[i].height, d[i].width, opt);
+            const int64_t nt = (int64_t)s.g.tiles_x * s.g.tiles_y;
+            if (nt > cap_tiles || !take_tiles((int32_t)nt, &s.tile_base))
+                return fail(OMAP_ERR_OUT_OF_MEMORY, "no tile ids left for %lld tiles", (long long)nt);
+            s.n_tiles = (int32_t)nt;
+            s.used = true;
+            s.V[0] = static_cast<int32_t*>(mem->alloc(s.g.v_bytes));
+            s.V[1] = static_cast<int32_t*>(mem->alloc(s.g.v_bytes));
+            s.mask = static_cast<uint32_t*>(mem->alloc(s.g.m_bytes));
+            if (s.g.bits) {
+                s.R[0] = static_cast<uint32_t*>(mem->alloc(s.g.m_bytes));
+                s.R[1] = static_cast<uint32_t*>(mem->alloc(s.g.m_bytes));
+            }
+            if (!s.V[0] || !s.V[1] || !s.mask || (s.g.bits && (!s.R[0] || !s.R[1])))
+                return fail(OMAP_ERR_OUT_OF_MEMORY, "activity and mask buffers for %d x %d", d[i].height, d[i].width);
+            s.src.assign(d[i].sources_host, d[i].sources_host + 2 * d[i].n_sources);
+            if (d[i].targets_host && d[i].n_targets > 0)
+                s.tgt.assign(d[i].targets_host, d[i].targets_host + 2 * d[i].n_targets);
+            std::fill(h_tile_maze.begin() + s.tile_base, h_tile_maze.begin() + s.tile_base + s.n_tiles, k);
+            PackJob jb;
+            jb.occ = static_cast<const uint8_t*>(d[i].occupancy_dev);
+            jb.mask = s.mask;
+            jb.H = s.g.H;
+            jb.W = s.g.W;
+            jb.mpitch = s.g.mpitch;
+            jb.word_begin = words;
+            words += (int64_t)s.g.H * s.g.mpitch;
+            jobs.push_back(jb);
+            src_rc.insert(src_rc.end(), s.src.begin(), s.src.end());
+            src_slot.insert(src_slot.end(), (size_t)d[i].n_sources, k);
+            set_desc(k);
+            out_slots->push_back(k);
+        }
+        const size_t b_jobs = (sizeof(PackJob) * jobs.size() + 255) & ~size_t(255);
+        const size_t b_rc = (sizeof(int32_t) * src_rc.size() + 255) & ~size_t(255);
+        const size_t b_sl = (sizeof(int32_t) * src_slot.size() + 255) & ~size_t(255);
+        char* base = nullptr;
+        OK_TRY(scratch(b_jobs + b_rc + b_sl, &base));
+        add_stage_.assign(b_jobs + b_rc + b_sl, 0);
+        std::memcpy(add_stage_.data(), jobs.data(), sizeof(PackJob) * jobs.size());
+        std::memcpy(add_stage_.data() + b_jobs, src_rc.data(), sizeof(int32_t) * src_rc.size());
+        std::memcpy(add_stage_.data() + b_jobs + b_rc, src_slot.data(), sizeof(int32_t) * src_slot.size());
+        HIP_TRY(hipMemcpyAsync(base, add_stage_.data(), add_stage_.size(), hipMemcpyHostToDevice, stream));
+        HIP_TRY(hipMemcpyAsync(d_tile_maze, h_tile_maze.data(), sizeof(int32_t) * tile_hwm, hipMemcpyHostToDevice,
+                               stream));
+        HIP_TRY(hipMemcpyAsync(d_mazes, h_mazes.data(), sizeof(MazeDev) * cap_slots, hipMemcpyHostToDevice, stream));
+        HIP_TRY(hipMemsetAsync(d_bad_slot, 0, sizeof(int32_t) * cap_slots, stream));
+        HIP_TRY(launch_pack_mask_many(reinterpret_cast<const PackJob*>(base), n, words, stream));
+        HIP_TRY(launch_check_sources_many(d_mazes, reinterpret_cast<const int32_t*>(base + b_jobs),
+                                          reinterpret_cast<const int32_t*>(base + b_jobs + b_rc),
+                                          (int32_t)src_slot.size(), d_bad_slot, stream));
+        return OMAP_OK;
+    }
+
     // Forget slot k: its tile ids and buffers go back to the pools
     // (stream-ordered).
     omap_status_t remove(int32_t k) {
@@ -722,33 +822,79 @@ class Solver {
     // Reset slot k's activity and seed it for L layers (L < 0: run-time L).
     // Stream-ordered: the maze's tiles join the next round.
     omap_status_t start(int32_t k, int64_t L) {
-        Slot& s = slots[k];
-        if (L < -1) return fail(OMAP_ERR_INVALID_ARG, "max_layers must be >= 0 or OMAP_AUTO_LAYERS");
-        if (L >= 0 && L + 1 > 0x7fffffffLL)
-            return fail(OMAP_ERR_TOO_LARGE, "L + 1 = %lld does not fit int32 activity", (long long)(L + 1));
-        s.L_req = L;
-        s.K = L < 0 ? 0x7fffffff : (int32_t)(L + 1);
-        s.first_round = next_round;
-        OK_TRY(upload_desc(k));
-        if (s.g.bits) {   // R_0 = the sources, set by the seeds below
-            HIP_TRY(launch_fill(reinterpret_cast<int32_t*>(s.R[0]), s.g.m_bytes / 4, 0, stream));
-            HIP_TRY(launch_fill(reinterpret_cast<int32_t*>(s.R[1]), s.g.m_bytes / 4, 0, stream));
+        std::vector<int32_t> one{k};
+        return start_many(one, &L);
+    }
+
+    // The same for several slots at once (Ls[i] for which[i]): one descriptor
+    // copy, one clear, one reset and one seed launch for all of them.
+    omap_status_t start_many(const std::vector<int32_t>& which, const int64_t* Ls) {
+        if (which.empty()) return OMAP_OK;
+        for (size_t i = 0; i < which.size(); ++i) {
+            const int64_t L = Ls[i];
+            if (L < -1) return fail(OMAP_ERR_INVALID_ARG, "max_layers must be >= 0 or OMAP_AUTO_LAYERS");
+            if (L >= 0 && L + 1 > 0x7fffffffLL)
+                return fail(OMAP_ERR_TOO_LARGE, "L + 1 = %lld does not fit int32 activity", (long long)(L + 1));
         }
+        std::vector<int32_t> sel(cap_slots, 0), seed_slot;
+        std::vector<int32_t> seed_rc;
+        int32_t lo = tile_hwm, hi = 0;
+        for (size_t i = 0; i < which.size(); ++i) {
+            const int32_t k = which[i];
+            Slot& s = slots[k];
+            s.L_req = Ls[i];
+            s.K = Ls[i] < 0 ? 0x7fffffff : (int32_t)(Ls[i] + 1);
+            s.first_round = next_round;
+            set_desc(k);
+            sel[k] = 1;
+            if (s.cleared) {
+                lo = std::min(lo, s.tile_base);
+                hi = std::max(hi, s.tile_base + s.n_tiles);
+            }
+            seed_rc.insert(seed_rc.end(), s.src.begin(), s.src.end());
+            seed_slot.insert(seed_slot.end(), s.src.size() / 2, k);
+        }
+        HIP_TRY(hipMemcpyAsync(d_mazes, h_mazes.data(), sizeof(MazeDev) * cap_slots, hipMemcpyHostToDevice, stream));
         const RoundArgs a = round_args(true);
-        if (s.cleared) {
-            HIP_TRY(launch_clear_touched(a, k, s.n_tiles, stream));
-        } else {
+        // staging: selection | slot list | seed (r, c) pairs | seed slots
+        const int32_t n_seed = (int32_t)seed_slot.size(), n_which = (int32_t)which.size();
+        std::vector<int32_t> stage;
+        stage.reserve(cap_slots + n_which + 3 * n_seed);
+        stage.insert(stage.end(), sel.begin(), sel.end());
+        stage.insert(stage.end(), which.begin(), which.end());
+        stage.insert(stage.end(), seed_rc.begin(), seed_rc.end());
+        stage.insert(stage.end(), seed_slot.begin(), seed_slot.end());
+        int32_t* d_stage = nullptr;
+        OK_TRY(start_scratch(stage.size(), &d_stage));
+        HIP_TRY(hipMemcpyAsync(d_stage, stage.data(), sizeof(int32_t) * stage.size(), hipMemcpyHostToDevice, stream));
+        const int32_t* d_sel_s = d_stage;
+        const int32_t* d_which = d_stage + cap_slots;
+        const int32_t* d_seed_rc = d_which + n_which;
+        const int32_t* d_seed_slot = d_seed_rc + 2 * n_seed;
+        if (hi > lo) HIP_TRY(launch_clear_touched(a, lo, hi - lo, d_sel_s, stream));
+        for (int32_t k : which) {
+            Slot& s = slots[k];
+            if (s.cleared) continue;
             HIP_TRY(launch_fill(s.V[0], s.g.v_bytes / 4, 0, stream));
             HIP_TRY(launch_fill(s.V[1], s.g.v_bytes / 4, 0, stream));
+            if (s.g.bits) {
+                HIP_TRY(launch_fill(reinterpret_cast<int32_t*>(s.R[0]), s.g.m_bytes / 4, 0, stream));
+                HIP_TRY(launch_fill(reinterpret_cast<int32_t*>(s.R[1]), s.g.m_bytes / 4, 0, stream));
+            }
             HIP_TRY(hipMemsetAsync(d_touched + s.tile_base, 0, s.n_tiles, stream));
             s.cleared = true;
         }
-        HIP_TRY(launch_slot_reset(a, k, stream));
-        HIP_TRY(launch_seed(a, k, s.d_src, (int32_t)(s.src.size() / 2), d_bad, stream));
-        s.first_round = next_round;
-        s.started = true;
-        s.finalized = false;
-        s.layers = -1;
+        HIP_TRY(launch_slot_reset(a, d_which, n_which, stream));
+        HIP_TRY(launch_seed(a, 0, d_seed_rc, d_seed_slot, n_seed, d_bad, stream));
+        // the staging buffer is reused by the next start: keep the host copy
+        // alive until the upload has been consumed
+        start_stage_.swap(stage);
+        for (int32_t k : which) {
+            Slot& s = slots[k];
+            s.started = true;
+            s.finalized = false;
+            s.layers = -1;
+        }
         return OMAP_OK;
     }
 
@@ -1511,17 +1657,11 @@ omap_status_t omap_batch_create(omap_batch_t* out, const omap_maze_desc* mazes, 
     if (!b->mem.init((size_t)bytes))
         return fail(OMAP_ERR_OUT_OF_MEMORY, "batch buffers (%lld bytes)", (long long)bytes);
     OK_TRY(b->solver.init(static_cast<hipStream_t>(stream), o, &b->mem, n_mazes, (int32_t)tiles));
-    for (int32_t i = 0; i < n_mazes; ++i) {
-        const omap_maze_desc& d = mazes[i];
-        int32_t slot = -1;
-        omap_status_t st = b->solver.add(d.height, d.width, d.occupancy_dev, d.sources_host, d.n_sources,
-                                         d.targets_host, d.n_targets, &slot, true);
-        if (st != OMAP_OK) {
-            g_last_error += " (maze " + std::to_string(i) + ")";
-            return st;
-        }
-        b->slots.push_back(slot);
-    }
+    // one clear of the whole arena (before the masks are packed into it):
+    // every maze starts with zero activity
+    HIP_TRY(hipMemsetAsync(b->mem.base(), 0, b->mem.size(), b->solver.stream));
+    OK_TRY(b->solver.add_many(mazes, n_mazes, &b->slots));
+    for (int32_t k : b->slots) b->solver.slots[k].cleared = true;
     int32_t bad = -1;
     omap_status_t st = b->solver.commit(b->slots, &bad);
     if (st != OMAP_OK) {
@@ -1540,8 +1680,9 @@ omap_status_t omap_batch_propagate(omap_batch_t batch, const int64_t* max_layers
     Solver& s = batch->solver;
     batch->propagated = false;
     OK_TRY(s.reset_schedule());
-    for (size_t i = 0; i < batch->slots.size(); ++i)
-        OK_TRY(s.start(batch->slots[i], max_layers_host ? max_layers_host[i] : OMAP_AUTO_LAYERS));
+    std::vector<int64_t> Ls(batch->slots.size(), (int64_t)OMAP_AUTO_LAYERS);
+    if (max_layers_host) Ls.assign(max_layers_host, max_layers_host + batch->slots.size());
+    OK_TRY(s.start_many(batch->slots, Ls.data()));
     OK_TRY(s.run_to_convergence());
     batch->propagated = true;
     if (infos_host) {
