@@ -83,8 +83,8 @@ typedef enum omap_status {
  * result: activity maps and paths are identical bit for bit for every value. */
 typedef struct omap_options {
     int32_t temporal_depth;  /* layers applied per tile visit: 4, 8, 12, 16 (and 24, 32    */
-                             /* with lane_columns = 2); 0 = default (plan, active: 12;     */
-                             /* batch, engine or dense: 16)                                */
+                             /* with lane_columns = 2); 0 = default (active: 12; dense and */
+                             /* bit-sliced: 16)                                            */
     int32_t tile_rows;       /* interior rows per tile, even, 2..4096, >= temporal_depth;  */
                              /* 0 = default (plan, active, 1 column per lane: depth;       */
                              /* other active: max(16, depth); dense: 256)                  */
@@ -114,16 +114,19 @@ typedef struct omap_options {
 
 /* The options a plan created with `options` (NULL = all defaults) would run
  * with: every zero field replaced by its default (batches and engines default
- * to other depth / column values, see above).  Host only, no device call.  Returns OMAP_ERR_INVALID_ARG (and leaves *resolved
- * untouched) for the same option values the create calls reject. */
+ * to other depth / column values, see above).  Host only, no device call.
+ * Returns OMAP_ERR_INVALID_ARG (and leaves *resolved untouched) for the same
+ * option values the create calls reject. */
 omap_status_t omap_resolve_options(const omap_options *options, omap_options *resolved);
 
 /* Per-maze report of a propagation. */
 typedef struct omap_propagate_info {
     int64_t layers;           /* L (fixed) or L* (run-time determined)               */
     int64_t sweeps_executed;  /* layers applied by the kernels (>= layers + 1 when   */
-                              /* converged: the last visit confirms the fixpoint)    */
+                              /* converged: the last visit confirms the fixpoint);   */
+                              /* 0 with OMAP_LAUNCH_ASYNC, which has no rounds       */
     int64_t rounds;           /* temporal blocks in which the maze had tiles visited */
+                              /* (0 with OMAP_LAUNCH_ASYNC)                          */
     int64_t tile_visits;      /* tile visits summed over rounds                       */
     int64_t reached_cells;    /* cells with activity > 0                              */
 } omap_propagate_info;

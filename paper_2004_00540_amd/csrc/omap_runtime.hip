@@ -78,9 +78,10 @@ struct Options {
 // latency-bound (a few hundred tiles per round on 1024 SIMDs): one column per
 // lane and 12 layers per visit keep each round short (23170^2 maze: 11.1 ms vs
 // 12.8 ms with 2 columns and 16 layers).  Many mazes at once (batch, engine)
-// fill the device, so 2 columns per lane and 16 layers waste less on halos
-// (512 mazes: 10.2k vs 9.0k mazes/s).  The dense schedule is throughput-bound:
-// 4 columns per lane and tall tiles.
+// fill the device, so 2 columns per lane waste less on halos (512 mazes:
+// 17.2k mazes/s with 12 layers per visit, 16.6k with 16, 13.6k with 4 columns).
+// The dense schedule is throughput-bound: 4 columns per lane, 16 layers and
+// tall tiles.
 enum class Use { kPlan, kMany };
 static omap_status_t resolve_options(const omap_options* o, Options* out, Use use = Use::kPlan) {
     Options r;
@@ -88,7 +89,7 @@ static omap_status_t resolve_options(const omap_options* o, Options* out, Use us
     const bool bits = o && o->schedule == OMAP_SCHEDULE_BITS;
     const bool single = use == Use::kPlan;
     r.C = dense ? 4 : (single ? 1 : 2);
-    r.T = dense ? 16 : (single ? 12 : 16);
+    r.T = dense ? 16 : 12;
     int th = 0;
     if (o) {
         if (o->lane_columns != 0) {
