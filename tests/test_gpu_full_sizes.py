@@ -80,3 +80,48 @@ def test_serving_queries_sample():
         rl, ro, rc = oracle.walk(A, q.sources, q.targets)
         assert res[k].info["layers"] == ecc
         assert np.array_equal(res[k].lengths, rl) and np.array_equal(res[k].cells, rc), q.name
+
+
+def test_maximum_size_empty_map():
+    """The largest grid the boundary accepts (46340^2 = 2,147,395,600 cells <
+    2^31): an empty map with a corner source, checked against the closed form
+    A(r, c) = L + 1 - max(r, c) with L = n - 1 (the Chebyshev distance; the CPU
+    tests pin the layers to it), on whole rows and columns and a seeded sample,
+    and paths whose shape follows from the fixed tie order."""
+    import torch
+    import paper_2004_00540_amd as omap
+    n = 46340
+    assert n * n < 2 ** 31
+    occ = torch.zeros((n, n), dtype=torch.uint8, device="cuda")
+    tgt = np.array([[n - 1, n - 1], [n - 1, 0], [0, n - 1], [12345, 30000], [0, 0]], np.int32)
+    with omap.Plan(occ, np.array([[0, 0]], np.int32), tgt) as plan:
+        info = plan.propagate()
+        print(f"max size: {info}", flush=True)
+        assert info["layers"] == n - 1
+        assert info["reached_cells"] == n * n
+        act = plan.activity()
+        idx = torch.arange(n, device="cuda", dtype=torch.int64)
+        assert torch.equal(act[0, :].long(), n - idx)
+        assert torch.equal(act[:, 0].long(), n - idx)
+        assert torch.equal(act[n - 1, :].long(), torch.ones(n, dtype=torch.int64, device="cuda"))
+        assert torch.equal(act[:, n - 1].long(), torch.ones(n, dtype=torch.int64, device="cuda"))
+        g = torch.Generator(device="cpu").manual_seed(46340)
+        r = torch.randint(0, n, (200000,), generator=g).cuda()
+        c = torch.randint(0, n, (200000,), generator=g).cuda()
+        assert torch.equal(act[r, c].long(), n - torch.maximum(r, c))
+        del act
+        torch.cuda.empty_cache()
+        ln, off, cells = (t.cpu().numpy() for t in plan.paths())
+    assert list(ln) == [n - 1, n - 1, n - 1, 30000, 0]
+    k = np.arange(n, dtype=np.int64)
+    # (n-1, n-1): the first maximal neighbour is the up-left diagonal
+    assert np.array_equal(cells[off[0]:off[1]], (n - 1 - k) * n + (n - 1 - k))
+    # (n-1, 0): straight up column 0; (0, n-1): straight left along row 0
+    assert np.array_equal(cells[off[1]:off[2]], (n - 1 - k) * n)
+    assert np.array_equal(cells[off[2]:off[3]], n - 1 - k)
+    # (12345, 30000): diagonal until row 0, then left
+    d = np.arange(12346, dtype=np.int64)
+    left = np.arange(1, 30000 - 12345 + 1, dtype=np.int64)
+    want = np.concatenate([(12345 - d) * n + (30000 - d), 30000 - 12345 - left])
+    assert np.array_equal(cells[off[3]:off[4]], want)
+    assert np.array_equal(cells[off[4]:off[5]], [0])
