@@ -200,6 +200,7 @@ def bench_plain(args):
     plan.close()
 
     step_s = wall
+    path_steps = int(lengths.clamp(min=0).sum().item())
     resolved = omap.resolve_options(**opts)
     gcups = N * S_J / step_s / 1e9
     alg_bytes = prof["cell_updates"] * BYTES_PER_CELL_UPDATE
@@ -216,6 +217,8 @@ def bench_plain(args):
                    "layers_run_time": L_star, "effective_layers": S_J,
                    "options": resolved},
         "paths_per_s": round(nt / step_s, 1),
+        "paths_per_s_extract_only": round(nt / (t_ext / 1e3), 1) if t_ext > 0 else None,
+        "path_steps_per_s_extract_only": round(path_steps / (t_ext / 1e3), 1) if t_ext > 0 else None,
         "path_cells": int(cells0.numel()),
         "phase_ms": {"ingest": round(t_load, 3), "propagate": round(t_prop, 3), "extract": round(t_ext, 3)},
         "event_ms_per_step": round(ms, 3),

@@ -116,7 +116,8 @@ def bench_serve(args):
     dev = torch.device("cuda:0")
     opts = dict(temporal_depth=args.depth, tile_rows=args.tile_rows, schedule=args.schedule,
                 lane_columns=args.lane_columns, round_launch=args.launch)
-    budget = int(args.serve_budget_gb * (1 << 30))
+    free, _ = torch.cuda.mem_get_info()
+    budget = int(min(args.serve_budget_gb * (1 << 30), 0.8 * free))
     seq = [pool[k % n_pool] for k in range(n_req)]
 
     # plain per-maze loop (device-resident occupancy uploaded per query, as the engine does)
@@ -175,7 +176,7 @@ def bench_serve(args):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
         "data": "synthetic",
         "config": {"workload": f"serve_poisson_{n_req}_requests_pool_{n_pool}", "arrival_rate_per_s": round(rate, 2),
-                   "budget_gb": args.serve_budget_gb, "slots": args.serve_slots,
+                   "budget_gb": round(budget / (1 << 30), 1), "slots": args.serve_slots,
                    "rounds_per_step": args.serve_rounds},
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)) * 1e3, 2),
                        "p99": round(float(np.percentile(lat, 99)) * 1e3, 2),

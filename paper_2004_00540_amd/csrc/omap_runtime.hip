@@ -1111,22 +1111,38 @@ class Solver {
         return finalize(one);
     }
 
-    omap_status_t info(int32_t k, omap_propagate_info* out) {
-        OK_TRY(ensure_finalized(k));
-        int64_t v[3] = {0, 0, 0};
-        int32_t last = 0;
-        int64_t vis[kSpread], cvis[kSpread];
-        HIP_TRY(hipMemcpyAsync(&last, d_last_round + k, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
-        HIP_TRY(hipMemcpyAsync(vis, d_visits + (size_t)k * kSpread, sizeof vis, hipMemcpyDeviceToHost, stream));
-        HIP_TRY(hipMemcpyAsync(cvis, d_cell_visits + (size_t)k * kSpread, sizeof cvis, hipMemcpyDeviceToHost,
+    // Host copies of every slot's visit counters (read_counters, synchronous).
+    std::vector<int32_t> h_last_round;
+    std::vector<int64_t> h_visits, h_cell_visits;
+
+    omap_status_t read_counters() {
+        h_last_round.resize(cap_slots);
+        h_visits.resize((size_t)cap_slots * kSpread);
+        h_cell_visits.resize((size_t)cap_slots * kSpread);
+        HIP_TRY(hipMemcpyAsync(h_last_round.data(), d_last_round, sizeof(int32_t) * cap_slots, hipMemcpyDeviceToHost,
                                stream));
+        HIP_TRY(hipMemcpyAsync(h_visits.data(), d_visits, sizeof(int64_t) * h_visits.size(), hipMemcpyDeviceToHost,
+                               stream));
+        HIP_TRY(hipMemcpyAsync(h_cell_visits.data(), d_cell_visits, sizeof(int64_t) * h_cell_visits.size(),
+                               hipMemcpyDeviceToHost, stream));
         HIP_TRY(hipStreamSynchronize(stream));
+        return OMAP_OK;
+    }
+
+    // Report of slot k; with counters_read the host copies of read_counters()
+    // are used instead of reading the device.
+    omap_status_t info(int32_t k, omap_propagate_info* out, bool counters_read = false) {
+        OK_TRY(ensure_finalized(k));
+        if (!counters_read) {
+            OK_TRY(read_counters());
+        }
+        int64_t v[3] = {0, 0, 0};
         for (int j = 0; j < kSpread; ++j) {
-            v[1] += vis[j];
-            v[2] += cvis[j];
+            v[1] += h_visits[(size_t)k * kSpread + j];
+            v[2] += h_cell_visits[(size_t)k * kSpread + j];
         }
         const Slot& s = slots[k];
-        v[0] = (int64_t)(int32_t)(last - (int32_t)s.first_round) + 1;   // rounds the maze was visited
+        v[0] = (int64_t)(int32_t)(h_last_round[k] - (int32_t)s.first_round) + 1;   // rounds the maze was visited
         if (v[0] < 0) v[0] = 0;
         out->layers = s.layers;
         out->rounds = v[0];
@@ -1443,21 +1459,33 @@ static omap_status_t engine_retire(omap_engine_s* e) {
     }
     if (done_slots.empty()) return OMAP_OK;
     OK_TRY(e->solver.finalize(done_slots));
+    // paths of every retiring maze in one extraction (sizing pass, then the
+    // cells), split per query afterwards
+    int64_t n_tgt = 0;
+    for (int64_t id : done_ids) n_tgt += (int64_t)(e->queries[id].tgt.size() / 2);
+    std::vector<int32_t> len((size_t)n_tgt + 1);
+    std::vector<int64_t> off((size_t)n_tgt + 2);
+    std::vector<int32_t> cells;
+    int64_t needed = 0;
+    omap_status_t st = e->solver.extract(done_slots, len.data(), off.data(), nullptr, 0, &needed, true);
+    if (st == OMAP_ERR_BUFFER_TOO_SMALL) {
+        cells.assign((size_t)needed, 0);
+        st = e->solver.extract(done_slots, len.data(), off.data(), cells.data(), needed, &needed, true);
+    }
+    if (st != OMAP_OK) return st;
+    // visit counters of every slot in one read
+    OK_TRY(e->solver.read_counters());
+    int64_t t0 = 0;
     for (size_t i = 0; i < done_ids.size(); ++i) {
         Query& q = e->queries[done_ids[i]];
         const int32_t k = done_slots[i];
-        const int32_t nt = (int32_t)(q.tgt.size() / 2);
-        q.len.assign(nt, 0);
-        q.off.assign(nt + 1, 0);
-        int64_t needed = 0;
-        std::vector<int32_t> one{k};
-        omap_status_t st = e->solver.extract(one, q.len.data(), q.off.data(), nullptr, 0, &needed, true);
-        if (st == OMAP_ERR_BUFFER_TOO_SMALL) {
-            q.cells.assign(needed, 0);
-            st = e->solver.extract(one, q.len.data(), q.off.data(), q.cells.data(), needed, &needed, true);
-        }
-        if (st != OMAP_OK) return st;
-        OK_TRY(e->solver.info(k, &q.info));
+        const int64_t nt = (int64_t)(q.tgt.size() / 2);
+        q.len.assign(len.begin() + t0, len.begin() + t0 + nt);
+        q.off.resize((size_t)nt + 1);
+        for (int64_t j = 0; j <= nt; ++j) q.off[j] = off[t0 + j] - off[t0];
+        q.cells.assign(cells.begin() + off[t0], cells.begin() + off[t0 + nt]);
+        t0 += nt;
+        OK_TRY(e->solver.info(k, &q.info, /*counters_read=*/true));
         OK_TRY(e->solver.remove(k));
         q.slot = -1;
         q.state = OMAP_QUERY_DONE;

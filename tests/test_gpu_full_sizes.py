@@ -61,8 +61,12 @@ def test_config4_all_512_batched():
 
 def test_serving_queries_sample():
     import paper_2004_00540_amd as omap
+    import torch
     qs = [workloads.serve_query(i) for i in range(6)]
-    with omap.Engine(24 << 30, max_slots=16) as eng:
+    free, _ = torch.cuda.mem_get_info()
+    budget = int(min(8 << 30, free // 2))   # the six queries need about 4 GiB at once
+    print(f"free device memory {free / 2**30:.1f} GiB, engine budget {budget / 2**30:.1f} GiB", flush=True)
+    with omap.Engine(budget, max_slots=16) as eng:
         ids = {eng.submit(q.occ, q.sources, q.targets): k for k, q in enumerate(qs)}
         res = {}
         n = 0
