@@ -179,28 +179,20 @@ __global__ __launch_bounds__(kBlockThreads) void k_bits(RoundArgs a) {
     int par = 0;
     for (int ib = blockIdx.x * kWavesPerBlock; ib < n; ib += stride, par ^= 1) {
         i = ib + wave;
-        int slot = 0, gn = 0;
-        bool won = false;
+        int slot = 0, gn = 0, g = 0, ty = 0, tx = 0;
+        bool won = false, visited = false;
+        MazeDev md;
         if (i < n) {
-            const int g = __builtin_amdgcn_readfirstlane((int)(uint32_t)e);
+            g = __builtin_amdgcn_readfirstlane((int)(uint32_t)e);
             slot = __builtin_amdgcn_readfirstlane((int)(uint32_t)(e >> 32));
             if (i + stride < n) e = *reinterpret_cast<const uint64_t*>(a.list_in + 2 * (i + stride));
-            if (lane == 0) a.flags_in[g] = 0;
-            const MazeDev md = a.n_slots == 1 ? a.md0 : a.mazes[slot];
+            md = a.n_slots == 1 ? a.md0 : a.mazes[slot];
             const int64_t n0 = (int64_t)(a.round_id - md.round0) * T;   // layers done before this round
             if (n0 + 1 < md.K) {
                 const int lt = g - md.tile_base;
-                const int ty = lt / md.tiles_x, tx = lt - ty * md.tiles_x;
-                if (lane == 0) {
-                    const unsigned long long cells =
-                        (unsigned long long)tile_cells(md, ty, tx, a.tile_rows, a.tile_cols);
-                    const int sp = blockIdx.x & (kSpread - 1);
-                    atomicAdd(reinterpret_cast<unsigned long long*>(&a.maze_visits[slot * kSpread + sp]), 1ull);
-                    atomicAdd(reinterpret_cast<unsigned long long*>(&a.maze_cell_visits[slot * kSpread + sp]), cells);
-                    atomicAdd(a.total_cells + sp, cells);
-                    if (a.maze_last_round[slot] != a.round_id) a.maze_last_round[slot] = a.round_id;
-                    a.touched[g] = 1;
-                }
+                ty = lt / md.tiles_x;
+                tx = lt - ty * md.tiles_x;
+                visited = true;
                 if (bits_tile<T>(md, ty, tx, a.tile_rows, a.parity, (int)n0)) {
                     const int ny = ty + lane / 3 - 1, nx = tx + lane % 3 - 1;
                     gn = md.tile_base + ny * md.tiles_x + nx;
@@ -229,6 +221,10 @@ __global__ __launch_bounds__(kBlockThreads) void k_bits(RoundArgs a) {
                 a.list_out[2 * k + 1] = slot;
             }
             if (a.n_slots > 1 && lane == 0) atomicAdd(&a.sched_out[slot], nwon);
+        }
+        if (i < n && lane == 0) {
+            if (visited) visit_bookkeeping_active(a, g, slot, md, ty, tx);
+            else a.flags_in[g] = 0;
         }
     }
 }

@@ -101,13 +101,14 @@ __device__ __forceinline__ void queue_push(const AsyncQueue& q, int g, int slot)
 // (P+1) mod 3.  Stage s writes its output row straight into stage s+1's slot
 // P, whose previous content (row i-3 of that stage) is dead, so no register
 // copies are needed.
-// With GUARD, stages above smax are skipped (see sweep_tile).
-template <int T, int P, int C, bool GUARD>
+// Stages above SMAX (compile time) and, with GUARD, above smax (run time)
+// are skipped (see sweep_tile).
+template <int T, int P, int C, bool GUARD, int SMAX = T - 1>
 __device__ __forceinline__ void sweep_row(uint32_t (&st)[T][3][C], uint32_t (&out)[C], int smax) {
     constexpr int PA = (P + 1) % 3, PB = (P + 2) % 3;
 #pragma unroll
     for (int s = 0; s < T; ++s) {
-        if (!GUARD || s <= smax) {
+        if (s <= SMAX && (!GUARD || s <= smax)) {
             const uint32_t* a = st[s][PA];   // row above the centre
             const uint32_t* b = st[s][PB];   // centre row
             const uint32_t* c = st[s][P];    // row below the centre
@@ -164,11 +165,11 @@ __device__ __forceinline__ void load_row(const MazeDev& md, const int32_t* Vin, 
     w = *(gconst_u32*)(md.mask + (int64_t)Rc * md.mpitch + (cc >> 5));
 }
 
-// One row of the tile.  (v, w) holds row R, loaded one group (three rows)
-// earlier; it is decoded into stage 0's slot P (cells outside the grid become
-// exactly 0x80000000) and the same registers then receive the load of row
-// R + 3, whose latency overlaps the T-stage arithmetic of the next rows.
-template <int T, int P, int C, bool GUARD>
+// One row of the tile.  (v, w) holds row R, loaded D rows earlier; it is
+// decoded into stage 0's slot P (cells outside the grid become exactly
+// 0x80000000) and the same registers then receive the load of row R + D, whose
+// latency overlaps the T-stage arithmetic of the next D rows.
+template <int T, int P, int C, bool GUARD, int D, int SMAX = T - 1>
 __device__ __forceinline__ void sweep_iter(uint32_t (&st)[T][3][C], typename LaneVec<C>::type& v,
                                            uint32_t& w, const MazeDev& md,
                                            const int32_t* Vin, int32_t* Vout, int R, int r0, int r_end,
@@ -180,7 +181,7 @@ __device__ __forceinline__ void sweep_iter(uint32_t (&st)[T][3][C], typename Lan
     uint32_t* c = st[0][P];
 #pragma unroll
     for (int j = 0; j < C; ++j) c[j] = ((uint32_t)v[j] & keep) | (((bits >> j) & 1u) << 31);
-    load_row<C>(md, Vin, R + 3, col, col_ok, v, w);
+    load_row<C>(md, Vin, R + D, col, col_ok, v, w);
     if (inner && R >= r0 && R < r_end) {
         uint64_t t = 0;
 #pragma unroll
@@ -188,7 +189,7 @@ __device__ __forceinline__ void sweep_iter(uint32_t (&st)[T][3][C], typename Lan
         sum_in += t;
     }
     uint32_t out[C] = {};   // left 0 when the last stage is skipped (its row is not stored then)
-    sweep_row<T, P, C, GUARD>(st, out, smax);
+    sweep_row<T, P, C, GUARD, SMAX>(st, out, smax);
     const int Ro = R - T;
     if (inner && Ro >= r0 && Ro < r_end) {
         typename LaneVec<C>::type o;
@@ -203,6 +204,51 @@ __device__ __forceinline__ void sweep_iter(uint32_t (&st)[T][3][C], typename Lan
     }
 }
 
+// Rows of a tile visit whose loads are in flight at once.  A row's arithmetic
+// (T stages) takes far less time than a load that misses the L2, so one group
+// of three rows ahead leaves the wave waiting on memory; D rows ahead hide the
+// latency.  A multiple of 3 (the pipeline's slot rotation).  Only the
+// one-column variants prefetch 12 rows: their pipeline takes 3*T registers, and
+// the wider variants, whose visits are longer anyway, compile to basic blocks
+// that the instruction scheduler takes many minutes over when unrolled 4 times.
+template <int T, int C>
+struct SweepPrefetch {
+    static constexpr int D = C == 1 ? 12 : 3;
+};
+
+// Rows R .. R + D - 1 of a visit: one sweep_iter per row with row buffer J
+// and pipeline slot J mod 3 (compile-time indices, so everything stays in
+// registers).  With GUARD, row R + J runs stages up to ((i + J) >> 1) - 1.
+template <int T, int C, bool GUARD, int D, int J = 0>
+__device__ __forceinline__ void sweep_rows(uint32_t (&st)[T][3][C], typename LaneVec<C>::type (&v)[D],
+                                           uint32_t (&w)[D], const MazeDev& md, const int32_t* Vin,
+                                           int32_t* Vout, int R, int i, int r0, int r_end, int col,
+                                           bool col_ok, bool inner, uint64_t& sum_in, uint64_t& sum_out) {
+    if constexpr (J < D) {
+        sweep_iter<T, J % 3, C, GUARD, D>(st, v[J], w[J], md, Vin, Vout, R + J, r0, r_end, col, col_ok, inner,
+                                          GUARD ? ((i + J) >> 1) - 1 : 0, sum_in, sum_out);
+        sweep_rows<T, C, GUARD, D, J + 1>(st, v, w, md, Vin, Vout, R, i, r0, r_end, col, col_ok, inner, sum_in,
+                                          sum_out);
+    }
+}
+
+// The first KW rows of a visit (the top of the trapezoid, see sweep_tile)
+// unrolled with each row's stage limit known at compile time: no run-time
+// guards, and no code for the skipped stages.
+template <int T, int C, int D, int KW, int I = 0>
+__device__ __forceinline__ void sweep_warm(uint32_t (&st)[T][3][C], typename LaneVec<C>::type (&v)[D],
+                                           uint32_t (&w)[D], const MazeDev& md, const int32_t* Vin,
+                                           int32_t* Vout, int R0, int r0, int r_end, int col, bool col_ok,
+                                           bool inner, uint64_t& sum_in, uint64_t& sum_out) {
+    if constexpr (I < KW) {
+        constexpr int SM = (I >> 1) - 1 < T - 1 ? (I >> 1) - 1 : T - 1;
+        sweep_iter<T, I % 3, C, false, D, SM>(st, v[I % D], w[I % D], md, Vin, Vout, R0 + I, r0, r_end, col,
+                                              col_ok, inner, 0, sum_in, sum_out);
+        sweep_warm<T, C, D, KW, I + 1>(st, v, w, md, Vin, Vout, R0, r0, r_end, col, col_ok, inner, sum_in,
+                                       sum_out);
+    }
+}
+
 // Returns true (wave-uniform) if any interior cell of the tile changed.  The
 // wave streams the strip of 64*C columns starting T columns left of the tile.
 // In place (IN_PLACE) the tile reads and writes buffer `parity`: a row is
@@ -212,6 +258,7 @@ template <int T, int C, bool IN_PLACE = false>
 __device__ bool sweep_tile(const MazeDev& md, int ty, int tx, int tile_rows, int parity) {
     constexpr int TW = kLanes * C - 2 * T;
     constexpr int HALO_LANES = T / C;
+    constexpr int D = SweepPrefetch<T, C>::D;
     const int lane = lane_id();
     const int r0 = ty * tile_rows;
     const int r_end = min(r0 + tile_rows, md.H);
@@ -231,38 +278,35 @@ __device__ bool sweep_tile(const MazeDev& md, int ty, int tx, int tile_rows, int
 
     uint64_t sum_in = 0, sum_out = 0;
     const int n_iter = (r_end - r0) + 2 * T;   // rows r0-T .. r_end+T-1
-    typename LaneVec<C>::type v0, v1, v2;
-    uint32_t w0, w1, w2;
-    load_row<C>(md, Vin, r0 - T, col, col_ok, v0, w0);
-    load_row<C>(md, Vin, r0 - T + 1, col, col_ok, v1, w1);
-    load_row<C>(md, Vin, r0 - T + 2, col, col_ok, v2, w2);
+    typename LaneVec<C>::type v[D];
+    uint32_t w[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) load_row<C>(md, Vin, r0 - T + j, col, col_ok, v[j], w[j]);
     // Stage s at step i (input row r0 - T + i) emits row r0 - T + i - 1 - s
     // after s + 1 layers; the stored rows [r0, r_end) after T layers need
     // exactly the emissions with i >= 2s + 2 (each of which reads only
     // emissions of stage s - 1 with i - 2 >= 2(s - 1) + 2).  So during the
     // first 2T steps, stages s > i/2 - 1 are skipped: the top of the tile's
     // trapezoid, a third of the work of a tile with as many rows as layers.
-    constexpr int kWarm = 3 * ((2 * T + 2) / 3);   // >= 2T, a multiple of 3
+    // Steps past n_iter (the last group's tail) store nothing.
+    constexpr int kWarm = D * ((2 * T + D - 1) / D);   // >= 2T, a multiple of D
     int i = 0;
+    if constexpr (C == 1) {
+        // one column per lane: the warm-up unrolled (straight-line code of about
+        // the size of one steady-state group for these depths)
+        sweep_warm<T, C, D, kWarm>(st, v, w, md, Vin, Vout, r0 - T, r0, r_end, col, col_ok, inner, sum_in,
+                                   sum_out);
+        i = kWarm;
+    } else {
 #pragma unroll 1
-    for (; i < kWarm; i += 3) {
-        const int R = r0 - T + i;
-        sweep_iter<T, 0, C, true>(st, v0, w0, md, Vin, Vout, R, r0, r_end, col, col_ok, inner, (i >> 1) - 1,
-                                  sum_in, sum_out);
-        sweep_iter<T, 1, C, true>(st, v1, w1, md, Vin, Vout, R + 1, r0, r_end, col, col_ok, inner,
-                                  ((i + 1) >> 1) - 1, sum_in, sum_out);
-        sweep_iter<T, 2, C, true>(st, v2, w2, md, Vin, Vout, R + 2, r0, r_end, col, col_ok, inner,
-                                  ((i + 2) >> 1) - 1, sum_in, sum_out);
+        for (; i < kWarm; i += D)
+            sweep_rows<T, C, true, D>(st, v, w, md, Vin, Vout, r0 - T + i, i, r0, r_end, col, col_ok, inner,
+                                      sum_in, sum_out);
     }
 #pragma unroll 1
-    for (; i < n_iter; i += 3) {
-        const int R = r0 - T + i;
-        sweep_iter<T, 0, C, false>(st, v0, w0, md, Vin, Vout, R, r0, r_end, col, col_ok, inner, 0, sum_in, sum_out);
-        sweep_iter<T, 1, C, false>(st, v1, w1, md, Vin, Vout, R + 1, r0, r_end, col, col_ok, inner, 0, sum_in,
+    for (; i < n_iter; i += D)
+        sweep_rows<T, C, false, D>(st, v, w, md, Vin, Vout, r0 - T + i, i, r0, r_end, col, col_ok, inner, sum_in,
                                    sum_out);
-        sweep_iter<T, 2, C, false>(st, v2, w2, md, Vin, Vout, R + 2, r0, r_end, col, col_ok, inner, 0, sum_in,
-                                   sum_out);
-    }
     return __ballot(sum_in != sum_out) != 0;
 }
 
@@ -295,24 +339,38 @@ __device__ __forceinline__ uint64_t load_sched64(const int32_t* p) {
 // round r+1.  Dense schedule: every tile of each maze that changed in round
 // r-1; a changed tile flags its maze for round r+1.  Block 0 also clears the
 // buffers round r+1 will fill.
-// Tile g of slot: visit counters, then T layers.  Returns true (wave-uniform)
-// if the interior changed; md, ty, tx describe the tile.
+// Tile g of slot: T layers.  Returns true (wave-uniform) if the interior
+// changed; md, ty, tx describe the tile.
 template <int T, int C>
 __device__ __forceinline__ bool visit_tile(const RoundArgs& a, int g, int slot, MazeDev& md, int& ty, int& tx) {
     md = a.n_slots == 1 ? a.md0 : a.mazes[slot];
     const int lt = g - md.tile_base;
     ty = lt / md.tiles_x;
     tx = lt - ty * md.tiles_x;
-    if (lane_id() == 0) {
-        const unsigned long long cells = (unsigned long long)tile_cells(md, ty, tx, a.tile_rows, a.tile_cols);
-        const int sp = blockIdx.x & (kSpread - 1);
-        atomicAdd(reinterpret_cast<unsigned long long*>(&a.maze_visits[slot * kSpread + sp]), 1ull);
-        atomicAdd(reinterpret_cast<unsigned long long*>(&a.maze_cell_visits[slot * kSpread + sp]), cells);
-        atomicAdd(a.total_cells + sp, cells);
-        if (a.maze_last_round[slot] != a.round_id) a.maze_last_round[slot] = a.round_id;
-        a.touched[g] = 1;
-    }
     return sweep_tile<T, C>(md, ty, tx, a.tile_rows, a.parity);
+}
+
+// Counters and flags of one visit (lane 0).  Called after the visit's own
+// scheduling work: the vector-memory counter completes in issue order, so
+// a load here issued before the tile's row loads would make the first row
+// wait for these atomics and this load as well.
+__device__ __forceinline__ void visit_bookkeeping(const RoundArgs& a, int g, int slot, const MazeDev& md,
+                                                  int ty, int tx) {
+    const unsigned long long cells = (unsigned long long)tile_cells(md, ty, tx, a.tile_rows, a.tile_cols);
+    const int sp = blockIdx.x & (kSpread - 1);
+    atomicAdd(reinterpret_cast<unsigned long long*>(&a.maze_visits[slot * kSpread + sp]), 1ull);
+    atomicAdd(reinterpret_cast<unsigned long long*>(&a.maze_cell_visits[slot * kSpread + sp]), cells);
+    atomicAdd(a.total_cells + sp, cells);
+    a.touched[g] = 1;
+    if (a.maze_last_round[slot] != a.round_id) a.maze_last_round[slot] = a.round_id;
+}
+
+// The same plus clearing the tile's scheduled flag of this round (active
+// schedule), which lets the next round claim the tile again.
+__device__ __forceinline__ void visit_bookkeeping_active(const RoundArgs& a, int g, int slot, const MazeDev& md,
+                                                         int ty, int tx) {
+    a.flags_in[g] = 0;
+    visit_bookkeeping(a, g, slot, md, ty, tx);
 }
 
 template <int T, int C, bool SHARED>
@@ -340,9 +398,13 @@ __device__ __forceinline__ void sweep_round(const RoundArgs& a) {
             if (slot < 0 || __builtin_amdgcn_readfirstlane(load_sched<SHARED>(a.dchg_prev + slot)) == 0) continue;
             MazeDev md;
             int ty, tx;
-            if (visit_tile<T, C>(a, i, slot, md, ty, tx) && lane == 0) {
-                a.dchg_cur[slot] = 1;
-                *a.count_out = 1;
+            const bool changed = visit_tile<T, C>(a, i, slot, md, ty, tx);
+            if (lane == 0) {
+                if (changed) {
+                    a.dchg_cur[slot] = 1;
+                    *a.count_out = 1;
+                }
+                visit_bookkeeping(a, i, slot, md, ty, tx);
             }
         }
         return;
@@ -356,15 +418,13 @@ __device__ __forceinline__ void sweep_round(const RoundArgs& a) {
     int par = 0;
     for (int ib = blockIdx.x * kWavesPerBlock; ib < n; ib += stride, par ^= 1) {
         i = ib + wave;
-        int slot = 0, gn = 0;
+        int slot = 0, gn = 0, g = 0, ty = 0, tx = 0;
         bool won = false;
+        MazeDev md;
         if (i < n) {
-            const int g = __builtin_amdgcn_readfirstlane((int)(uint32_t)e);
+            g = __builtin_amdgcn_readfirstlane((int)(uint32_t)e);
             slot = __builtin_amdgcn_readfirstlane((int)(uint32_t)(e >> 32));
             if (i + stride < n) e = load_sched64<SHARED>(a.list_in + 2 * (i + stride));
-            if (lane == 0) a.flags_in[g] = 0;
-            MazeDev md;
-            int ty, tx;
             if (visit_tile<T, C>(a, g, slot, md, ty, tx)) {
                 // lanes 0..8 claim the 3x3 tiles around (ty, tx) for the next round
                 const int ny = ty + lane / 3 - 1, nx = tx + lane % 3 - 1;
@@ -394,6 +454,7 @@ __device__ __forceinline__ void sweep_round(const RoundArgs& a) {
             }
             if (a.n_slots > 1 && lane == 0) atomicAdd(&a.sched_out[slot], nwon);
         }
+        if (i < n && lane == 0) visit_bookkeeping_active(a, g, slot, md, ty, tx);
     }
 }
 
