@@ -83,8 +83,8 @@ typedef enum omap_status {
  * result: activity maps and paths are identical bit for bit for every value. */
 typedef struct omap_options {
     int32_t temporal_depth;  /* layers applied per tile visit: 4, 8, 12, 16 (and 24, 32    */
-                             /* with lane_columns = 2); 0 = default (active: 12; dense and */
-                             /* bit-sliced: 16)                                            */
+                             /* with lane_columns = 2); 0 = default (16; active with more  */
+                             /* than one column per lane, as in batches and engines: 12)   */
     int32_t tile_rows;       /* interior rows per tile, even, 2..4096, >= temporal_depth;  */
                              /* 0 = default (plan, active, 1 column per lane: depth;       */
                              /* other active: max(16, depth); dense: 256)                  */

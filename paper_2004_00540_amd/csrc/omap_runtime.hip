@@ -76,8 +76,9 @@ struct Options {
 
 // Defaults (measured on MI355X).  A single maze under the active schedule is
 // latency-bound (a few hundred tiles per round on 1024 SIMDs): one column per
-// lane and 12 layers per visit keep each round short (23170^2 maze: 11.1 ms vs
-// 12.8 ms with 2 columns and 16 layers).  Many mazes at once (batch, engine)
+// lane keeps each visit short, and with the one-column visits' unrolled
+// warm-up 16 layers per visit beat 12 (23170^2 maze: propagation 8.2 vs
+// 8.5 ms; 2 columns and 16 layers: 12.8 ms).  Many mazes at once (batch, engine)
 // fill the device, so 2 columns per lane waste less on halos (512 mazes:
 // 17.2k mazes/s with 12 layers per visit, 16.6k with 16, 13.6k with 4 columns).
 // The dense schedule is throughput-bound: 4 columns per lane, 16 layers and
@@ -89,7 +90,7 @@ static omap_status_t resolve_options(const omap_options* o, Options* out, Use us
     const bool bits = o && o->schedule == OMAP_SCHEDULE_BITS;
     const bool single = use == Use::kPlan;
     r.C = dense ? 4 : (single ? 1 : 2);
-    r.T = dense ? 16 : 12;
+    r.T = 0;
     int th = 0;
     if (o) {
         if (o->lane_columns != 0) {
@@ -97,7 +98,7 @@ static omap_status_t resolve_options(const omap_options* o, Options* out, Use us
                 return fail(OMAP_ERR_INVALID_ARG, "lane_columns must be 1, 2 or 4 (got %d)", o->lane_columns);
             r.C = o->lane_columns;
         }
-        if (o->temporal_depth != 0) r.T = o->temporal_depth;
+        r.T = o->temporal_depth;
         if (o->tile_rows != 0) {
             if (o->tile_rows < 2 || o->tile_rows > 4096 || (o->tile_rows & 1))
                 return fail(OMAP_ERR_INVALID_ARG, "tile_rows must be even in [2, 4096] (got %d)",
@@ -143,6 +144,7 @@ static omap_status_t resolve_options(const omap_options* o, Options* out, Use us
         *out = r;
         return OMAP_OK;
     }
+    if (r.T == 0) r.T = (dense || r.C == 1) ? 16 : 12;
     // a depth chosen without a column count takes the narrowest strip that has it
     if ((!o || o->lane_columns == 0) && !sweep_supported(r.T, r.C)) {
         if (sweep_supported(r.T, 2)) r.C = 2;

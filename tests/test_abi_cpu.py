@@ -110,7 +110,7 @@ def test_batch_validation_names_the_maze():
 
 def test_resolve_options_fills_defaults():
     d = omap.resolve_options()
-    assert d == {"temporal_depth": 12, "tile_rows": 12, "schedule": omap.SCHEDULE_ACTIVE,
+    assert d == {"temporal_depth": 16, "tile_rows": 16, "schedule": omap.SCHEDULE_ACTIVE,
                  "check_interval": 0, "lane_columns": 1, "round_launch": omap.LAUNCH_PER_ROUND,
                  "async_budget_us": 50000}
     d = omap.resolve_options(schedule=omap.SCHEDULE_DENSE)
@@ -119,6 +119,10 @@ def test_resolve_options_fills_defaults():
     assert (d["tile_rows"], d["lane_columns"], d["round_launch"]) == (32, 2, omap.LAUNCH_PERSISTENT)
     d = omap.resolve_options(temporal_depth=16, lane_columns=2)
     assert (d["tile_rows"], d["lane_columns"]) == (16, 2)
+    d = omap.resolve_options(lane_columns=2)
+    assert (d["temporal_depth"], d["tile_rows"]) == (12, 16)
+    d = omap.resolve_options(temporal_depth=12)
+    assert (d["temporal_depth"], d["tile_rows"], d["lane_columns"]) == (12, 12, 1)
     with pytest.raises(omap.OmapError):
         omap.resolve_options(temporal_depth=32, lane_columns=4)
     with pytest.raises(omap.OmapError):
