@@ -341,10 +341,12 @@ constexpr int kWalkWaves = 4;
 // (dr + 1) | (dc + 1) << 2 of neighbour k in bits 4k..4k+3
 constexpr uint32_t kDirNibbles = 0xA6291840u;
 
+// (the identity as the old value lets each DPP move fold into its max)
 __device__ __forceinline__ int row_max16(int x) {
-    x = max(x, __builtin_amdgcn_mov_dpp(x, 0x124, 0xF, 0xF, false));   // row_ror:4
-    x = max(x, __builtin_amdgcn_mov_dpp(x, 0x122, 0xF, 0xF, false));   // row_ror:2
-    x = max(x, __builtin_amdgcn_mov_dpp(x, 0x121, 0xF, 0xF, false));   // row_ror:1
+    constexpr int kMin = (int)0x80000000;
+    x = max(__builtin_amdgcn_update_dpp(kMin, x, 0x124, 0xF, 0xF, false), x);   // row_ror:4
+    x = max(__builtin_amdgcn_update_dpp(kMin, x, 0x122, 0xF, 0xF, false), x);   // row_ror:2
+    x = max(__builtin_amdgcn_update_dpp(kMin, x, 0x121, 0xF, 0xF, false), x);   // row_ror:1
     return x;
 }
 
@@ -363,10 +365,11 @@ __global__ __launch_bounds__(kLanes * kWalkWaves) void k_walk(
     const MazeDev md = mazes[slot];
     const int32_t* __restrict__ V = parity ? md.V[1] : md.V[0];
     int32_t* win = win_all[wave];
-    // this lane's neighbour: k = lane mod 8, offset in the window
+    // this lane's neighbour: k = lane mod 8, offset in the window from the
+    // current cell's upper-left neighbour (non-negative)
     const int k8 = lane & 7;
     const uint32_t nib = (kDirNibbles >> (4 * k8)) & 15u;
-    const int my_off = ((int)(nib & 3u) - 1) * kWinCols + ((int)(nib >> 2) - 1);
+    const int my_off = (int)(nib & 3u) * kWinCols + (int)(nib >> 2);
     const int my_tie = 7 - k8;
     int r = __builtin_amdgcn_readfirstlane(trc[2 * i]);
     int c = __builtin_amdgcn_readfirstlane(trc[2 * i + 1]);
@@ -397,23 +400,27 @@ __global__ __launch_bounds__(kLanes * kWalkWaves) void k_walk(
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         int lr = r - R0, lc = c - C0;
-        int pos = lr * kWinCols + lc;
+        int ul = (lr - 1) * kWinCols + (lc - 1);   // upper-left neighbour of the current cell
         // the first maximal neighbour of a reached non-source cell holds its value + 1
-        int v0 = __builtin_amdgcn_readfirstlane(win[pos]);
+        int v0 = __builtin_amdgcn_readfirstlane(win[ul + kWinCols + 1]);
         const int todo = min(kWinSteps, steps - s);
+        // lane k keeps the window position of step k; the window's cells are
+        // stored together after its last step
+        int my_rc = 0;
         for (int k = 0; k < todo; ++k) {
-            const int v = win[pos + my_off];
+            const int v = win[ul + my_off];
             const int key = row_max16((max(v - v0 + 2, 0) << 3) | my_tie);
             const int best = 7 - (__builtin_amdgcn_readfirstlane(key) & 7);
             const uint32_t d = (kDirNibbles >> (4 * best)) & 15u;
             const int dr = (int)(d & 3u) - 1, dc = (int)(d >> 2) - 1;
             lr += dr;
             lc += dc;
-            pos += dr * kWinCols + dc;
+            ul += dr * kWinCols + dc;
             ++v0;
-            if (lane == 0) cells[o] = (R0 + lr) * md.W + (C0 + lc);
-            ++o;
+            my_rc = lane == k ? (lr << 16) | lc : my_rc;
         }
+        if (lane < todo) cells[o + lane] = (R0 + (my_rc >> 16)) * md.W + (C0 + (my_rc & 0xffff));
+        o += todo;
         s += todo;
         r = R0 + lr;
         c = C0 + lc;
