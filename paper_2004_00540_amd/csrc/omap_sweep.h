@@ -169,20 +169,27 @@ __device__ __forceinline__ void load_row(const MazeDev& md, const int32_t* Vin, 
 // decoded into stage 0's slot P (cells outside the grid become exactly
 // 0x80000000) and the same registers then receive the load of row R + D, whose
 // latency overlaps the T-stage arithmetic of the next D rows.
-template <int T, int P, int C, bool GUARD, int D, int SMAX = T - 1>
+// ROW is the row's step index in the visit when known at compile time
+// (warm-up rows), -1 for a steady-state step (index >= 2T), -2 if unknown;
+// bounds that follow from it are not tested at run time.
+template <int T, int P, int C, bool GUARD, int D, int SMAX = T - 1, int ROW = -2>
 __device__ __forceinline__ void sweep_iter(uint32_t (&st)[T][3][C], typename LaneVec<C>::type& v,
                                            uint32_t& w, const MazeDev& md,
                                            const int32_t* Vin, int32_t* Vout, int R, int r0, int r_end,
                                            int col, bool col_ok, bool inner, int smax,
                                            uint64_t& sum_in, uint64_t& sum_out) {
-    const bool ok = R >= 0 && R < md.H && col_ok;
+    constexpr bool kFromR0 = ROW == -1 || ROW >= T;          // R >= r0 (>= 0)
+    constexpr bool kStoreFromR0 = ROW == -1 || ROW >= 2 * T;  // R - T >= r0
+    constexpr bool kAboveTile = ROW >= 0 && ROW < T;          // R < r0
+    constexpr bool kNotStored = ROW >= 0 && ROW < 2 * T;      // R - T < r0
+    const bool ok = (kFromR0 || R >= 0) && R < md.H && col_ok;
     const uint32_t keep = ok ? 0xffffffffu : 0u;
     const uint32_t bits = ok ? (w >> (col & 31)) : 0xFu;   // outside the grid: obstacle
     uint32_t* c = st[0][P];
 #pragma unroll
     for (int j = 0; j < C; ++j) c[j] = ((uint32_t)v[j] & keep) | (((bits >> j) & 1u) << 31);
     load_row<C>(md, Vin, R + D, col, col_ok, v, w);
-    if (inner && R >= r0 && R < r_end) {
+    if (!kAboveTile && inner && (kFromR0 || R >= r0) && R < r_end) {
         uint64_t t = 0;
 #pragma unroll
         for (int j = 0; j < C; ++j) t += c[j] & 0x7fffffffu;
@@ -191,7 +198,7 @@ __device__ __forceinline__ void sweep_iter(uint32_t (&st)[T][3][C], typename Lan
     uint32_t out[C] = {};   // left 0 when the last stage is skipped (its row is not stored then)
     sweep_row<T, P, C, GUARD, SMAX>(st, out, smax);
     const int Ro = R - T;
-    if (inner && Ro >= r0 && Ro < r_end) {
+    if (!kNotStored && inner && (kStoreFromR0 || Ro >= r0) && Ro < r_end) {
         typename LaneVec<C>::type o;
         uint64_t t = 0;
 #pragma unroll
@@ -225,8 +232,9 @@ __device__ __forceinline__ void sweep_rows(uint32_t (&st)[T][3][C], typename Lan
                                            int32_t* Vout, int R, int i, int r0, int r_end, int col,
                                            bool col_ok, bool inner, uint64_t& sum_in, uint64_t& sum_out) {
     if constexpr (J < D) {
-        sweep_iter<T, J % 3, C, GUARD, D>(st, v[J], w[J], md, Vin, Vout, R + J, r0, r_end, col, col_ok, inner,
-                                          GUARD ? ((i + J) >> 1) - 1 : 0, sum_in, sum_out);
+        sweep_iter<T, J % 3, C, GUARD, D, T - 1, GUARD ? -2 : -1>(st, v[J], w[J], md, Vin, Vout, R + J, r0, r_end,
+                                                                  col, col_ok, inner,
+                                                                  GUARD ? ((i + J) >> 1) - 1 : 0, sum_in, sum_out);
         sweep_rows<T, C, GUARD, D, J + 1>(st, v, w, md, Vin, Vout, R, i, r0, r_end, col, col_ok, inner, sum_in,
                                           sum_out);
     }
@@ -242,8 +250,8 @@ __device__ __forceinline__ void sweep_warm(uint32_t (&st)[T][3][C], typename Lan
                                            bool inner, uint64_t& sum_in, uint64_t& sum_out) {
     if constexpr (I < KW) {
         constexpr int SM = (I >> 1) - 1 < T - 1 ? (I >> 1) - 1 : T - 1;
-        sweep_iter<T, I % 3, C, false, D, SM>(st, v[I % D], w[I % D], md, Vin, Vout, R0 + I, r0, r_end, col,
-                                              col_ok, inner, 0, sum_in, sum_out);
+        sweep_iter<T, I % 3, C, false, D, SM, I>(st, v[I % D], w[I % D], md, Vin, Vout, R0 + I, r0, r_end, col,
+                                                 col_ok, inner, 0, sum_in, sum_out);
         sweep_warm<T, C, D, KW, I + 1>(st, v, w, md, Vin, Vout, R0, r0, r_end, col, col_ok, inner, sum_in,
                                        sum_out);
     }
