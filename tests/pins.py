@@ -433,6 +433,66 @@ def check_euclidean_walk(o, n_cases=40):
             assert cost >= min(_octile(tuple(t), s) for s in srcset) - 1e-9
 
 
+def octile_dijkstra(occ, sources):
+    """Shortest Euclidean 8-move distance to the nearest source (orthogonal
+    step 1, diagonal step sqrt 2, diagonal steps between two obstacles allowed
+    as in the 3x3 window): Dijkstra (1959) with a binary heap."""
+    import heapq
+    H, W = occ.shape
+    D = np.full((H, W), np.inf)
+    pq = []
+    for s in np.asarray(sources).reshape(-1, 2):
+        s = (int(s[0]), int(s[1]))
+        D[s] = 0.0
+        pq.append((0.0, s))
+    heapq.heapify(pq)
+    while pq:
+        d, (r, c) = heapq.heappop(pq)
+        if d > D[r, c]:
+            continue
+        for dr, dc in NB:
+            rr, cc = r + dr, c + dc
+            if 0 <= rr < H and 0 <= cc < W and not occ[rr, cc]:
+                nd = d + (math.sqrt(2) if dr and dc else 1.0)
+                if nd < D[rr, cc] - 1e-12:
+                    D[rr, cc] = nd
+                    heapq.heappush(pq, (nd, (rr, cc)))
+    return D
+
+
+def check_euclidean_literal_optimal(o, n_cases=180, min_literal=80):
+    """Sec. "Path Reconstruction" states that the straightened path of the
+    4-neighbour climb (Eq. 1) is shortest in Euclidean distance.  Where the
+    paper's rule applies as written -- every 4-neighbour move rises by one, so
+    after straightening each orthogonal segment rises by 1 and each diagonal
+    segment by 2 -- the oracle's path must cost exactly the octile Dijkstra
+    distance and no more than the simple path of the same map.  (Paths that
+    need the reading's sideways or 8-neighbour moves, where the paper's rule
+    has no next cell, are only checked for validity; some of them cost more
+    than the simple path.)"""
+    literal = 0
+    for m in maze_cases(n_cases, 1007, hmax=40, pmax=0.45):
+        A, _ = o.layers(m.occ, m.sources, -1)
+        D = octile_dijkstra(m.occ, m.sources)
+        l1, o1, c1 = o.walk(A, m.sources, m.targets)
+        l2, o2, c2 = o.walk_euclidean(A, m.sources, m.targets)
+        for k, t in enumerate(m.targets):
+            if l1[k] < 0:
+                assert l2[k] == -1
+                continue
+            p1 = [divmod(int(x), m.W) for x in c1[o1[k]:o1[k + 1]]]
+            p2 = [divmod(int(x), m.W) for x in c2[o2[k]:o2[k + 1]]]
+            rises = [int(A[b] - A[a]) - (2 if (a[0] != b[0] and a[1] != b[1]) else 1) for a, b in zip(p2, p2[1:])]
+            if any(rises):
+                continue
+            literal += 1
+            cost = sum(_octile(a, b) for a, b in zip(p2, p2[1:]))
+            simple = sum(_octile(a, b) for a, b in zip(p1, p1[1:]))
+            assert abs(cost - D[t[0], t[1]]) < 1e-9, (m.name, tuple(t), cost, D[t[0], t[1]])
+            assert cost <= simple + 1e-9, (m.name, tuple(t), cost, simple)
+    assert literal >= min_literal, literal
+
+
 def check_tie_hash_vectors(o):
     """The tie-break hash is SplitMix64's output function: from state 0 the
     published generator yields the three reference values."""
@@ -494,6 +554,7 @@ ALL_CHECKS = [
     check_source_on_obstacle_plateau,
     check_comb_bound,
     check_euclidean_walk,
+    check_euclidean_literal_optimal,
     check_tie_hash_vectors,
     check_walk_random,
 ]
