@@ -271,7 +271,18 @@ omap_status_t omap_batch_destroy(omap_batch_t batch);
  * in at submit; they are admitted into the running set of mazes when a slot
  * and device memory (within memory_budget_bytes) are free, advanced together
  * with every other admitted query, and retired with their paths as soon as
- * they converge, freeing memory for waiting queries.
+ * they converge, freeing memory for waiting queries.  The results of a query
+ * are those of solving it alone with a plan (the paper treats one maze per
+ * run; the tests compare both).
+ *
+ * The engine's host side does not wait for the device while there is device
+ * work to enqueue: occupancy grids are copied to pinned memory at submit and
+ * reach the device by DMA in stream order, convergence is read from counts
+ * copied after each step (one step late), and a retirement runs in three
+ * stream-ordered phases across steps (finalize and path lengths; walk and
+ * copies; hand-over).  A step blocks only to stay at most two steps of
+ * rounds ahead of the device, or, when nothing is left to advance, until the
+ * retirement in flight completes.
  * ------------------------------------------------------------------------- */
 typedef struct omap_engine_s *omap_engine_t;
 
@@ -279,6 +290,11 @@ typedef struct omap_engine_s *omap_engine_t;
 #define OMAP_QUERY_RUNNING 1
 #define OMAP_QUERY_DONE 2
 #define OMAP_QUERY_FAILED 3
+
+/* Flags of omap_engine_submit_ex. */
+#define OMAP_QUERY_KEEP_ACTIVITY 1u   /* keep the query's activity map O (Sec. Methods, "Activity  */
+                                      /* Map Generation") for omap_engine_fetch_activity; costs a  */
+                                      /* device-to-host copy of height*width int32 at retirement   */
 
 /* max_slots: most queries resident at once; memory_budget_bytes: device bytes
  * the engine may hold for query state (activity, masks, paths). */
@@ -296,9 +312,19 @@ omap_status_t omap_engine_submit(omap_engine_t engine, int32_t height, int32_t w
                                  const int32_t *targets_host, int32_t n_targets,
                                  int64_t max_layers, int64_t *query_id);
 
-/* One engine step: admit waiting queries that fit, advance all resident
- * queries by up to `rounds` temporal blocks, retire the converged ones
- * (paths extracted to host).  *n_resident / *n_done_total may be NULL. */
+/* omap_engine_submit with flags (0 or OMAP_QUERY_KEEP_ACTIVITY); same
+ * validation and errors, plus INVALID_ARG for unknown flags. */
+omap_status_t omap_engine_submit_ex(omap_engine_t engine, int32_t height, int32_t width,
+                                    const uint8_t *occupancy_host,
+                                    const int32_t *sources_host, int32_t n_sources,
+                                    const int32_t *targets_host, int32_t n_targets,
+                                    int64_t max_layers, uint32_t flags, int64_t *query_id);
+
+/* One engine step: admit waiting queries that fit, advance all running
+ * queries by `rounds` temporal blocks, and move converged queries through
+ * retirement (paths, and kept activity maps, copied to host).  A query is
+ * DONE a few steps after it converged.  *n_resident (queries holding a
+ * slot) / *n_done_total (DONE or FAILED so far) may be NULL. */
 omap_status_t omap_engine_step(omap_engine_t engine, int32_t rounds, int32_t *n_resident,
                                int64_t *n_done_total);
 
@@ -313,6 +339,14 @@ omap_status_t omap_engine_fetch(omap_engine_t engine, int64_t query_id, int32_t 
                                 int64_t *offsets_host, int32_t *cells_host,
                                 int64_t cells_capacity, int64_t *cells_needed_host,
                                 omap_propagate_info *info_host);
+
+/* Activity map O of a DONE query submitted with OMAP_QUERY_KEEP_ACTIVITY
+ * (the same map omap_get_activity gives for the maze alone):
+ *   dst_host: height rows of width int32, row stride dst_pitch_elems >= width.
+ * Call before omap_engine_fetch, which forgets the query.  Errors:
+ * INVALID_ARG (NULL, pitch, flag not given), NOT_FOUND, BUSY. */
+omap_status_t omap_engine_fetch_activity(omap_engine_t engine, int64_t query_id, int32_t *dst_host,
+                                         int64_t dst_pitch_elems);
 
 omap_status_t omap_engine_destroy(omap_engine_t engine);
 

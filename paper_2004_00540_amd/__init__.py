@@ -29,6 +29,7 @@ SCHEDULE_ACTIVE = 0
 SCHEDULE_DENSE = 1
 SCHEDULE_BITS = 2
 QUERY_QUEUED, QUERY_RUNNING, QUERY_DONE, QUERY_FAILED = 0, 1, 2, 3
+QUERY_KEEP_ACTIVITY = 1
 
 STATUS = {
     0: "OMAP_OK", 1: "OMAP_ERR_INVALID_ARG", 2: "OMAP_ERR_TOO_LARGE",
@@ -106,6 +107,8 @@ def lib() -> ctypes.CDLL:
         "omap_batch_destroy": [P],
         "omap_engine_create": [PP, i64, i32, P, P],
         "omap_engine_submit": [P, i32, i32, P, P, i32, P, i32, i64, P],
+        "omap_engine_submit_ex": [P, i32, i32, P, P, i32, P, i32, i64, ctypes.c_uint32, P],
+        "omap_engine_fetch_activity": [P, i64, P, i64],
         "omap_engine_step": [P, i32, P, P],
         "omap_engine_poll": [P, i64, P],
         "omap_engine_fetch": [P, i64, P, P, P, i64, P, P],
@@ -387,17 +390,31 @@ class Engine:
                                         ctypes.byref(self._opts), ctypes.c_void_p(_stream(stream))))
         self.handle = h
         self._nt = {}
+        self._shape = {}
 
-    def submit(self, occupancy: np.ndarray, sources, targets, layers: int = AUTO) -> int:
+    def submit(self, occupancy: np.ndarray, sources, targets, layers: int = AUTO,
+               keep_activity: bool = False) -> int:
+        """Queue a query (omap_engine_submit_ex); keep_activity keeps its
+        activity map for activity()."""
         occ = np.ascontiguousarray(occupancy, dtype=np.uint8)
         src = _rc(sources)
         tgt = _rc(targets if targets is not None else np.zeros((0, 2), np.int32))
         qid = ctypes.c_int64()
-        _check(lib().omap_engine_submit(self.handle, occ.shape[0], occ.shape[1], _host_ptr(occ),
-                                        _host_ptr(src), len(src), _host_ptr(tgt), len(tgt),
-                                        int(layers), ctypes.byref(qid)))
+        _check(lib().omap_engine_submit_ex(self.handle, occ.shape[0], occ.shape[1], _host_ptr(occ),
+                                           _host_ptr(src), len(src), _host_ptr(tgt), len(tgt),
+                                           int(layers), QUERY_KEEP_ACTIVITY if keep_activity else 0,
+                                           ctypes.byref(qid)))
         self._nt[qid.value] = len(tgt)
+        self._shape[qid.value] = (int(occ.shape[0]), int(occ.shape[1]))
         return qid.value
+
+    def activity(self, qid: int) -> np.ndarray:
+        """Activity map (int32 (H, W), host) of a finished query submitted with
+        keep_activity; call before fetch()."""
+        H, W = self._shape[qid]
+        out = np.empty((H, W), np.int32)
+        _check(lib().omap_engine_fetch_activity(self.handle, int(qid), out.ctypes.data_as(ctypes.c_void_p), W))
+        return out
 
     def step(self, rounds: int = 4):
         res, done = ctypes.c_int32(), ctypes.c_int64()
@@ -420,6 +437,7 @@ class Engine:
                                      ctypes.byref(needed), ctypes.byref(info))
         if st == OK:     # no target has a path: the query is complete already
             del self._nt[qid]
+            self._shape.pop(qid, None)
             return QueryResult(ln[:nt], off, np.zeros(0, np.int32), info.as_dict())
         if st != ERR_BUFFER_TOO_SMALL:
             _check(st)
@@ -429,6 +447,7 @@ class Engine:
                                        cells.ctypes.data_as(ctypes.c_void_p), cells.size,
                                        ctypes.byref(needed), ctypes.byref(info)))
         del self._nt[qid]
+        self._shape.pop(qid, None)
         return QueryResult(ln[:nt], off, cells[: int(needed.value)], info.as_dict())
 
     def close(self):

@@ -189,18 +189,22 @@ class DirectMemory : public DeviceMemory {
     }
 };
 
-// One hipMalloc of the whole budget, carved into 256-byte aligned blocks by a
-// best-fit free list.  Reuse after release is safe in stream order because all
-// work of the owner runs on one stream.
+// One allocation of the whole budget (device memory, or pinned host memory with
+// `pinned`), carved into 256-byte aligned blocks by a best-fit free list.
+// Reuse of device blocks after release is safe in stream order because all
+// work of the owner runs on one stream; pinned blocks read by copies in flight
+// are released through PinnedPool, which waits for those copies first.
 class ArenaMemory : public DeviceMemory {
    public:
     ~ArenaMemory() override {
-        if (base_) (void)hipFree(base_);
+        if (base_) (void)(pinned_ ? hipHostFree(base_) : hipFree(base_));
     }
     void* base() const { return base_; }
-    bool init(size_t bytes) {
+    bool init(size_t bytes, bool pinned = false) {
         bytes = (bytes + 255) & ~size_t(255);
-        if (hipMalloc(&base_, bytes) != hipSuccess) {
+        pinned_ = pinned;
+        const hipError_t e = pinned ? hipHostMalloc(&base_, bytes, hipHostMallocDefault) : hipMalloc(&base_, bytes);
+        if (e != hipSuccess) {
             (void)hipGetLastError();
             base_ = nullptr;
             return false;
@@ -248,12 +252,94 @@ class ArenaMemory : public DeviceMemory {
     }
     size_t size() const { return size_; }
     size_t in_use() const { return in_use_; }
+    bool owns(const void* p) const {
+        return base_ && p >= base_ && static_cast<const char*>(p) < static_cast<const char*>(base_) + size_;
+    }
 
    private:
     void* base_ = nullptr;
+    bool pinned_ = false;
     size_t size_ = 0, in_use_ = 0;
     std::map<size_t, size_t> free_;   // offset -> length
     std::map<size_t, size_t> used_;
+};
+
+// Pinned host staging.  A host-to-device copy from pageable memory makes the
+// host wait until the stream has drained up to it; staged through pinned
+// memory it is a plain DMA in stream order, so the host can keep enqueueing
+// work.  A block stays reserved until an event recorded after the copies that
+// read it has completed.
+class PinnedPool {
+   public:
+    ~PinnedPool() { clear(); }
+    bool init(size_t bytes) { return arena_.init(bytes, true); }
+    bool ready() const { return arena_.base() != nullptr; }
+    size_t size() const { return arena_.size(); }
+
+    // A pinned block of n bytes, nullptr if none is free even after waiting
+    // for every pending release (the caller then copies from pageable memory).
+    void* alloc(size_t n) {
+        if (!ready() || n > arena_.size()) return nullptr;
+        reap(false);
+        void* p = arena_.alloc(n);
+        while (!p && !pending_.empty()) {
+            reap_one(true);
+            p = arena_.alloc(n);
+        }
+        return p;
+    }
+    // Release p once the work enqueued on s so far has completed.
+    hipError_t release_after(void* p, hipStream_t s) {
+        hipEvent_t ev = nullptr;
+        hipError_t e = spare_.empty() ? hipEventCreateWithFlags(&ev, hipEventDisableTiming) : hipSuccess;
+        if (e != hipSuccess) return e;
+        if (!ev) {
+            ev = spare_.back();
+            spare_.pop_back();
+        }
+        e = hipEventRecord(ev, s);
+        if (e != hipSuccess) {
+            spare_.push_back(ev);
+            return e;
+        }
+        pending_.push_back({p, ev});
+        return hipSuccess;
+    }
+    // Release p now (nothing in flight reads it).
+    void release_now(void* p) { arena_.release(p); }
+    bool owns(const void* p) const { return arena_.owns(p); }
+
+    // Frees the blocks whose copies have completed (all of them with wait).
+    void reap(bool wait) {
+        while (!pending_.empty()) {
+            if (!wait && hipEventQuery(pending_.front().second) != hipSuccess) {
+                (void)hipGetLastError();
+                break;
+            }
+            reap_one(true);
+        }
+    }
+
+   private:
+    void reap_one(bool wait) {
+        auto [p, ev] = pending_.front();
+        if (wait) (void)hipEventSynchronize(ev);
+        pending_.pop_front();
+        arena_.release(p);
+        spare_.push_back(ev);
+    }
+    void clear() {
+        for (auto& pe : pending_) {
+            (void)hipEventSynchronize(pe.second);
+            (void)hipEventDestroy(pe.second);
+        }
+        pending_.clear();
+        for (hipEvent_t e : spare_) (void)hipEventDestroy(e);
+        spare_.clear();
+    }
+    ArenaMemory arena_;
+    std::deque<std::pair<void*, hipEvent_t>> pending_;
+    std::vector<hipEvent_t> spare_;
 };
 
 // ---------------------------------------------------------------------------
@@ -372,8 +458,7 @@ class Solver {
     size_t scratch_bytes = 0;
     int32_t* d_start_ = nullptr;              // grow-only staging of start_many
     size_t start_cap_ = 0;
-    std::vector<int32_t> start_stage_;        // host copy of the last staging upload
-    std::vector<char> add_stage_;             // host copy of add_many's upload
+    PinnedPool pin;                           // pinned staging of host-to-device copies
 
     int64_t next_round = 0;                   // index of the next round to run
     int parity = 0;                           // next_round mod 2: activity buffer holding the latest values
@@ -405,6 +490,10 @@ class Solver {
         h_pinned = nullptr;
         if (h_bad) (void)hipHostFree(h_bad);
         h_bad = nullptr;
+        if (h_fin_min) (void)hipHostFree(h_fin_min);
+        h_fin_min = nullptr;
+        if (h_fin_reached) (void)hipHostFree(h_fin_reached);
+        h_fin_reached = nullptr;
         for (auto& e : prof_events) {
             (void)hipEventDestroy(e.first);
             (void)hipEventDestroy(e.second);
@@ -421,8 +510,25 @@ class Solver {
         return OMAP_OK;
     }
 
+    // Stream-ordered host-to-device copy of n bytes that does not make the
+    // host wait for the stream: staged through pinned memory when a block is
+    // free, else copied from the caller's memory (then the host waits).
+    omap_status_t upload(void* dst, const void* src, size_t n) {
+        if (n == 0) return OMAP_OK;
+        void* p = pin.alloc(n);
+        if (p) {
+            std::memcpy(p, src, n);
+            HIP_TRY(hipMemcpyAsync(dst, p, n, hipMemcpyHostToDevice, stream));
+            HIP_TRY(pin.release_after(p, stream));
+            return OMAP_OK;
+        }
+        HIP_TRY(hipMemcpyAsync(dst, src, n, hipMemcpyHostToDevice, stream));
+        HIP_TRY(hipStreamSynchronize(stream));
+        return OMAP_OK;
+    }
+
     omap_status_t init(hipStream_t s, const Options& o, DeviceMemory* m, int32_t slots_cap,
-                       int32_t tiles_cap) {
+                       int32_t tiles_cap, size_t pinned_bytes = size_t(1) << 20) {
         stream = s;
         opt = o;
         mem = m;
@@ -456,6 +562,9 @@ class Solver {
         OK_TRY(dalloc(&d_bad, 1));
         OK_TRY(dalloc(&d_sel, cap_slots));
         HIP_TRY(hipHostMalloc((void**)&h_pinned, 64 * sizeof(int32_t), hipHostMallocDefault));
+        HIP_TRY(hipHostMalloc((void**)&h_fin_min, sizeof(int32_t) * cap_slots, hipHostMallocDefault));
+        HIP_TRY(hipHostMalloc((void**)&h_fin_reached, sizeof(unsigned long long) * cap_slots, hipHostMallocDefault));
+        if (!pin.init(pinned_bytes)) return fail(OMAP_ERR_OUT_OF_MEMORY, "pinned staging (%zu bytes)", pinned_bytes);
         HIP_TRY(hipMemsetAsync(d_tile_maze, 0xff, sizeof(int32_t) * cap_tiles, stream));
         HIP_TRY(hipMemsetAsync(d_flags[0], 0, sizeof(int32_t) * cap_tiles, stream));
         HIP_TRY(hipMemsetAsync(d_flags[1], 0, sizeof(int32_t) * cap_tiles, stream));
@@ -564,8 +673,7 @@ class Solver {
     // mirror outlives the copy).
     omap_status_t upload_desc(int32_t k) {
         set_desc(k);
-        HIP_TRY(hipMemcpyAsync(d_mazes + k, &h_mazes[k], sizeof(MazeDev), hipMemcpyHostToDevice, stream));
-        return OMAP_OK;
+        return upload(d_mazes + k, &h_mazes[k], sizeof(MazeDev));
     }
 
     // Host mirror of slot k's descriptor.
@@ -588,7 +696,8 @@ class Solver {
         md.round0 = (int32_t)s.first_round;
     }
 
-    // Grow-only device staging of start_many (synchronizes only to grow).
+    // Grow-only device staging of start_many (synchronizes only to grow; the
+    // next start's upload is ordered after this start's kernels on the stream).
     omap_status_t start_scratch(size_t n_int32, int32_t** out) {
         if (n_int32 > start_cap_) {
             HIP_TRY(hipStreamSynchronize(stream));
@@ -598,9 +707,6 @@ class Solver {
             const size_t want = std::max<size_t>(n_int32, 1024);
             HIP_TRY(hipMalloc(&d_start_, want * sizeof(int32_t)));
             start_cap_ = want;
-        } else {
-            // the previous start's upload may still be in flight from start_stage_
-            HIP_TRY(hipStreamSynchronize(stream));
         }
         *out = d_start_;
         return OMAP_OK;
@@ -609,8 +715,7 @@ class Solver {
     omap_status_t upload_tile_range(int32_t base, int32_t n, int32_t value) {
         if (n <= 0) return OMAP_OK;
         std::fill(h_tile_maze.begin() + base, h_tile_maze.begin() + base + n, value);
-        HIP_TRY(hipMemcpyAsync(d_tile_maze + base, h_tile_maze.data() + base, sizeof(int32_t) * n,
-                               hipMemcpyHostToDevice, stream));
+        HIP_TRY(launch_fill(d_tile_maze + base, n, value, stream));
         return OMAP_OK;
     }
 
@@ -654,20 +759,23 @@ class Solver {
 
     // Pack one maze into slot k and check its sources on the device; the
     // verdict is read by commit() (stream-ordered, no host wait).
+    // With check_sources = false the caller has checked the sources itself.
     omap_status_t pack_async(int32_t k, const uint8_t* occ_dev, const int32_t* src, int32_t n_src,
-                             const int32_t* tgt, int32_t n_tgt) {
+                             const int32_t* tgt, int32_t n_tgt, bool check_sources = true) {
         Slot& s = slots[k];
         OK_TRY(validate_problem(s.g.H, s.g.W, occ_dev, src, n_src, tgt, n_tgt));
         s.src.assign(src, src + 2 * n_src);
         if (tgt && n_tgt > 0) s.tgt.assign(tgt, tgt + 2 * n_tgt);
         else s.tgt.clear();
-        mem->release(s.d_src);
-        s.d_src = static_cast<int32_t*>(mem->alloc(sizeof(int32_t) * 2 * n_src));
-        if (!s.d_src) return fail(OMAP_ERR_OUT_OF_MEMORY, "source list (%d sources)", n_src);
         HIP_TRY(launch_pack_mask(occ_dev, s.g.H, s.g.W, s.mask, s.g.mpitch, stream));
-        HIP_TRY(hipMemcpyAsync(s.d_src, s.src.data(), sizeof(int32_t) * 2 * n_src, hipMemcpyHostToDevice, stream));
-        HIP_TRY(hipMemsetAsync(d_bad_slot + k, 0, sizeof(int32_t), stream));
-        HIP_TRY(launch_check_sources(s.mask, s.g.mpitch, s.d_src, n_src, d_bad_slot + k, stream));
+        if (check_sources) {
+            mem->release(s.d_src);
+            s.d_src = static_cast<int32_t*>(mem->alloc(sizeof(int32_t) * 2 * n_src));
+            if (!s.d_src) return fail(OMAP_ERR_OUT_OF_MEMORY, "source list (%d sources)", n_src);
+            OK_TRY(upload(s.d_src, s.src.data(), sizeof(int32_t) * 2 * n_src));
+            HIP_TRY(launch_fill(d_bad_slot + k, 1, 0, stream));
+            HIP_TRY(launch_check_sources(s.mask, s.g.mpitch, s.d_src, n_src, d_bad_slot + k, stream));
+        }
         s.started = s.finalized = false;
         s.layers = -1;
         return OMAP_OK;
@@ -699,7 +807,7 @@ class Solver {
     // a failing maze is removed again.
     omap_status_t add(int32_t H, int32_t W, const uint8_t* occ_dev, const int32_t* src,
                       int32_t n_src, const int32_t* tgt, int32_t n_tgt, int32_t* slot_out,
-                      bool defer = false) {
+                      bool defer = false, bool check_sources = true) {
         OK_TRY(validate_problem(H, W, occ_dev, src, n_src, tgt, n_tgt));
         const int32_t k = free_slot_index();
         if (k < 0) return fail(OMAP_ERR_OUT_OF_MEMORY, "no free maze slot (capacity %d)", cap_slots);
@@ -722,7 +830,7 @@ class Solver {
             remove(k);
             return fail(OMAP_ERR_OUT_OF_MEMORY, "activity and mask buffers for %d x %d", H, W);
         }
-        omap_status_t st = pack_async(k, occ_dev, src, n_src, tgt, n_tgt);
+        omap_status_t st = pack_async(k, occ_dev, src, n_src, tgt, n_tgt, check_sources);
         if (st == OMAP_OK) st = upload_tile_range(s.tile_base, s.n_tiles, k);
         if (st == OMAP_OK) st = upload_desc(k);
         if (st == OMAP_OK && !defer) {
@@ -792,14 +900,13 @@ class Solver {
         const size_t b_sl = (sizeof(int32_t) * src_slot.size() + 255) & ~size_t(255);
         char* base = nullptr;
         OK_TRY(scratch(b_jobs + b_rc + b_sl, &base));
-        add_stage_.assign(b_jobs + b_rc + b_sl, 0);
-        std::memcpy(add_stage_.data(), jobs.data(), sizeof(PackJob) * jobs.size());
-        std::memcpy(add_stage_.data() + b_jobs, src_rc.data(), sizeof(int32_t) * src_rc.size());
-        std::memcpy(add_stage_.data() + b_jobs + b_rc, src_slot.data(), sizeof(int32_t) * src_slot.size());
-        HIP_TRY(hipMemcpyAsync(base, add_stage_.data(), add_stage_.size(), hipMemcpyHostToDevice, stream));
-        HIP_TRY(hipMemcpyAsync(d_tile_maze, h_tile_maze.data(), sizeof(int32_t) * tile_hwm, hipMemcpyHostToDevice,
-                               stream));
-        HIP_TRY(hipMemcpyAsync(d_mazes, h_mazes.data(), sizeof(MazeDev) * cap_slots, hipMemcpyHostToDevice, stream));
+        std::vector<char> stage(b_jobs + b_rc + b_sl, 0);
+        std::memcpy(stage.data(), jobs.data(), sizeof(PackJob) * jobs.size());
+        std::memcpy(stage.data() + b_jobs, src_rc.data(), sizeof(int32_t) * src_rc.size());
+        std::memcpy(stage.data() + b_jobs + b_rc, src_slot.data(), sizeof(int32_t) * src_slot.size());
+        OK_TRY(upload(base, stage.data(), stage.size()));
+        OK_TRY(upload(d_tile_maze, h_tile_maze.data(), sizeof(int32_t) * tile_hwm));
+        OK_TRY(upload(d_mazes, h_mazes.data(), sizeof(MazeDev) * cap_slots));
         HIP_TRY(hipMemsetAsync(d_bad_slot, 0, sizeof(int32_t) * cap_slots, stream));
         HIP_TRY(launch_pack_mask_many(reinterpret_cast<const PackJob*>(base), n, words, stream));
         HIP_TRY(launch_check_sources_many(d_mazes, reinterpret_cast<const int32_t*>(base + b_jobs),
@@ -857,7 +964,7 @@ class Solver {
             seed_rc.insert(seed_rc.end(), s.src.begin(), s.src.end());
             seed_slot.insert(seed_slot.end(), s.src.size() / 2, k);
         }
-        HIP_TRY(hipMemcpyAsync(d_mazes, h_mazes.data(), sizeof(MazeDev) * cap_slots, hipMemcpyHostToDevice, stream));
+        OK_TRY(upload(d_mazes, h_mazes.data(), sizeof(MazeDev) * cap_slots));
         const RoundArgs a = round_args(true);
         // staging: selection | slot list | seed (r, c) pairs | seed slots
         const int32_t n_seed = (int32_t)seed_slot.size(), n_which = (int32_t)which.size();
@@ -869,7 +976,7 @@ class Solver {
         stage.insert(stage.end(), seed_slot.begin(), seed_slot.end());
         int32_t* d_stage = nullptr;
         OK_TRY(start_scratch(stage.size(), &d_stage));
-        HIP_TRY(hipMemcpyAsync(d_stage, stage.data(), sizeof(int32_t) * stage.size(), hipMemcpyHostToDevice, stream));
+        OK_TRY(upload(d_stage, stage.data(), sizeof(int32_t) * stage.size()));
         const int32_t* d_sel_s = d_stage;
         const int32_t* d_which = d_stage + cap_slots;
         const int32_t* d_seed_rc = d_which + n_which;
@@ -889,9 +996,6 @@ class Solver {
         }
         HIP_TRY(launch_slot_reset(a, d_which, n_which, stream));
         HIP_TRY(launch_seed(a, 0, d_seed_rc, d_seed_slot, n_seed, d_bad, stream));
-        // the staging buffer is reused by the next start: keep the host copy
-        // alive until the upload has been consumed
-        start_stage_.swap(stage);
         for (int32_t k : which) {
             Slot& s = slots[k];
             s.started = true;
@@ -1062,15 +1166,15 @@ class Solver {
         return OMAP_OK;
     }
 
-    // Smallest positive activity and reached count of the selected slots
-    // (sel == nullptr: every slot), then layers = L or K - min (synchronous).
-    omap_status_t finalize(const std::vector<int32_t>& which) {
-        std::vector<int32_t> mins(cap_slots, 0x7fffffff);
-        HIP_TRY(hipMemcpyAsync(d_min, mins.data(), sizeof(int32_t) * cap_slots, hipMemcpyHostToDevice, stream));
-        HIP_TRY(hipMemsetAsync(d_reached, 0, sizeof(unsigned long long) * cap_slots, stream));
+    // Enqueues the reduction of the selected slots: their smallest positive
+    // activity and reached count land in h_min / h_reached (pinned host
+    // arrays of cap_slots entries) once the stream gets there.
+    omap_status_t finalize_enqueue(const std::vector<int32_t>& which, int32_t* h_min, unsigned long long* h_reached) {
+        HIP_TRY(launch_fill(d_min, cap_slots, 0x7fffffff, stream));
+        HIP_TRY(launch_fill(reinterpret_cast<int32_t*>(d_reached), 2 * (int64_t)cap_slots, 0, stream));
         std::vector<int32_t> sel(cap_slots, 0);
         for (int32_t k : which) sel[k] = 1;
-        HIP_TRY(hipMemcpyAsync(d_sel, sel.data(), sizeof(int32_t) * cap_slots, hipMemcpyHostToDevice, stream));
+        OK_TRY(upload(d_sel, sel.data(), sizeof(int32_t) * cap_slots));
         int32_t lo = tile_hwm, hi = 0;
         for (int32_t k : which) {
             lo = std::min(lo, slots[k].tile_base);
@@ -1078,17 +1182,34 @@ class Solver {
         }
         HIP_TRY(launch_reduce(d_mazes, d_tile_maze, d_touched, lo, hi, d_sel, opt.TH, opt.TW, vparity(), d_min,
                               d_reached, stream));
-        std::vector<unsigned long long> reached(cap_slots);
-        HIP_TRY(hipMemcpyAsync(mins.data(), d_min, sizeof(int32_t) * cap_slots, hipMemcpyDeviceToHost, stream));
-        HIP_TRY(hipMemcpyAsync(reached.data(), d_reached, sizeof(unsigned long long) * cap_slots,
-                               hipMemcpyDeviceToHost, stream));
-        HIP_TRY(hipStreamSynchronize(stream));
+        HIP_TRY(hipMemcpyAsync(h_min, d_min, sizeof(int32_t) * cap_slots, hipMemcpyDeviceToHost, stream));
+        HIP_TRY(hipMemcpyAsync(h_reached, d_reached, sizeof(unsigned long long) * cap_slots, hipMemcpyDeviceToHost,
+                               stream));
+        return OMAP_OK;
+    }
+
+    // Layers (L or K - min) and reached counts of the selected slots from a
+    // completed finalize_enqueue.
+    void finalize_apply(const std::vector<int32_t>& which, const int32_t* h_min,
+                        const unsigned long long* h_reached) {
         for (int32_t k : which) {
             Slot& s = slots[k];
-            s.layers = s.L_req >= 0 ? s.L_req : (int64_t)s.K - mins[k];
-            s.reached = (int64_t)reached[k];
+            s.layers = s.L_req >= 0 ? s.L_req : (int64_t)s.K - h_min[k];
+            s.reached = (int64_t)h_reached[k];
             s.finalized = true;
         }
+    }
+
+    // Pinned host arrays of the synchronous finalize (cap_slots each).
+    int32_t* h_fin_min = nullptr;
+    unsigned long long* h_fin_reached = nullptr;
+
+    // Smallest positive activity and reached count of the selected slots,
+    // then layers = L or K - min (synchronous).
+    omap_status_t finalize(const std::vector<int32_t>& which) {
+        OK_TRY(finalize_enqueue(which, h_fin_min, h_fin_reached));
+        HIP_TRY(hipStreamSynchronize(stream));
+        finalize_apply(which, h_fin_min, h_fin_reached);
         return OMAP_OK;
     }
 
@@ -1215,14 +1336,13 @@ class Solver {
         // lengths and offsets (the Euclidean walk learns its lengths by walking)
         auto lengths = [&](decltype(q)& d) -> omap_status_t {
             if (n > 0) {
-                HIP_TRY(hipMemcpyAsync(d.tslot, tslot.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, stream));
-                HIP_TRY(hipMemcpyAsync(d.trc, trc.data(), sizeof(int32_t) * 2 * n, hipMemcpyHostToDevice, stream));
-                HIP_TRY(hipMemcpyAsync(d.tlocal, tlocal.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, stream));
+                OK_TRY(upload(d.tslot, tslot.data(), sizeof(int32_t) * n));
+                OK_TRY(upload(d.trc, trc.data(), sizeof(int32_t) * 2 * n));
+                OK_TRY(upload(d.tlocal, tlocal.data(), sizeof(int32_t) * n));
                 if (src_out) {
-                    HIP_TRY(hipMemcpyAsync(d.sbase, sbase.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, stream));
-                    HIP_TRY(hipMemcpyAsync(d.scount, scount.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, stream));
-                    HIP_TRY(hipMemcpyAsync(d.ss, ssorted.data(), sizeof(int32_t) * ssorted.size(),
-                                           hipMemcpyHostToDevice, stream));
+                    OK_TRY(upload(d.sbase, sbase.data(), sizeof(int32_t) * n));
+                    OK_TRY(upload(d.scount, scount.data(), sizeof(int32_t) * n));
+                    OK_TRY(upload(d.ss, ssorted.data(), sizeof(int32_t) * ssorted.size()));
                 }
                 if (mode == 2)
                     HIP_TRY(launch_walk_euclid(false, d_mazes, d.tslot, d.trc, n, vparity(), d.len, nullptr, nullptr, stream));
@@ -1234,7 +1354,7 @@ class Solver {
         };
         OK_TRY(lengths(q));
         HIP_TRY(hipMemcpyAsync(h_pinned, q.off + n, sizeof(int64_t), hipMemcpyDeviceToHost, stream));
-        HIP_TRY(hipStreamSynchronize(stream));   // also retires the host sources of the uploads
+        HIP_TRY(hipStreamSynchronize(stream));
         int64_t total = 0;
         std::memcpy(&total, h_pinned, sizeof total);
         if (needed) *needed = total;
@@ -1353,9 +1473,11 @@ namespace omap {
 struct Query {
     int64_t id = 0;
     int32_t H = 0, W = 0;
-    std::vector<uint8_t> occ;
+    std::vector<uint8_t> occ;     // copy of the occupancy when no pinned block was free at submit
+    uint8_t* occ_pinned = nullptr;
     std::vector<int32_t> src, tgt;
     int64_t L = -1;
+    uint32_t flags = 0;           // OMAP_QUERY_KEEP_ACTIVITY
     int32_t state = OMAP_QUERY_QUEUED;
     int32_t slot = -1;
     int64_t bytes = 0;
@@ -1363,7 +1485,58 @@ struct Query {
     std::vector<int32_t> len;
     std::vector<int64_t> off;
     std::vector<int32_t> cells;
+    std::vector<int32_t> activity;   // kept activity map (H x W) with OMAP_QUERY_KEEP_ACTIVITY
     omap_propagate_info info{};
+};
+
+// Grow-only pinned host buffer.
+struct PinnedBuffer {
+    char* p = nullptr;
+    size_t size = 0;
+    ~PinnedBuffer() {
+        if (p) (void)hipHostFree(p);
+    }
+    omap_status_t reserve(size_t bytes) {
+        if (bytes <= size) return OMAP_OK;
+        if (p) (void)hipHostFree(p);
+        p = nullptr;
+        size = 0;
+        const size_t want = std::max(bytes, size_t(1) << 20);
+        HIP_TRY(hipHostMalloc((void**)&p, want, hipHostMallocDefault));
+        size = want;
+        return OMAP_OK;
+    }
+};
+
+// Per-slot convergence counts copied to the host after a step's rounds.
+struct Snapshot {
+    int32_t* counts = nullptr;   // pinned, cap_slots entries
+    hipEvent_t ev = nullptr;
+    int64_t round = 0;           // next_round when the copy was enqueued
+    bool busy = false;
+};
+
+// Retirement of the mazes found converged together, in three stream-ordered
+// phases so that the host never waits for the device: (1) finalize and path
+// lengths, (2) once their sizes are known on the host, the walk and the copies
+// of paths, counters and kept activity maps, (3) the results handed to the
+// queries and the slots freed.
+struct Retirement {
+    int phase = 0;               // 0 idle, 1 lengths in flight, 2 paths in flight
+    std::vector<int64_t> ids;
+    std::vector<int32_t> slots;
+    int32_t n = 0;               // targets of all of them
+    int64_t total = 0;           // path cells of all of them
+    hipEvent_t ev = nullptr;
+    int32_t* h_min = nullptr;    // pinned, cap_slots
+    unsigned long long* h_reached = nullptr;
+    PinnedBuffer h_lo;           // lengths, offsets
+    PinnedBuffer h_out;          // counters, cells, kept activity maps
+    std::vector<int64_t> act_off;   // per retiring query: byte offset of its map in h_out (-1 = none)
+    int32_t* d_cells = nullptr;  // grow-only device buffers
+    size_t cells_cap = 0;
+    int32_t* d_act = nullptr;
+    size_t act_cap = 0;
 };
 
 }  // namespace omap
@@ -1371,16 +1544,40 @@ struct Query {
 struct omap_engine_s {
     omap::ArenaMemory mem;
     omap::Solver solver;
+    omap::PinnedPool occ_pool;       // pinned copies of submitted occupancy grids
     int64_t budget = 0;
     int32_t max_slots = 0;
     int64_t next_id = 1;
     int64_t done_total = 0;
     std::deque<int64_t> waiting;
     std::unordered_map<int64_t, omap::Query> queries;
-    std::vector<int64_t> resident;   // query ids
+    std::vector<int64_t> running;     // admitted, not yet seen converged
+    std::vector<int64_t> converged;   // seen converged, waiting for a retirement
+    omap::Snapshot snap[2];
+    int snap_next = 0;                // snapshot slot the next copy goes to
+    omap::Retirement ret;
+
+    ~omap_engine_s() {
+        (void)hipStreamSynchronize(solver.stream);
+        for (auto& sn : snap) {
+            if (sn.ev) (void)hipEventDestroy(sn.ev);
+            if (sn.counts) (void)hipHostFree(sn.counts);
+        }
+        if (ret.ev) (void)hipEventDestroy(ret.ev);
+        if (ret.h_min) (void)hipHostFree(ret.h_min);
+        if (ret.h_reached) (void)hipHostFree(ret.h_reached);
+        if (ret.d_cells) (void)hipFree(ret.d_cells);
+        if (ret.d_act) (void)hipFree(ret.d_act);
+    }
+    int32_t resident() const {
+        return (int32_t)(running.size() + converged.size() + ret.ids.size());
+    }
 };
 
 namespace omap {
+
+// Byte offset of the offsets array in a retirement's lengths / offsets buffer.
+static size_t lo_offsets_at(size_t n) { return (4 * (n + 1) + 63) & ~size_t(63); }
 
 static int64_t query_bytes(const Query& q, const Options& o) {
     // activity ping-pong + mask + staging of the occupancy + path scratch
@@ -1389,114 +1586,311 @@ static int64_t query_bytes(const Query& q, const Options& o) {
            nt * 64 + nt * 4 * ((int64_t)q.H + q.W) + 4096;
 }
 
+static void query_release_occ(omap_engine_s* e, Query& q) {
+    if (q.occ_pinned) e->occ_pool.release_now(q.occ_pinned);
+    q.occ_pinned = nullptr;
+    q.occ.clear();
+    q.occ.shrink_to_fit();
+}
+
+// Admits waiting queries in arrival order while a slot and device memory are
+// free: sources checked on the host copy, occupancy copied in and packed,
+// then one start for all of them.  Nothing here waits for the device.
 static omap_status_t engine_admit(omap_engine_s* e) {
-    while (!e->waiting.empty() && (int32_t)e->resident.size() < e->max_slots) {
+    Solver& sv = e->solver;
+    std::vector<int32_t> started;
+    std::vector<int64_t> Ls, ids;
+    e->occ_pool.reap(false);
+    while (!e->waiting.empty() && e->resident() + (int32_t)started.size() < e->max_slots) {
         Query& q = e->queries[e->waiting.front()];
         if ((int64_t)e->mem.in_use() + q.bytes > (int64_t)e->mem.size()) break;   // wait for memory
-        e->waiting.pop_front();
-        void* occ_dev = e->mem.alloc(q.occ.size());
-        if (!occ_dev) {
-            e->waiting.push_front(q.id);
-            break;
-        }
-        HIP_TRY(hipMemcpyAsync(occ_dev, q.occ.data(), q.occ.size(), hipMemcpyHostToDevice, e->solver.stream));
-        int32_t slot = -1;
-        omap_status_t st = e->solver.add(q.H, q.W, static_cast<uint8_t*>(occ_dev), q.src.data(),
-                                         (int32_t)(q.src.size() / 2), q.tgt.empty() ? nullptr : q.tgt.data(),
-                                         (int32_t)(q.tgt.size() / 2), &slot);
-        e->mem.release(occ_dev);
-        if (st != OMAP_OK) {
-            if (st == OMAP_ERR_OUT_OF_MEMORY && !e->resident.empty()) {
-                e->waiting.push_front(q.id);   // retry when something retires
-                break;
-            }
+        const uint8_t* occ_host = q.occ_pinned ? q.occ_pinned : q.occ.data();
+        int32_t bad = 0;
+        for (size_t j = 0; j < q.src.size(); j += 2)
+            bad += occ_host[(int64_t)q.src[j] * q.W + q.src[j + 1]] != 0;
+        if (bad) {
+            e->waiting.pop_front();
             q.state = OMAP_QUERY_FAILED;
-            q.error = g_last_error;
+            q.error = std::string(omap_status_string(OMAP_ERR_SOURCE_ON_OBSTACLE)) + ": " + std::to_string(bad) +
+                      " source(s) lie on obstacles";
+            query_release_occ(e, q);
             ++e->done_total;
             continue;
         }
-        st = e->solver.start(slot, q.L);
+        const size_t n_occ = (size_t)q.H * q.W;
+        void* occ_dev = e->mem.alloc(n_occ);
+        if (!occ_dev) break;
+        e->waiting.pop_front();
+        if (q.occ_pinned) {
+            HIP_TRY(hipMemcpyAsync(occ_dev, q.occ_pinned, n_occ, hipMemcpyHostToDevice, sv.stream));
+            HIP_TRY(e->occ_pool.release_after(q.occ_pinned, sv.stream));
+            q.occ_pinned = nullptr;
+        } else {
+            OK_TRY(sv.upload(occ_dev, q.occ.data(), n_occ));
+        }
+        int32_t slot = -1;
+        omap_status_t st = sv.add(q.H, q.W, static_cast<uint8_t*>(occ_dev), q.src.data(),
+                                  (int32_t)(q.src.size() / 2), q.tgt.empty() ? nullptr : q.tgt.data(),
+                                  (int32_t)(q.tgt.size() / 2), &slot, /*defer=*/true, /*check_sources=*/false);
+        e->mem.release(occ_dev);   // read by the packing kernel before any later reuse (stream order)
+        query_release_occ(e, q);
         if (st != OMAP_OK) {
             q.state = OMAP_QUERY_FAILED;
             q.error = g_last_error;
-            e->solver.remove(slot);
             ++e->done_total;
             continue;
         }
         q.slot = slot;
-        q.state = OMAP_QUERY_RUNNING;
-        q.occ.clear();
-        q.occ.shrink_to_fit();
-        e->resident.push_back(q.id);
+        started.push_back(slot);
+        Ls.push_back(q.L);
+        ids.push_back(q.id);
+    }
+    if (started.empty()) return OMAP_OK;
+    omap_status_t st = sv.start_many(started, Ls.data());
+    if (st != OMAP_OK) {
+        const std::string msg = g_last_error;
+        for (size_t i = 0; i < ids.size(); ++i) {
+            Query& q = e->queries[ids[i]];
+            sv.remove(started[i]);
+            q.slot = -1;
+            q.state = OMAP_QUERY_FAILED;
+            q.error = msg;
+            ++e->done_total;
+        }
+        g_last_error = msg;
+        return OMAP_OK;
+    }
+    for (int64_t id : ids) {
+        e->queries[id].state = OMAP_QUERY_RUNNING;
+        e->running.push_back(id);
     }
     return OMAP_OK;
 }
 
-static omap_status_t engine_retire(omap_engine_s* e) {
-    if (e->resident.empty()) return OMAP_OK;
-    // A resident maze is done when nothing of it is scheduled for the next
-    // round: no listed tile (active schedule) / no change in the last round
-    // (dense schedule).
+// Copies the per-slot counts that tell which mazes have nothing scheduled for
+// the next round (active: no listed tile; dense: no change in the last round).
+static omap_status_t engine_snapshot(omap_engine_s* e) {
     Solver& sv = e->solver;
+    Snapshot& sn = e->snap[e->snap_next];
+    if (!sn.counts) {
+        HIP_TRY(hipHostMalloc((void**)&sn.counts, sizeof(int32_t) * sv.cap_slots, hipHostMallocDefault));
+        HIP_TRY(hipEventCreateWithFlags(&sn.ev, hipEventDisableTiming));
+    }
     const int64_t r = sv.next_round;
     // (with one slot the kernels keep only the list count, which is that slot's)
     const int32_t* src = sv.opt.dense     ? sv.d_dchg + (size_t)((r + 2) % 3) * sv.cap_slots
                          : sv.cap_slots > 1 ? sv.d_sched + (size_t)(r % 3) * sv.cap_slots
                                             : sv.d_count + r % 3;
-    std::vector<int32_t> pending(sv.cap_slots);
-    HIP_TRY(hipMemcpyAsync(pending.data(), src, sizeof(int32_t) * pending.size(), hipMemcpyDeviceToHost,
-                           sv.stream));
-    HIP_TRY(hipStreamSynchronize(sv.stream));
+    HIP_TRY(hipMemcpyAsync(sn.counts, src, sizeof(int32_t) * sv.cap_slots, hipMemcpyDeviceToHost, sv.stream));
+    HIP_TRY(hipEventRecord(sn.ev, sv.stream));
+    sn.round = r;
+    sn.busy = true;
+    e->snap_next ^= 1;
+    return OMAP_OK;
+}
+
+// A completed snapshot: running mazes that had rounds before it and nothing
+// scheduled in it have converged (a converged maze is never visited again,
+// so the verdict cannot go stale while other mazes run on).
+static void engine_take_snapshot(omap_engine_s* e, Snapshot& sn) {
     std::vector<int64_t> keep;
-    std::vector<int32_t> done_slots;
-    std::vector<int64_t> done_ids;
-    for (int64_t id : e->resident) {
-        Query& q = e->queries[id];
-        if (pending[q.slot] == 0) {
-            done_slots.push_back(q.slot);
-            done_ids.push_back(id);
-        } else {
-            keep.push_back(id);
+    for (int64_t id : e->running) {
+        const Query& q = e->queries[id];
+        const Slot& s = e->solver.slots[q.slot];
+        if (s.first_round < sn.round && sn.counts[q.slot] == 0) e->converged.push_back(id);
+        else keep.push_back(id);
+    }
+    e->running.swap(keep);
+    sn.busy = false;
+}
+
+// Phase 1 of a retirement: finalize every converged maze and compute the
+// lengths and offsets of all their paths.
+static omap_status_t retire_begin(omap_engine_s* e) {
+    Solver& sv = e->solver;
+    Retirement& R = e->ret;
+    R.ids.swap(e->converged);
+    e->converged.clear();
+    R.slots.clear();
+    std::vector<int32_t> tslot, trc;
+    for (int64_t id : R.ids) {
+        const Query& q = e->queries[id];
+        R.slots.push_back(q.slot);
+        const int32_t nt = (int32_t)(q.tgt.size() / 2);
+        tslot.insert(tslot.end(), nt, q.slot);
+        trc.insert(trc.end(), q.tgt.begin(), q.tgt.end());
+    }
+    R.n = (int32_t)tslot.size();
+    if (!R.h_min) {
+        HIP_TRY(hipHostMalloc((void**)&R.h_min, sizeof(int32_t) * sv.cap_slots, hipHostMallocDefault));
+        HIP_TRY(hipHostMalloc((void**)&R.h_reached, sizeof(unsigned long long) * sv.cap_slots, hipHostMallocDefault));
+        HIP_TRY(hipEventCreateWithFlags(&R.ev, hipEventDisableTiming));
+    }
+    OK_TRY(sv.finalize_enqueue(R.slots, R.h_min, R.h_reached));
+    // device layout: tslot | trc | len | off
+    const size_t n = (size_t)R.n;
+    auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
+    char* base = nullptr;
+    OK_TRY(sv.scratch(up(4 * (n + 1)) + up(8 * (n + 1)) + up(4 * (n + 1)) + up(8 * (n + 1)), &base));
+    int32_t* d_tslot = reinterpret_cast<int32_t*>(base);
+    int32_t* d_trc = reinterpret_cast<int32_t*>(base + up(4 * (n + 1)));
+    int32_t* d_len = reinterpret_cast<int32_t*>(base + up(4 * (n + 1)) + up(8 * (n + 1)));
+    int64_t* d_off = reinterpret_cast<int64_t*>(base + 2 * up(4 * (n + 1)) + up(8 * (n + 1)));
+    if (n > 0) {
+        OK_TRY(sv.upload(d_tslot, tslot.data(), 4 * n));
+        OK_TRY(sv.upload(d_trc, trc.data(), 8 * n));
+        HIP_TRY(launch_path_lengths(sv.d_mazes, d_tslot, d_trc, R.n, sv.vparity(), d_len, sv.stream));
+    }
+    HIP_TRY(launch_scan_offsets(d_len, R.n, d_off, sv.stream));
+    OK_TRY(R.h_lo.reserve(lo_offsets_at(n) + 8 * (n + 1)));
+    if (n > 0) HIP_TRY(hipMemcpyAsync(R.h_lo.p, d_len, 4 * n, hipMemcpyDeviceToHost, sv.stream));
+    HIP_TRY(hipMemcpyAsync(R.h_lo.p + lo_offsets_at(n), d_off, 8 * (n + 1), hipMemcpyDeviceToHost, sv.stream));
+    HIP_TRY(hipEventRecord(R.ev, sv.stream));
+    R.phase = 1;
+    return OMAP_OK;
+}
+
+// Phase 2: with the path sizes known, walk every path and copy paths,
+// visit counters and kept activity maps to pinned host memory.
+static omap_status_t retire_paths(omap_engine_s* e) {
+    Solver& sv = e->solver;
+    Retirement& R = e->ret;
+    sv.finalize_apply(R.slots, R.h_min, R.h_reached);
+    const size_t n = (size_t)R.n;
+    const int64_t* h_off = reinterpret_cast<const int64_t*>(R.h_lo.p + lo_offsets_at(n));
+    R.total = h_off[n];
+    auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
+    char* base = nullptr;
+    OK_TRY(sv.scratch(up(4 * (n + 1)) + up(8 * (n + 1)) + up(4 * (n + 1)) + up(8 * (n + 1)), &base));
+    const int32_t* d_tslot = reinterpret_cast<const int32_t*>(base);
+    const int32_t* d_trc = reinterpret_cast<const int32_t*>(base + up(4 * (n + 1)));
+    const int32_t* d_len = reinterpret_cast<const int32_t*>(base + up(4 * (n + 1)) + up(8 * (n + 1)));
+    const int64_t* d_off = reinterpret_cast<const int64_t*>(base + 2 * up(4 * (n + 1)) + up(8 * (n + 1)));
+    if ((size_t)R.total > R.cells_cap) {
+        const size_t want = std::max<size_t>((size_t)R.total, R.cells_cap * 2);
+        HIP_TRY(hipStreamSynchronize(sv.stream));
+        if (R.d_cells) (void)hipFree(R.d_cells);
+        R.d_cells = nullptr;
+        R.cells_cap = 0;
+        HIP_TRY(hipMalloc(&R.d_cells, 4 * want));
+        R.cells_cap = want;
+    }
+    if (n > 0 && R.total > 0)
+        HIP_TRY(launch_walk(sv.d_mazes, d_tslot, d_trc, R.n, sv.vparity(), d_len, d_off, R.d_cells, sv.stream));
+    // host layout: last_round | visits | cell visits | cells | activity maps
+    const size_t b_lr = up(4 * (size_t)sv.cap_slots), b_v = up(8 * (size_t)sv.cap_slots * kSpread);
+    size_t act_bytes = 0;
+    R.act_off.assign(R.ids.size(), -1);
+    const size_t cells_at = b_lr + 2 * b_v, act_at = cells_at + up(4 * (size_t)R.total);
+    for (size_t i = 0; i < R.ids.size(); ++i) {
+        const Query& q = e->queries[R.ids[i]];
+        if (!(q.flags & OMAP_QUERY_KEEP_ACTIVITY)) continue;
+        R.act_off[i] = (int64_t)(act_at + act_bytes);
+        act_bytes += up(4 * (size_t)q.H * q.W);
+    }
+    OK_TRY(R.h_out.reserve(act_at + act_bytes));
+    HIP_TRY(hipMemcpyAsync(R.h_out.p, sv.d_last_round, 4 * (size_t)sv.cap_slots, hipMemcpyDeviceToHost, sv.stream));
+    HIP_TRY(hipMemcpyAsync(R.h_out.p + b_lr, sv.d_visits, 8 * (size_t)sv.cap_slots * kSpread, hipMemcpyDeviceToHost,
+                           sv.stream));
+    HIP_TRY(hipMemcpyAsync(R.h_out.p + b_lr + b_v, sv.d_cell_visits, 8 * (size_t)sv.cap_slots * kSpread,
+                           hipMemcpyDeviceToHost, sv.stream));
+    if (R.total > 0)
+        HIP_TRY(hipMemcpyAsync(R.h_out.p + cells_at, R.d_cells, 4 * (size_t)R.total, hipMemcpyDeviceToHost,
+                               sv.stream));
+    if (act_bytes > 0) {
+        if (act_bytes > R.act_cap) {
+            HIP_TRY(hipStreamSynchronize(sv.stream));
+            if (R.d_act) (void)hipFree(R.d_act);
+            R.d_act = nullptr;
+            R.act_cap = 0;
+            HIP_TRY(hipMalloc(&R.d_act, act_bytes));
+            R.act_cap = act_bytes;
+        }
+        for (size_t i = 0; i < R.ids.size(); ++i) {
+            if (R.act_off[i] < 0) continue;
+            const Query& q = e->queries[R.ids[i]];
+            const Slot& s = sv.slots[q.slot];
+            int32_t* d = reinterpret_cast<int32_t*>(reinterpret_cast<char*>(R.d_act) + (R.act_off[i] - act_at));
+            HIP_TRY(launch_activity(sv.d_mazes, q.slot, q.H, q.W, sv.vparity(), (int32_t)((int64_t)s.K - s.layers - 1),
+                                    d, q.W, sv.stream));
+            HIP_TRY(hipMemcpyAsync(R.h_out.p + R.act_off[i], d, 4 * (size_t)q.H * q.W, hipMemcpyDeviceToHost,
+                                   sv.stream));
         }
     }
-    if (done_slots.empty()) return OMAP_OK;
-    OK_TRY(e->solver.finalize(done_slots));
-    // paths of every retiring maze in one extraction (sizing pass, then the
-    // cells), split per query afterwards
-    int64_t n_tgt = 0;
-    for (int64_t id : done_ids) n_tgt += (int64_t)(e->queries[id].tgt.size() / 2);
-    std::vector<int32_t> len((size_t)n_tgt + 1);
-    std::vector<int64_t> off((size_t)n_tgt + 2);
-    std::vector<int32_t> cells;
-    int64_t needed = 0;
-    omap_status_t st = e->solver.extract(done_slots, len.data(), off.data(), nullptr, 0, &needed, true);
-    if (st == OMAP_ERR_BUFFER_TOO_SMALL) {
-        cells.assign((size_t)needed, 0);
-        st = e->solver.extract(done_slots, len.data(), off.data(), cells.data(), needed, &needed, true);
-    }
-    if (st != OMAP_OK) return st;
-    // visit counters of every slot in one read
-    OK_TRY(e->solver.read_counters());
+    HIP_TRY(hipEventRecord(R.ev, sv.stream));
+    R.phase = 2;
+    return OMAP_OK;
+}
+
+// Phase 3: results to the queries, slots and memory freed.
+static omap_status_t retire_finish(omap_engine_s* e) {
+    Solver& sv = e->solver;
+    Retirement& R = e->ret;
+    const size_t n = (size_t)R.n;
+    auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
+    const size_t b_lr = up(4 * (size_t)sv.cap_slots), b_v = up(8 * (size_t)sv.cap_slots * kSpread);
+    const int32_t* h_len = reinterpret_cast<const int32_t*>(R.h_lo.p);
+    const int64_t* h_off = reinterpret_cast<const int64_t*>(R.h_lo.p + lo_offsets_at(n));
+    const int32_t* h_cells = reinterpret_cast<const int32_t*>(R.h_out.p + b_lr + 2 * b_v);
+    const int32_t* h_lr = reinterpret_cast<const int32_t*>(R.h_out.p);
+    const int64_t* h_v = reinterpret_cast<const int64_t*>(R.h_out.p + b_lr);
+    const int64_t* h_cv = reinterpret_cast<const int64_t*>(R.h_out.p + b_lr + b_v);
+    sv.h_last_round.assign(h_lr, h_lr + sv.cap_slots);
+    sv.h_visits.assign(h_v, h_v + (size_t)sv.cap_slots * kSpread);
+    sv.h_cell_visits.assign(h_cv, h_cv + (size_t)sv.cap_slots * kSpread);
     int64_t t0 = 0;
-    for (size_t i = 0; i < done_ids.size(); ++i) {
-        Query& q = e->queries[done_ids[i]];
-        const int32_t k = done_slots[i];
+    for (size_t i = 0; i < R.ids.size(); ++i) {
+        Query& q = e->queries[R.ids[i]];
+        const int32_t k = R.slots[i];
         const int64_t nt = (int64_t)(q.tgt.size() / 2);
-        q.len.assign(len.begin() + t0, len.begin() + t0 + nt);
+        q.len.assign(h_len + t0, h_len + t0 + nt);
         q.off.resize((size_t)nt + 1);
-        for (int64_t j = 0; j <= nt; ++j) q.off[j] = off[t0 + j] - off[t0];
-        q.cells.assign(cells.begin() + off[t0], cells.begin() + off[t0 + nt]);
+        for (int64_t j = 0; j <= nt; ++j) q.off[j] = h_off[t0 + j] - h_off[t0];
+        q.cells.assign(h_cells + h_off[t0], h_cells + h_off[t0 + nt]);
+        if (R.act_off[i] >= 0) {
+            const int32_t* a = reinterpret_cast<const int32_t*>(R.h_out.p + R.act_off[i]);
+            q.activity.assign(a, a + (size_t)q.H * q.W);
+        }
         t0 += nt;
-        OK_TRY(e->solver.info(k, &q.info, /*counters_read=*/true));
-        OK_TRY(e->solver.remove(k));
+        OK_TRY(sv.info(k, &q.info, /*counters_read=*/true));
+        OK_TRY(sv.remove(k));
         q.slot = -1;
         q.state = OMAP_QUERY_DONE;
         ++e->done_total;
     }
-    e->resident.swap(keep);
+    R.ids.clear();
+    R.slots.clear();
+    R.phase = 0;
     return OMAP_OK;
 }
 
+static bool event_done(hipEvent_t ev, bool wait) {
+    if (wait) return hipEventSynchronize(ev) == hipSuccess;
+    const hipError_t e = hipEventQuery(ev);
+    if (e == hipSuccess) return true;
+    (void)hipGetLastError();
+    return false;
+}
+
+// Advances everything that completed on the device: snapshots, then the
+// retirement phases.  With wait, blocks until the current retirement phase
+// (if any) has completed.
+static omap_status_t engine_progress(omap_engine_s* e, bool wait) {
+    for (int k = 0; k < 2; ++k) {
+        Snapshot& sn = e->snap[e->snap_next ^ k];   // the older one first
+        if (sn.busy && event_done(sn.ev, false)) engine_take_snapshot(e, sn);
+    }
+    for (;;) {
+        Retirement& R = e->ret;
+        if (R.phase == 0) {
+            if (e->converged.empty()) return OMAP_OK;
+            OK_TRY(retire_begin(e));
+        }
+        if (!event_done(R.ev, wait)) return OMAP_OK;
+        if (R.phase == 1) OK_TRY(retire_paths(e));
+        else OK_TRY(retire_finish(e));
+    }
+}
 }  // namespace omap
 
 // ---------------------------------------------------------------------------
@@ -1785,17 +2179,64 @@ omap_status_t omap_engine_create(omap_engine_t* out, int64_t memory_budget_bytes
     Options o;
     OK_TRY(resolve_options(opts, &o, Use::kMany));
     o.async = 0;   // the engine advances mazes by whole rounds
+    o.per_round = 1;
     std::unique_ptr<omap_engine_s> e(new omap_engine_s());
     if (!e->mem.init((size_t)memory_budget_bytes))
         return fail(OMAP_ERR_OUT_OF_MEMORY, "engine budget of %lld bytes", (long long)memory_budget_bytes);
+    // pinned copies of queued occupancy grids: a quarter of the budget, 16 MiB .. 1 GiB
+    const int64_t pool = std::min<int64_t>(std::max<int64_t>(memory_budget_bytes / 4, 16 << 20), int64_t(1) << 30);
+    if (!e->occ_pool.init((size_t)pool)) return fail(OMAP_ERR_OUT_OF_MEMORY, "pinned staging of %lld bytes", (long long)pool);
     e->budget = memory_budget_bytes;
     e->max_slots = max_slots;
     // tile ids: enough for the whole budget filled with the smallest mazes
     const int64_t per_tile = (int64_t)o.TH * o.TW * 8;
     int64_t cap_tiles = memory_budget_bytes / per_tile + 4 * (int64_t)max_slots + 64;
     if (cap_tiles > (int64_t(1) << 28)) cap_tiles = int64_t(1) << 28;
-    OK_TRY(e->solver.init(static_cast<hipStream_t>(stream), o, &e->mem, max_slots, (int32_t)cap_tiles));
+    OK_TRY(e->solver.init(static_cast<hipStream_t>(stream), o, &e->mem, max_slots, (int32_t)cap_tiles,
+                          size_t(16) << 20));
     *out = e.release();
+    return OMAP_OK;
+    API_GUARD_END
+}
+
+omap_status_t omap_engine_submit_ex(omap_engine_t engine, int32_t height, int32_t width,
+                                    const uint8_t* occupancy_host, const int32_t* sources_host,
+                                    int32_t n_sources, const int32_t* targets_host, int32_t n_targets,
+                                    int64_t max_layers, uint32_t flags, int64_t* query_id) {
+    API_GUARD_BEGIN
+    if (!engine || !query_id) return fail(OMAP_ERR_INVALID_ARG, "engine/query_id is NULL");
+    if (flags & ~uint32_t(OMAP_QUERY_KEEP_ACTIVITY)) return fail(OMAP_ERR_INVALID_ARG, "unknown flags 0x%x", flags);
+    OK_TRY(validate_problem(height, width, occupancy_host, sources_host, n_sources, targets_host, n_targets));
+    if (max_layers < -1) return fail(OMAP_ERR_INVALID_ARG, "max_layers must be >= 0 or OMAP_AUTO_LAYERS");
+    if (max_layers >= 0 && max_layers + 1 > 0x7fffffffLL) return fail(OMAP_ERR_TOO_LARGE, "L + 1 >= 2^31");
+    Query q;
+    q.id = engine->next_id;
+    q.H = height;
+    q.W = width;
+    q.src.assign(sources_host, sources_host + 2 * n_sources);
+    if (n_targets > 0) q.tgt.assign(targets_host, targets_host + 2 * n_targets);
+    q.L = max_layers;
+    q.flags = flags;
+    q.bytes = query_bytes(q, engine->solver.opt);
+    if (q.bytes > (int64_t)engine->mem.size())
+        return fail(OMAP_ERR_OUT_OF_MEMORY, "query needs %lld bytes, budget is %lld", (long long)q.bytes,
+                    (long long)engine->mem.size());
+    const Geometry g = make_geometry(height, width, engine->solver.opt);
+    if ((int64_t)g.tiles_x * g.tiles_y > engine->solver.cap_tiles)
+        return fail(OMAP_ERR_OUT_OF_MEMORY, "query has more tiles than the engine's tile table");
+    const size_t n_occ = (size_t)height * width;
+    engine->occ_pool.reap(false);
+    void* pinned = engine->occ_pool.alloc(n_occ);
+    if (pinned) {
+        std::memcpy(pinned, occupancy_host, n_occ);
+        q.occ_pinned = static_cast<uint8_t*>(pinned);
+    } else {
+        q.occ.assign(occupancy_host, occupancy_host + n_occ);
+    }
+    ++engine->next_id;
+    *query_id = q.id;
+    engine->waiting.push_back(q.id);
+    engine->queries.emplace(q.id, std::move(q));
     return OMAP_OK;
     API_GUARD_END
 }
@@ -1804,43 +2245,43 @@ omap_status_t omap_engine_submit(omap_engine_t engine, int32_t height, int32_t w
                                  const uint8_t* occupancy_host, const int32_t* sources_host,
                                  int32_t n_sources, const int32_t* targets_host, int32_t n_targets,
                                  int64_t max_layers, int64_t* query_id) {
-    API_GUARD_BEGIN
-    if (!engine || !query_id) return fail(OMAP_ERR_INVALID_ARG, "engine/query_id is NULL");
-    OK_TRY(validate_problem(height, width, occupancy_host, sources_host, n_sources, targets_host, n_targets));
-    if (max_layers < -1) return fail(OMAP_ERR_INVALID_ARG, "max_layers must be >= 0 or OMAP_AUTO_LAYERS");
-    if (max_layers >= 0 && max_layers + 1 > 0x7fffffffLL) return fail(OMAP_ERR_TOO_LARGE, "L + 1 >= 2^31");
-    Query q;
-    q.id = engine->next_id++;
-    q.H = height;
-    q.W = width;
-    q.occ.assign(occupancy_host, occupancy_host + (size_t)height * width);
-    q.src.assign(sources_host, sources_host + 2 * n_sources);
-    if (n_targets > 0) q.tgt.assign(targets_host, targets_host + 2 * n_targets);
-    q.L = max_layers;
-    q.bytes = query_bytes(q, engine->solver.opt);
-    if (q.bytes > (int64_t)engine->mem.size())
-        return fail(OMAP_ERR_OUT_OF_MEMORY, "query needs %lld bytes, budget is %lld", (long long)q.bytes,
-                    (long long)engine->mem.size());
-    const Geometry g = make_geometry(height, width, engine->solver.opt);
-    if ((int64_t)g.tiles_x * g.tiles_y > engine->solver.cap_tiles)
-        return fail(OMAP_ERR_OUT_OF_MEMORY, "query has more tiles than the engine's tile table");
-    *query_id = q.id;
-    engine->waiting.push_back(q.id);
-    engine->queries.emplace(q.id, std::move(q));
-    return OMAP_OK;
-    API_GUARD_END
+    return omap_engine_submit_ex(engine, height, width, occupancy_host, sources_host, n_sources, targets_host,
+                                 n_targets, max_layers, 0, query_id);
 }
 
 omap_status_t omap_engine_step(omap_engine_t engine, int32_t rounds, int32_t* n_resident,
                                int64_t* n_done_total) {
     API_GUARD_BEGIN
     if (!engine || rounds < 0) return fail(OMAP_ERR_INVALID_ARG, "engine is NULL or rounds < 0");
-    OK_TRY(engine_admit(engine));
-    if (!engine->resident.empty()) OK_TRY(engine->solver.run_rounds(rounds));
-    OK_TRY(engine_retire(engine));
-    OK_TRY(engine_admit(engine));
-    if (n_resident) *n_resident = (int32_t)engine->resident.size();
-    if (n_done_total) *n_done_total = engine->done_total;
+    omap_engine_s* e = engine;
+    OK_TRY(engine_progress(e, false));
+    OK_TRY(engine_admit(e));
+    if (!e->running.empty() && rounds > 0) {
+        // at most two steps of rounds ahead of the device: wait for the older
+        // snapshot before enqueueing more
+        Snapshot& old = e->snap[e->snap_next];
+        if (old.busy) {
+            HIP_TRY(hipEventSynchronize(old.ev));
+            engine_take_snapshot(e, old);
+        }
+        OK_TRY(e->solver.run_rounds(rounds));
+        OK_TRY(engine_snapshot(e));
+        OK_TRY(engine_progress(e, false));
+    } else {
+        // nothing to advance: wait for what is in flight so that a caller's
+        // loop of steps makes progress
+        for (int k = 0; k < 2; ++k) {
+            Snapshot& sn = e->snap[e->snap_next ^ k];
+            if (sn.busy) {
+                HIP_TRY(hipEventSynchronize(sn.ev));
+                engine_take_snapshot(e, sn);
+            }
+        }
+        OK_TRY(engine_progress(e, true));
+        OK_TRY(engine_admit(e));
+    }
+    if (n_resident) *n_resident = e->resident();
+    if (n_done_total) *n_done_total = e->done_total;
     return OMAP_OK;
     API_GUARD_END
 }
@@ -1851,6 +2292,25 @@ omap_status_t omap_engine_poll(omap_engine_t engine, int64_t query_id, int32_t* 
     auto it = engine->queries.find(query_id);
     if (it == engine->queries.end()) return fail(OMAP_ERR_NOT_FOUND, "query %lld", (long long)query_id);
     *state = it->second.state;
+    return OMAP_OK;
+    API_GUARD_END
+}
+
+omap_status_t omap_engine_fetch_activity(omap_engine_t engine, int64_t query_id, int32_t* dst_host,
+                                         int64_t dst_pitch_elems) {
+    API_GUARD_BEGIN
+    if (!engine || !dst_host) return fail(OMAP_ERR_INVALID_ARG, "engine/destination is NULL");
+    auto it = engine->queries.find(query_id);
+    if (it == engine->queries.end()) return fail(OMAP_ERR_NOT_FOUND, "query %lld", (long long)query_id);
+    const Query& q = it->second;
+    if (q.state != OMAP_QUERY_DONE) return fail(OMAP_ERR_BUSY, "query %lld not finished", (long long)query_id);
+    if (!(q.flags & OMAP_QUERY_KEEP_ACTIVITY))
+        return fail(OMAP_ERR_INVALID_ARG, "query %lld was not submitted with OMAP_QUERY_KEEP_ACTIVITY",
+                    (long long)query_id);
+    if (dst_pitch_elems < q.W) return fail(OMAP_ERR_INVALID_ARG, "pitch %lld < width %d", (long long)dst_pitch_elems, q.W);
+    for (int32_t r = 0; r < q.H; ++r)
+        std::memcpy(dst_host + (int64_t)r * dst_pitch_elems, q.activity.data() + (int64_t)r * q.W,
+                    sizeof(int32_t) * q.W);
     return OMAP_OK;
     API_GUARD_END
 }
@@ -1889,6 +2349,8 @@ omap_status_t omap_engine_destroy(omap_engine_t engine) {
     API_GUARD_BEGIN
     if (!engine) return OMAP_OK;
     (void)hipStreamSynchronize(engine->solver.stream);
+    for (auto& kv : engine->queries)
+        if (kv.second.occ_pinned) engine->occ_pool.release_now(kv.second.occ_pinned);
     engine->solver.destroy();
     delete engine;
     return OMAP_OK;

@@ -92,27 +92,36 @@ def test_engine_results_alone_equal_mixed():
     alone = {}
     for i, m in enumerate(ms):
         act, ln, off, cells, info = run_plan(m, layers[i])
-        alone[i] = (ln, off, cells, info)
+        alone[i] = (ln, off, cells, info, act)
     with omap.Engine(256 << 20, max_slots=7, temporal_depth=8, tile_rows=32) as eng:
         ids = {}
         pending = list(range(len(ms)))
-        done = {}
+        done, acts = {}, {}
         step = 0
         while len(done) < len(ms):
             # staggered arrivals: a few new queries every step while others run
             for _ in range(3):
                 if pending:
                     i = pending.pop(0)
-                    ids[eng.submit(ms[i].occ, ms[i].sources, ms[i].targets, layers[i])] = i
+                    ids[eng.submit(ms[i].occ, ms[i].sources, ms[i].targets, layers[i],
+                                   keep_activity=i % 2 == 0)] = i
             eng.step(rounds=1 + step % 3)
             step += 1
             for q, i in list(ids.items()):
                 if eng.poll(q) == omap.QUERY_DONE:
+                    if i % 2 == 0:
+                        acts[i] = eng.activity(q)
+                    else:
+                        with pytest.raises(omap.OmapError) as e:
+                            eng.activity(q)
+                        assert e.value.name == "OMAP_ERR_INVALID_ARG"
                     done[i] = eng.fetch(q)
                     del ids[q]
             assert step < 100000
     for i in range(len(ms)):
-        ln, off, cells, info = alone[i]
+        ln, off, cells, info, act = alone[i]
+        if i % 2 == 0:
+            assert np.array_equal(acts[i], act), i
         r = done[i]
         assert np.array_equal(r.lengths, ln), i
         assert np.array_equal(r.offsets, off), i

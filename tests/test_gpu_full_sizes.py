@@ -47,9 +47,8 @@ def test_config4_all_512_batched():
         for i, m in enumerate(ms):
             d, ecc = oracle.bfs(m.occ, m.sources)
             assert infos[i]["layers"] == ecc, i
-            if i % 16 == 0:   # full activity maps for every 16th maze
-                act = b.activity(i).cpu().numpy()
-                assert np.array_equal(act, np.where(d >= 0, ecc + 1 - d, 0)), i
+            act = b.activity(i).cpu().numpy()   # every maze's full activity map
+            assert np.array_equal(act, np.where(d >= 0, ecc + 1 - d, 0)), i
             A = oracle.activity_from_bfs(d, ecc)
             rl, ro, rc = oracle.walk(A, m.sources, m.targets)
             n = len(m.targets)
@@ -60,20 +59,23 @@ def test_config4_all_512_batched():
 
 
 def test_serving_queries_sample():
+    """Served queries (the serving workload's first ten): every activity map
+    and every path against the oracle."""
     import paper_2004_00540_amd as omap
     import torch
-    qs = [workloads.serve_query(i) for i in range(6)]
+    qs = [workloads.serve_query(i) for i in range(10)]
     free, _ = torch.cuda.mem_get_info()
-    budget = int(min(8 << 30, free // 2))   # the six queries need about 4 GiB at once
+    budget = int(min(8 << 30, free // 2))
     print(f"free device memory {free / 2**30:.1f} GiB, engine budget {budget / 2**30:.1f} GiB", flush=True)
     with omap.Engine(budget, max_slots=16) as eng:
-        ids = {eng.submit(q.occ, q.sources, q.targets): k for k, q in enumerate(qs)}
-        res = {}
+        ids = {eng.submit(q.occ, q.sources, q.targets, keep_activity=True): k for k, q in enumerate(qs)}
+        res, act = {}, {}
         n = 0
         while len(res) < len(qs):
             eng.step(rounds=8)
             for qid, k in list(ids.items()):
                 if eng.poll(qid) == omap.QUERY_DONE:
+                    act[k] = eng.activity(qid)
                     res[k] = eng.fetch(qid)
                     del ids[qid]
             n += 1
@@ -82,8 +84,10 @@ def test_serving_queries_sample():
         d, ecc = oracle.bfs(q.occ, q.sources)
         A = oracle.activity_from_bfs(d, ecc)
         rl, ro, rc = oracle.walk(A, q.sources, q.targets)
-        assert res[k].info["layers"] == ecc
-        assert np.array_equal(res[k].lengths, rl) and np.array_equal(res[k].cells, rc), q.name
+        assert res[k].info["layers"] == ecc, q.name
+        assert np.array_equal(act[k], A), q.name
+        assert np.array_equal(res[k].lengths, rl) and np.array_equal(res[k].offsets, ro), q.name
+        assert np.array_equal(res[k].cells, rc), q.name
 
 
 def test_maximum_size_empty_map():
