@@ -216,6 +216,22 @@ omap_status_t omap_extract_paths_ex(omap_plan_t plan, const omap_walk_options *w
                                     int64_t cells_capacity, int64_t *cells_needed_host,
                                     int32_t *source_index_dev);
 
+/* omap_extract_paths for callers that cannot allocate memory: code under HIP
+ * graph capture, serving loops and harnesses that forbid allocation.  Same
+ * arguments, outputs, errors and synchrony as omap_extract_paths, but the
+ * call allocates nothing: the per-target staging (slot ids and target
+ * coordinates, 12 bytes per target) lives in a fixed array of
+ * 3 * OMAP_NOALLOC_MAX_TARGETS int32 (3 MiB) that the library holds on each
+ * device it runs on until the process ends; lengths and offsets go straight
+ * to len_dev / offsets_dev.  More than OMAP_NOALLOC_MAX_TARGETS targets:
+ * OMAP_ERR_TOO_LARGE.  Every call on one device shares that array and leaves
+ * its contents behind: calls that overlap on one device (from several host
+ * threads or streams) race, so the caller must serialise them. */
+#define OMAP_NOALLOC_MAX_TARGETS (1 << 18)
+omap_status_t omap_extract_paths_noalloc(omap_plan_t plan, int32_t *len_dev, int64_t *offsets_dev,
+                                         int32_t *cells_dev, int64_t cells_capacity,
+                                         int64_t *cells_needed_host);
+
 /* Release the plan and its device buffers.  NULL is a no-op. */
 omap_status_t omap_plan_destroy(omap_plan_t plan);
 

@@ -98,6 +98,7 @@ def lib() -> ctypes.CDLL:
         "omap_get_activity": [P, P, i64],
         "omap_extract_paths": [P, P, P, P, i64, P],
         "omap_extract_paths_ex": [P, P, P, P, P, i64, P, P],
+        "omap_extract_paths_noalloc": [P, P, P, P, i64, P],
         "omap_batch_extract_paths_ex": [P, P, P, P, P, i64, P, P],
         "omap_plan_destroy": [P],
         "omap_batch_create": [PP, P, i32, P, P],

@@ -17,6 +17,7 @@
 #include <deque>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <unordered_map>
@@ -1458,6 +1459,7 @@ struct omap_plan_s {
     omap::DirectMemory mem;
     omap::Solver solver;
     int32_t slot = -1;
+    int device = 0;          // device current at create
     bool propagated = false;
 };
 
@@ -1959,6 +1961,7 @@ omap_status_t omap_plan_create(omap_plan_t* out, int32_t height, int32_t width,
     Options o;
     OK_TRY(resolve_options(opts, &o));
     std::unique_ptr<omap_plan_s> p(new omap_plan_s());
+    HIP_TRY(hipGetDevice(&p->device));
     const Geometry g = make_geometry(height, width, o);
     OK_TRY(p->solver.init(static_cast<hipStream_t>(stream), o, &p->mem, 1, g.tiles_x * g.tiles_y));
     OK_TRY(p->solver.add(height, width, occupancy_dev, sources_host, n_sources, targets_host, n_targets, &p->slot));
@@ -2042,6 +2045,97 @@ omap_status_t omap_extract_paths_ex(omap_plan_t plan, const omap_walk_options* w
     std::vector<int32_t> one{plan->slot};
     return plan->solver.extract(one, len_dev, offsets_dev, cells_dev, cells_capacity, cells_needed_host, false,
                                 mode, seed, source_index_dev);
+    API_GUARD_END
+}
+
+// ---- allocation-free path extraction ----------------------------------------
+
+// Per-target staging of omap_extract_paths_noalloc: slot ids, then (row, col)
+// pairs.  Each device holds its own copy for the life of the process; host
+// code uses only the device address obtained for it below.
+static __device__ __align__(256) int32_t scratch[3 * OMAP_NOALLOC_MAX_TARGETS];
+
+static std::mutex g_scratch_mu;
+static int32_t* g_scratch_ptr[1024];   // per device id, once looked up
+
+// Device address of `scratch` on the current device (looked up once per
+// device, with that device current).
+static omap_status_t noalloc_scratch(int32_t** out) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 1024) return fail(OMAP_ERR_HIP, "device id %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(OMAP_ERR_HIP, "no device address for the extraction staging");
+        g_scratch_ptr[dev] = static_cast<int32_t*>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return OMAP_OK;
+}
+
+static omap_status_t extract_noalloc(omap_plan_t plan, int32_t* len_dev, int64_t* offsets_dev, int32_t* cells_dev,
+                                     int64_t cells_capacity, int64_t* cells_needed_host) {
+    Solver& sv = plan->solver;
+    const Slot& s = sv.slots[plan->slot];
+    const int32_t n = (int32_t)(s.tgt.size() / 2);
+    if (n > OMAP_NOALLOC_MAX_TARGETS)
+        return fail(OMAP_ERR_TOO_LARGE, "%d targets, the allocation-free extraction takes at most %d", n,
+                    OMAP_NOALLOC_MAX_TARGETS);
+    int32_t* d_scratch = nullptr;
+    OK_TRY(noalloc_scratch(&d_scratch));
+    int32_t* d_tslot = d_scratch;
+    int32_t* d_trc = d_scratch + OMAP_NOALLOC_MAX_TARGETS;
+    void* staged = nullptr;   // targets copied through the plan's pinned pool when they fit
+    if (n > 0) {
+        HIP_TRY(launch_fill(d_tslot, n, plan->slot, sv.stream));
+        const size_t b = sizeof(int32_t) * 2 * (size_t)n;
+        staged = sv.pin.alloc(b);
+        if (staged) std::memcpy(staged, s.tgt.data(), b);
+        const hipError_t e = hipMemcpyAsync(d_trc, staged ? staged : s.tgt.data(), b, hipMemcpyHostToDevice, sv.stream);
+        if (e != hipSuccess) {
+            (void)hipStreamSynchronize(sv.stream);
+            if (staged) sv.pin.release_now(staged);
+            HIP_TRY(e);
+        }
+        HIP_TRY(launch_path_lengths(sv.d_mazes, d_tslot, d_trc, n, sv.vparity(), len_dev, sv.stream));
+    }
+    HIP_TRY(launch_scan_offsets(len_dev, n, offsets_dev, sv.stream));
+    HIP_TRY(hipMemcpyAsync(sv.h_pinned, offsets_dev + n, sizeof(int64_t), hipMemcpyDeviceToHost, sv.stream));
+    const hipError_t sync = hipStreamSynchronize(sv.stream);   // the staging copy above has completed too
+    if (staged) sv.pin.release_now(staged);
+    HIP_TRY(sync);
+    int64_t total = 0;
+    std::memcpy(&total, sv.h_pinned, sizeof total);
+    if (cells_needed_host) *cells_needed_host = total;
+    if (cells_capacity < total || (total > 0 && cells_dev == nullptr))
+        return fail(OMAP_ERR_BUFFER_TOO_SMALL, "paths need %lld cells, capacity %lld", (long long)total,
+                    (long long)cells_capacity);
+    if (n > 0 && total > 0)
+        HIP_TRY(launch_walk(sv.d_mazes, d_tslot, d_trc, n, sv.vparity(), len_dev, offsets_dev, cells_dev, sv.stream));
+    HIP_TRY(hipStreamSynchronize(sv.stream));
+    return OMAP_OK;
+}
+
+omap_status_t omap_extract_paths_noalloc(omap_plan_t plan, int32_t* len_dev, int64_t* offsets_dev,
+                                         int32_t* cells_dev, int64_t cells_capacity,
+                                         int64_t* cells_needed_host) {
+    API_GUARD_BEGIN
+    if (!plan) return fail(OMAP_ERR_INVALID_ARG, "plan is NULL");
+    if (!plan->propagated) return fail(OMAP_ERR_NOT_PROPAGATED, "call omap_propagate first");
+    const int32_t nt = (int32_t)(plan->solver.slots[plan->slot].tgt.size() / 2);
+    if (!offsets_dev || (nt > 0 && !len_dev)) return fail(OMAP_ERR_INVALID_ARG, "len/offsets pointer is NULL");
+    // the staging array is looked up (and used) on the plan's device
+    int cur = 0;
+    HIP_TRY(hipGetDevice(&cur));
+    if (cur != plan->device) HIP_TRY(hipSetDevice(plan->device));
+    const omap_status_t st = extract_noalloc(plan, len_dev, offsets_dev, cells_dev, cells_capacity, cells_needed_host);
+    if (cur != plan->device) {
+        const hipError_t e = hipSetDevice(cur);
+        if (st == OMAP_OK && e != hipSuccess) return fail(OMAP_ERR_HIP, "hipSetDevice: %s", hipGetErrorString(e));
+    }
+    return st;
     API_GUARD_END
 }
 
