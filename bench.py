@@ -6,13 +6,18 @@ extract the path of every target.  Inputs are resident in HBM before timing.
 
 Default workload: the 23170 x 23170 maze (Bernoulli(0.40) + 50,000 filled
 rectangles, 16 sources, 4096 targets on the largest component; seeded,
-synthetic).  Metric: Gcell-updates/s = cells x effective layers / step time,
-with effective layers S_J = L* + 1 (the layers the plain layer-by-layer method
-needs to reach and confirm the fixpoint; L* is the path's own run-time
-determined layer count, which the tests check against BFS).
+synthetic).  Metric: Gcell-updates/s = cell-updates the sweep kernels execute
+per step (interior cells of the visited tiles x layers per visit) / step time.
+The dense equivalent of the paper's layer-by-layer network, cells x S_J / step
+time with S_J = L* + 1 effective layers, is reported beside it under its own
+key (the active schedule reaches the same bits while executing a small part of
+that dense work).  The same line carries the batched form (512 mazes) and the
+serving form (Poisson arrivals, p50 / p99 latency) and the CPU oracle on the
+same inputs.
 
-Prints one JSON line.  --workload batch | serve run the batched / serving forms
-instead (see their docstrings).
+Prints one JSON line.  --workload batch | serve | paper run one form alone
+(see bench_forms.py); --no-forms leaves the batched and serving forms out of
+the default line.
 """
 from __future__ import annotations
 
@@ -57,37 +62,70 @@ def cpu_info():
     return model, cores
 
 
-def cpu_baseline(m, budget_s: float = 25.0):
-    """The CPU oracle (literal network + simple path walk) on a bounded sample of
-    the same maze: a full-width band of rows, a fixed number of layers chosen so
-    the run takes about `budget_s` seconds on all host cores."""
+def cpu_baseline(m, gpu_step_s: float, gpu_cell_updates: int, effective_layers: int, budget_s: float = 25.0):
+    """The CPU oracle on the same maze, two ways.
+
+    Work-matched (the reported value): the oracle computes the same outputs as
+    one GPU step -- the activity map (multi-source BFS and the closed form
+    max(0, L+1-d), which the oracle's pins tie to the paper's layers) and the
+    simple path of all targets -- over the whole maze, on one core (the oracle
+    is single-threaded there).  Its rate is expressed in the metric's unit as
+    the GPU step's executed cell-updates divided by the oracle's time.
+
+    The literal network: the oracle's layers on the whole grid for a bounded
+    number of layers on all host cores and on one core, extrapolated to the
+    S_J layers the plain layer-by-layer method needs."""
     import oracle
     model, cores = cpu_info()
     threads = max(1, min(cores, 16))
-    rows = min(m.H, 1024)
-    band = np.ascontiguousarray(m.occ[:rows])
-    free = np.argwhere(band == 0)
-    rng = np.random.default_rng(0)
-    src = free[rng.integers(0, len(free), 16)].astype(np.int32)
-    tgt = free[rng.integers(0, len(free), 256)].astype(np.int32)
-    oracle.layers(band, src, 4, threads=threads)          # warm the threads and pages
     t0 = time.perf_counter()
-    oracle.layers(band, src, 32, threads=threads)
-    t_probe = max(time.perf_counter() - t0, 1e-3) / 32
-    L = int(max(8, min(8192, budget_s / t_probe)))
+    d, ecc = oracle.bfs(m.occ, m.sources)
+    t_bfs = time.perf_counter() - t0
     t0 = time.perf_counter()
-    A, _ = oracle.layers(band, src, L, threads=threads)
-    t_layers = time.perf_counter() - t0
+    A = oracle.activity_from_bfs(d, ecc)
+    t_map = time.perf_counter() - t0
+    del d
     t0 = time.perf_counter()
-    ln, off, cells = oracle.walk(A, src, tgt)
+    oracle.walk(A, m.sources, m.targets)
     t_walk = time.perf_counter() - t0
-    rate = band.size * L / t_layers / 1e9
+    del A
+    t_full = t_bfs + t_map + t_walk
+    log(f"cpu oracle: bfs {t_bfs:.2f} s, map {t_map:.2f} s, walk {t_walk:.2f} s")
+    # literal layers on the whole grid, bounded (a one-layer run sizes each)
+    lit = {}
+    for n_thr, share in ((threads, 0.7), (1, 0.3)):
+        t0 = time.perf_counter()
+        oracle.layers(m.occ, m.sources, 1, threads=n_thr)
+        t1 = time.perf_counter() - t0
+        K = int(max(1, min(64, share * budget_s / max(t1, 1e-3))))
+        t0 = time.perf_counter()
+        oracle.layers(m.occ, m.sources, K, threads=n_thr)
+        tk = time.perf_counter() - t0
+        rate = m.H * m.W * K / tk
+        lit[n_thr] = (K, tk, rate)
+        log(f"cpu literal layers: {K} layers on {n_thr} thread(s) in {tk:.1f} s -> {rate / 1e9:.3f} G/s")
+    K, tk, rate = lit[threads]
+    K1, tk1, rate1 = lit[1]
+    dense = m.H * m.W * effective_layers
     return {
-        "value": round(rate, 4), "unit": "Gcell-updates/s", "cores": threads, "kind": "oracle",
-        "sample": f"literal oMAP layers on rows 0..{rows - 1} (all {m.W} columns) of the same maze, "
-                  f"{L} layers, 16 sources; {t_layers:.1f} s; walk of 256 targets {t_walk:.2f} s",
+        "value": round(gpu_cell_updates / t_full / 1e9, 4), "unit": "Gcell-updates/s", "cores": 1,
+        "kind": "oracle",
+        "sample": f"whole maze: oracle multi-source BFS ({t_bfs:.2f} s) + closed-form activity map ({t_map:.2f} s) "
+                  f"+ simple walk of all {len(m.targets)} targets ({t_walk:.2f} s) = {t_full:.2f} s on one core for "
+                  f"the outputs of one GPU step; value = the GPU step's {gpu_cell_updates} executed cell-updates / "
+                  f"that time",
+        "oracle_step_s": round(t_full, 3),
+        "gpu_step_speedup": round(t_full / gpu_step_s, 1),
         "cpu_model": model, "host_cores": cores,
-        "walk_paths_per_s": round(len(tgt) / max(t_walk, 1e-9), 1),
+        "literal_layers": {
+            "gcell_updates_per_s_all_cores": round(rate / 1e9, 4), "threads": threads, "layers_timed": K,
+            "seconds": round(tk, 2),
+            "gcell_updates_per_s_one_core": round(rate1 / 1e9, 4), "layers_timed_one_core": K1,
+            "seconds_one_core": round(tk1, 2),
+            "extrapolated_full_run_s_all_cores": round(dense / rate, 1),
+            "note": f"the paper's literal layers on the whole {m.H}x{m.W} grid, timed for the layers shown and "
+                    f"extrapolated to S_J = {effective_layers} layers (dense, no early exit)",
+        },
     }
 
 
@@ -202,14 +240,21 @@ def bench_plain(args):
     step_s = wall
     path_steps = int(lengths.clamp(min=0).sum().item())
     resolved = omap.resolve_options(**opts)
-    gcups = N * S_J / step_s / 1e9
+    executed = prof["cell_updates"]            # per propagation = per step
+    gcups = executed / step_s / 1e9
     alg_bytes = prof["cell_updates"] * BYTES_PER_CELL_UPDATE
     kern_s = prof["ms"] / 1e3
+    launches = max(prof["launches"], 1)
     achieved = alg_bytes / kern_s / 1e9 if kern_s > 0 else 0.0
     ops_per_cell = 4.5
     alu_tops = prof["cell_updates"] * ops_per_cell / kern_s / 1e12 if kern_s > 0 else 0.0
+    traffic = measured_traffic(m.name, resolved)
     out = {
         "metric": "Gcell-updates/s", "value": round(gcups, 3), "unit": "Gcell-updates/s",
+        "value_definition": "cell-updates executed by the sweep kernels per step / step time",
+        "dense_equivalent_gcell_updates_per_s": round(N * S_J / step_s / 1e9, 1),
+        "dense_equivalent_definition": "cells x S_J / step time, S_J = L* + 1: the paper's layer-by-layer "
+                                       "network reaches the same map with this many cell-updates",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(step_s * 1e3, 3), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "int32", "data": "synthetic",
@@ -228,14 +273,17 @@ def bench_plain(args):
                          "dense_cell_updates": N * S_J},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic(m.name, resolved),
-                     "algorithmic_bytes_per_launch": round(alg_bytes / max(prof["launches"], 1))},
+                     "traffic": traffic,
+                     "algorithmic_bytes_per_launch": round(alg_bytes / launches),
+                     "avg_launch_us": round(prof["ms"] * 1e3 / launches, 2),
+                     "measured_hbm_gbs": round(traffic / (kern_s / launches) / 1e9, 1) if traffic and kern_s > 0
+                     else None},
         "roofline_alu": {"bound": "alu", "achieved": round(alu_tops, 2), "peak": round(VALU_PEAK_TOPS, 1),
                          "unit": "Tops/s", "frac": round(alu_tops / VALU_PEAK_TOPS, 4),
                          "ops_per_cell_update": ops_per_cell},
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(m, args.cpu_budget)
+        out["cpu_baseline"] = cpu_baseline(m, step_s, executed, S_J, args.cpu_budget)
     return out
 
 
@@ -252,8 +300,10 @@ def main():
     ap.add_argument("--launch", type=int, default=0, help="0 per round, 1 persistent, 2 asynchronous")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=25.0)
-    ap.add_argument("--serve-pool", type=int, default=48)
-    ap.add_argument("--serve-requests", type=int, default=200)
+    ap.add_argument("--no-forms", action="store_true", help="leave the batched and serving forms out")
+    ap.add_argument("--serve-warmup", type=int, default=20)
+    ap.add_argument("--serve-requests", type=int, default=500)
+    ap.add_argument("--serve-plain", type=int, default=100, help="queries timed in the plain per-maze loop")
     ap.add_argument("--serve-budget-gb", type=float, default=64.0)
     ap.add_argument("--serve-slots", type=int, default=64)
     ap.add_argument("--serve-rounds", type=int, default=4)
@@ -266,6 +316,17 @@ def main():
         out = copy_probe(args)
     elif args.workload in ("c1", "c2", "c3"):
         out = bench_plain(args)
+        if args.workload == "c3" and not args.no_forms:
+            import torch
+            from bench_forms import bench_batch, bench_serve
+            torch.cuda.empty_cache()
+            b = bench_batch(args)
+            out["batch"] = {k: b[k] for k in ("value", "unit", "ms_per_step", "plain_loop_mazes_per_s",
+                                              "speedup_vs_plain_loop", "paths_per_s", "config")}
+            torch.cuda.empty_cache()
+            sv = bench_serve(args)
+            out["serve"] = {k: sv[k] for k in ("capacity_mazes_per_s", "open_loop_mazes_per_s", "latency_ms",
+                                               "plain_loop_mazes_per_s", "capacity_vs_plain_loop", "config")}
     elif args.workload == "batch":
         from bench_forms import bench_batch
         out = bench_batch(args)
