@@ -297,7 +297,7 @@ def main():
     ap.add_argument("--tile-rows", type=int, default=0)
     ap.add_argument("--schedule", type=int, default=0)
     ap.add_argument("--lane-columns", type=int, default=0)
-    ap.add_argument("--launch", type=int, default=0, help="0 per round, 1 persistent, 2 asynchronous")
+    ap.add_argument("--launch", type=int, default=0, help="0 one launch per round, 1 rounds replayed from HIP graphs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=25.0)
     ap.add_argument("--no-forms", action="store_true", help="leave the batched and serving forms out")

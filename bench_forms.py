@@ -55,9 +55,10 @@ def bench_batch(args):
         return out
 
     def plain():
+        # the plain loop runs single-maze plans with their own defaults
         res = []
         for i, m in enumerate(mazes):
-            with omap.Plan(occs[i], m.sources, m.targets, **opts) as p:
+            with omap.Plan(occs[i], m.sources, m.targets) as p:
                 p.propagate(sync=False)
                 res.append(p.paths())
         return res
@@ -127,8 +128,9 @@ def bench_serve(args):
     budget = int(min(args.serve_budget_gb * (1 << 30), 0.8 * free))
 
     def plain_one(q):
+        # the plain loop runs single-maze plans with their own defaults
         occ = torch.from_numpy(q.occ).to(dev)
-        with omap.Plan(occ, q.sources, q.targets, **opts) as p:
+        with omap.Plan(occ, q.sources, q.targets) as p:
             p.propagate(sync=False)
             ln, off, cells = p.paths()
             cells.cpu()

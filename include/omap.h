@@ -73,44 +73,34 @@ typedef enum omap_status {
 #define OMAP_AUTO_LAYERS (-1)
 
 /* Schedules of tile visits (see omap_options.schedule). */
-#define OMAP_SCHEDULE_ACTIVE 0   /* visit a tile only while it or a neighbour changed */
-#define OMAP_SCHEDULE_DENSE 1    /* visit every tile of a maze until the maze stops changing */
-#define OMAP_SCHEDULE_BITS 2     /* active schedule on a bit-packed reached set instead of      */
-                                 /* int32 activity: same results; temporal_depth 8 or 16,      */
-                                 /* one launch per round, lane_columns 0                       */
+#define OMAP_SCHEDULE_DEFAULT 0  /* plan: ACTIVE; batch and engine: BITS (the fastest measured for */
+                                 /* each; with lane_columns set, or a depth BITS lacks: ACTIVE)   */
+#define OMAP_SCHEDULE_ACTIVE 1   /* visit a tile only while it or a neighbour changed             */
+#define OMAP_SCHEDULE_DENSE 2    /* visit every tile of a maze until the maze stops changing      */
+#define OMAP_SCHEDULE_BITS 3     /* active schedule on a bit-packed reached set instead of int32  */
+                                 /* activity: same results; temporal_depth 8 or 16, lane_columns 0 */
+
+/* Round launches (see omap_options.round_launch). */
+#define OMAP_LAUNCH_PER_ROUND 0  /* one kernel launch per round, enqueued by the host             */
+#define OMAP_LAUNCH_GRAPH 1      /* groups of rounds captured once in a HIP graph and replayed     */
 
 /* Execution options.  Zero-initialised = tuned defaults.  No option changes a
  * result: activity maps and paths are identical bit for bit for every value. */
 typedef struct omap_options {
     int32_t temporal_depth;  /* layers applied per tile visit: 4, 8, 12, 16 (and 24, 32    */
-                             /* with lane_columns = 2); 0 = default (16; active with more  */
-                             /* than one column per lane, as in batches and engines: 12)   */
+                             /* with lane_columns = 2; bit-sliced: 8, 16); 0 = default     */
+                             /* (16; active with more than one column per lane: 12)        */
     int32_t tile_rows;       /* interior rows per tile, even, 2..4096, >= temporal_depth;  */
                              /* 0 = default (plan, active, 1 column per lane: depth;       */
-                             /* other active: max(16, depth); dense: 256)                  */
-    int32_t schedule;        /* OMAP_SCHEDULE_ACTIVE or OMAP_SCHEDULE_DENSE                 */
+                             /* other active and bit-sliced: max(16, depth); dense: 256)   */
+    int32_t schedule;        /* OMAP_SCHEDULE_*                                             */
     int32_t check_interval;  /* rounds between host reads of the convergence count;        */
                              /* 0 = adaptive                                                */
     int32_t lane_columns;    /* columns each lane owns (tile strip = 64 x this): 1, 2 or   */
                              /* 4 (1: temporal_depth 4..16); 0 = default (plan, active: 1; */
                              /* batch, engine: 2; dense: 4; the narrowest with the depth)  */
-    int32_t round_launch;    /* OMAP_LAUNCH_PER_ROUND (default): one launch per round;     */
-                             /* OMAP_LAUNCH_PERSISTENT: one cooperative launch runs rounds */
-                             /* until convergence, separated by a device-wide barrier      */
-                             /* (bit-identical results; slower on MI355X, where the        */
-                             /* barrier costs more than a kernel boundary);                */
-                             /* OMAP_LAUNCH_ASYNC: waves take tiles from a work queue and  */
-                             /* update them in place, with no rounds (active schedule      */
-                             /* only; bit-identical results).  The serving engine always   */
-                             /* runs rounds (OMAP_LAUNCH_ASYNC acts as PER_ROUND there)    */
-    int32_t async_budget_us; /* OMAP_LAUNCH_ASYNC: microseconds one launch may spend taking */
-                             /* new tiles before it pauses and the host relaunches it with  */
-                             /* the tiles still queued; 0 = default (50000), else >= 10     */
+    int32_t round_launch;    /* OMAP_LAUNCH_PER_ROUND (default) or OMAP_LAUNCH_GRAPH        */
 } omap_options;
-
-#define OMAP_LAUNCH_PER_ROUND 0
-#define OMAP_LAUNCH_PERSISTENT 1
-#define OMAP_LAUNCH_ASYNC 2
 
 /* The options a plan created with `options` (NULL = all defaults) would run
  * with: every zero field replaced by its default (batches and engines default
@@ -123,10 +113,8 @@ omap_status_t omap_resolve_options(const omap_options *options, omap_options *re
 typedef struct omap_propagate_info {
     int64_t layers;           /* L (fixed) or L* (run-time determined)               */
     int64_t sweeps_executed;  /* layers applied by the kernels (>= layers + 1 when   */
-                              /* converged: the last visit confirms the fixpoint);   */
-                              /* 0 with OMAP_LAUNCH_ASYNC, which has no rounds       */
+                              /* converged: the last visit confirms the fixpoint)    */
     int64_t rounds;           /* temporal blocks in which the maze had tiles visited */
-                              /* (0 with OMAP_LAUNCH_ASYNC)                          */
     int64_t tile_visits;      /* tile visits summed over rounds                       */
     int64_t reached_cells;    /* cells with activity > 0                              */
 } omap_propagate_info;

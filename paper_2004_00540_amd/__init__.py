@@ -25,9 +25,10 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("OMAP_LIBRARY") or os.path.join(_HERE, "libomap.so")
 
 AUTO = -1
-SCHEDULE_ACTIVE = 0
-SCHEDULE_DENSE = 1
-SCHEDULE_BITS = 2
+SCHEDULE_DEFAULT = 0
+SCHEDULE_ACTIVE = 1
+SCHEDULE_DENSE = 2
+SCHEDULE_BITS = 3
 QUERY_QUEUED, QUERY_RUNNING, QUERY_DONE, QUERY_FAILED = 0, 1, 2, 3
 QUERY_KEEP_ACTIVITY = 1
 
@@ -50,8 +51,7 @@ class OmapError(RuntimeError):
 class Options(ctypes.Structure):
     _fields_ = [("temporal_depth", ctypes.c_int32), ("tile_rows", ctypes.c_int32),
                 ("schedule", ctypes.c_int32), ("check_interval", ctypes.c_int32),
-                ("lane_columns", ctypes.c_int32), ("round_launch", ctypes.c_int32),
-                ("async_budget_us", ctypes.c_int32)]
+                ("lane_columns", ctypes.c_int32), ("round_launch", ctypes.c_int32)]
 
 
 class PropagateInfo(ctypes.Structure):
@@ -152,13 +152,12 @@ def _stream(stream=None) -> int:
     return int(stream.cuda_stream) if hasattr(stream, "cuda_stream") else int(stream)
 
 
-LAUNCH_PER_ROUND, LAUNCH_PERSISTENT, LAUNCH_ASYNC = 0, 1, 2
+LAUNCH_PER_ROUND, LAUNCH_GRAPH = 0, 1
 
 
-def _options(temporal_depth=0, tile_rows=0, schedule=SCHEDULE_ACTIVE, check_interval=0,
-             lane_columns=0, round_launch=LAUNCH_PER_ROUND, async_budget_us=0):
-    return Options(temporal_depth, tile_rows, schedule, check_interval, lane_columns, round_launch,
-                   async_budget_us)
+def _options(temporal_depth=0, tile_rows=0, schedule=SCHEDULE_DEFAULT, check_interval=0,
+             lane_columns=0, round_launch=LAUNCH_PER_ROUND):
+    return Options(temporal_depth, tile_rows, schedule, check_interval, lane_columns, round_launch)
 
 
 def resolve_options(**options) -> dict:

@@ -163,6 +163,7 @@ __device__ bool bits_tile(const MazeDev& md, int ty, int tx, int tile_rows, int 
 // visited any more.
 template <int T>
 __global__ __launch_bounds__(kBlockThreads) void k_bits(RoundArgs a) {
+    if (a.round_base) a.round_id += *a.round_base;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = lane_id();
     const int stride = a.wave_stride;

@@ -35,22 +35,6 @@ struct MazeDev {
     int32_t round0;         // bit-sliced schedule: index of the maze's first round
 };
 
-// Work queue of the asynchronous launch.  A tile id is in the ring at most
-// once at a time (only a tile going from idle to "needs a visit" is pushed),
-// so a ring of at least twice (tile ids + waves) entries never wraps onto an
-// entry that has not been taken.
-struct AsyncQueue {
-    unsigned long long* ring;     // entries: 0 = empty, else (slot << 32) | (tile id + 1)
-    uint32_t ring_mask;           // ring size - 1 (a power of two)
-    uint32_t* head;               // tickets handed to waiting waves
-    uint32_t* tail;               // entries pushed
-    int32_t* state;               // per tile id: bit 0 = needs a visit, bit 1 = being visited
-    int32_t* pending;             // tiles that need or are receiving a visit
-    int32_t* done;                // 1 once pending reached 0
-    int32_t* error;               // nonzero: a ring entry was still occupied (cannot happen by the sizing)
-    unsigned long long budget;    // wall-clock ticks a launch may take on new tiles (then it pauses)
-};
-
 // Arguments of round r of the tile schedule.  The tile lists and their dedup
 // flags alternate by r mod 2; the list counts, the per-maze scheduled counts
 // and the dense schedule's "changed" flags rotate over three buffers by r mod
@@ -79,32 +63,16 @@ struct RoundArgs {
     int64_t* maze_cell_visits;    // [slot][kSpread]: interior cells of visited tiles
     unsigned long long* total_cells;  // [kSpread], all slots: interior cells of visited tiles
     int32_t n_slots;
-    int32_t round_id;             // r (wraps; only differences are used)
+    int32_t round_id;             // r (wraps; only differences are used); in a graph replay
+                                  // the round's offset in the captured group
+    const int32_t* round_base;    // graph replays: device counter holding the group's first
+                                  // round, added to round_id by the kernels (else null)
     int32_t parity;               // activity buffer read in round r (r mod 2)
     int32_t tile_rows;            // interior rows per tile
     int32_t tile_cols;            // interior columns per tile (64*C - 2T)
     int32_t dense;                // 1 = dense schedule
     int32_t wave_stride;          // waves in the launch (set by the launch wrapper)
-    int32_t async;                // 1 = seeds go to the asynchronous work queue
-    AsyncQueue q;
     MazeDev md0;                  // copy of mazes[0] when n_slots == 1 (saves a dependent load)
-};
-
-// Arguments of a persistent launch running rounds r0, r0+1, ... : the
-// per-round pointers are derived on the device from these bases exactly as
-// the host derives them for a single-round launch.
-struct PersistentArgs {
-    RoundArgs base;               // constant fields; round_id = r0
-    int32_t* list[2];
-    int32_t* count;               // [3]
-    int32_t* flags[2];
-    int32_t* sched;               // [3][n_slots]
-    int32_t* dchg;                // [3][n_slots]
-    int32_t r0_mod6;              // r0 mod 6 (both mod-2 and mod-3 phases)
-    int32_t max_rounds;
-    unsigned int* bar_count;      // barrier state, zero between launches
-    unsigned int* bar_gen;
-    int32_t* rounds_done;         // rounds actually run
 };
 
 // Sweep variants (layers per visit T, columns per lane C); each is compiled in
@@ -116,10 +84,7 @@ struct PersistentArgs {
 #define X(t, c)                                                                                       \
     hipError_t launch_sweep_T##t##_C##c(const RoundArgs& a, int32_t grid, hipStream_t s, hipEvent_t e0, \
                                         hipEvent_t e1);                                               \
-    hipError_t launch_sweep_persistent_T##t##_C##c(const PersistentArgs& p, int32_t grid, hipStream_t s); \
-    hipError_t launch_sweep_async_T##t##_C##c(const RoundArgs& a, int32_t grid, hipStream_t s, hipEvent_t e0, \
-                                              hipEvent_t e1);                                         \
-    int sweep_blocks_per_cu_T##t##_C##c(int kind);
+    int sweep_blocks_per_cu_T##t##_C##c();
 OMAP_SWEEP_VARIANTS(X)
 #undef X
 
@@ -149,22 +114,12 @@ bool sweep_supported(int T, int C);
 // start and end (hipExtLaunchKernel), for profiling.
 hipError_t launch_sweep(int T, int C, const RoundArgs& a, int32_t grid, hipStream_t s,
                         hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
-// Cooperative launch of up to p.max_rounds rounds (grid must fit co-resident).
-hipError_t launch_sweep_persistent(int T, int C, const PersistentArgs& p, int32_t grid, hipStream_t s);
-int sweep_persistent_blocks_per_cu(int T, int C);
 // Clears slot's counters before its seeds (last round = r-1; dense: marks the
 // maze for a visit in the round about to run through a.dchg_prev).
-// Asynchronous launch: waves take tiles from a.q until no tile needs a visit
-// (*a.q.done = 1) or the time budget is spent (tiles still queued stay in the
-// ring; launch_queue_compact then moves them to the ring's start).
-hipError_t launch_sweep_async(int T, int C, const RoundArgs& a, int32_t grid, hipStream_t s,
-                              hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 bool bits_supported(int T);
 int bits_max_waves_per_cu(int T);
 hipError_t launch_bits(int T, const RoundArgs& a, int32_t grid, hipStream_t s, hipEvent_t e0 = nullptr,
                        hipEvent_t e1 = nullptr);
-hipError_t launch_queue_compact(const AsyncQueue& q, unsigned long long* tmp, uint32_t* tmp_count, hipStream_t s);
-int sweep_async_waves_per_cu(int T, int C);
 hipError_t launch_slot_reset(const RoundArgs& a, const int32_t* slots, int32_t n, hipStream_t s);
 
 // Packing of several mazes' occupancy in one launch.
@@ -203,6 +158,8 @@ hipError_t launch_activity(const MazeDev* mazes, int32_t slot, int32_t H, int32_
                            int32_t parity, int32_t offset, int32_t* dst, int64_t dpitch,
                            hipStream_t s);
 hipError_t launch_selftest(int32_t* out, hipStream_t s);
+// *counter += add (one thread): advances the round counter of graph replays.
+hipError_t launch_round_advance(int32_t* counter, int32_t add, hipStream_t s);
 // Zeroes both activity buffers (and bit planes) over the interiors of the
 // touched tiles among tile ids [tile_begin, +n_tiles) of the selected mazes
 // (sel == nullptr: all) and clears their touched flags.

@@ -86,12 +86,7 @@ __global__ void k_seed(RoundArgs a, int32_t slot0, const int32_t* __restrict__ s
         for (int dx = -1; dx <= 1; ++dx) {
             const int ny = ty + dy, nx = tx + dx;
             if (ny < 0 || ny >= md.tiles_y || nx < 0 || nx >= md.tiles_x) continue;
-            if (a.async) {
-                const int g = md.tile_base + ny * md.tiles_x + nx;
-                if (atomicOr(&a.q.state[g], 1) == 0 && atomicAdd(a.q.pending, 1) >= 0) queue_push(a.q, g, slot);
-            } else {
-                schedule_tile(a, md, slot, ny, nx);
-            }
+            schedule_tile(a, md, slot, ny, nx);
         }
 }
 
@@ -108,37 +103,6 @@ __global__ void k_slot_reset(RoundArgs a, const int32_t* __restrict__ slots, int
         a.maze_cell_visits[slot * kSpread + k] = 0;
     }
     if (a.dense) a.dchg_prev[slot] = 1;
-}
-
-// After a paused launch: moves the entries still in the ring (in ring order)
-// to a temporary array; the host copies them back to the ring's start and
-// sets head = 0, tail = count.  One block.
-__global__ __launch_bounds__(1024) void k_queue_gather(AsyncQueue q, unsigned long long* __restrict__ tmp,
-                                                       uint32_t* __restrict__ count) {
-    __shared__ uint32_t wsum[16];
-    __shared__ uint32_t base_s;
-    if (threadIdx.x == 0) base_s = 0;
-    __syncthreads();
-    const uint32_t n = q.ring_mask + 1;
-    for (uint32_t i0 = 0; i0 < n; i0 += 1024) {
-        const uint32_t i = i0 + threadIdx.x;
-        const unsigned long long e = i < n ? q.ring[i] : 0ull;
-        const uint64_t m = __ballot(e != 0);
-        const int w = threadIdx.x >> 6;
-        if (lane_id() == 0) wsum[w] = (uint32_t)__popcll(m);
-        __syncthreads();
-        uint32_t before = base_s;
-        for (int k = 0; k < w; ++k) before += wsum[k];
-        if (e != 0) {
-            tmp[before + (uint32_t)__popcll(m & ((1ull << lane_id()) - 1))] = e;
-            q.ring[i] = 0ull;
-        }
-        __syncthreads();
-        if (threadIdx.x == 0)
-            for (int k = 0; k < 16; ++k) base_s += wsum[k];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) *count = base_s;
 }
 
 // One wave per tile id in [tile_begin, tile_begin + n_tiles) whose maze is
@@ -697,40 +661,16 @@ hipError_t launch_sweep(int T, int C, const RoundArgs& a, int32_t grid, hipStrea
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_sweep_persistent(int T, int C, const PersistentArgs& p, int32_t grid, hipStream_t s) {
+static int sweep_blocks_per_cu(int T, int C) {
 #define X(t, c) \
-    if (T == t && C == c) return launch_sweep_persistent_T##t##_C##c(p, grid, s);
-    OMAP_SWEEP_VARIANTS(X)
-#undef X
-    return hipErrorInvalidValue;
-}
-
-hipError_t launch_sweep_async(int T, int C, const RoundArgs& a, int32_t grid, hipStream_t s, hipEvent_t e0,
-                              hipEvent_t e1) {
-#define X(t, c) \
-    if (T == t && C == c) return launch_sweep_async_T##t##_C##c(a, grid, s, e0, e1);
-    OMAP_SWEEP_VARIANTS(X)
-#undef X
-    return hipErrorInvalidValue;
-}
-
-static int sweep_blocks_per_cu(int T, int C, int kind) {
-#define X(t, c) \
-    if (T == t && C == c) return sweep_blocks_per_cu_T##t##_C##c(kind);
+    if (T == t && C == c) return sweep_blocks_per_cu_T##t##_C##c();
     OMAP_SWEEP_VARIANTS(X)
 #undef X
     return 0;
 }
 
-int sweep_persistent_blocks_per_cu(int T, int C) { return sweep_blocks_per_cu(T, C, 1); }
-
 int sweep_max_waves_per_cu(int T, int C) {
-    const int b = sweep_blocks_per_cu(T, C, 0);
-    return (b > 1 ? b : 1) * kWavesPerBlock;
-}
-
-int sweep_async_waves_per_cu(int T, int C) {
-    const int b = sweep_blocks_per_cu(T, C, 2);
+    const int b = sweep_blocks_per_cu(T, C);
     return (b > 1 ? b : 1) * kWavesPerBlock;
 }
 
@@ -846,14 +786,17 @@ hipError_t launch_clear_touched(const RoundArgs& a, int32_t tile_begin, int32_t 
     return hipGetLastError();
 }
 
+__global__ void k_round_advance(int32_t* counter, int32_t add) { *counter += add; }
+
+hipError_t launch_round_advance(int32_t* counter, int32_t add, hipStream_t s) {
+    hipLaunchKernelGGL(k_round_advance, dim3(1), dim3(1), 0, s, counter, add);
+    return hipGetLastError();
+}
+
 hipError_t launch_selftest(int32_t* out, hipStream_t s) {
     hipLaunchKernelGGL(k_selftest, dim3(1), dim3(64), 0, s, out);
     return hipGetLastError();
 }
 
-hipError_t launch_queue_compact(const AsyncQueue& q, unsigned long long* tmp, uint32_t* tmp_count, hipStream_t s) {
-    hipLaunchKernelGGL(k_queue_gather, dim3(1), dim3(1024), 0, s, q, tmp, tmp_count);
-    return hipGetLastError();
-}
 
 }  // namespace omap

@@ -69,27 +69,37 @@ struct Options {
     int TW = 64 * 4 - 2 * 16;
     int dense = 0;
     int check = 0;       // 0 = adaptive
-    int per_round = 1;   // 0 = one persistent launch instead of one launch per round
-    int async = 0;       // 1 = asynchronous work-queue launch (active schedule only)
     int bits = 0;        // 1 = bit-sliced reached-set schedule (C unused; TW = 1984)
-    int budget_us = 50000;   // asynchronous launch: time taking new tiles per launch
+    int graph = 0;       // 1 = rounds replayed from captured HIP graphs
 };
 
 // Defaults (measured on MI355X).  A single maze under the active schedule is
 // latency-bound (a few hundred tiles per round on 1024 SIMDs): one column per
 // lane keeps each visit short, and with the one-column visits' unrolled
 // warm-up 16 layers per visit beat 12 (23170^2 maze: propagation 8.2 vs
-// 8.5 ms; 2 columns and 16 layers: 12.8 ms).  Many mazes at once (batch, engine)
-// fill the device, so 2 columns per lane waste less on halos (512 mazes:
-// 17.2k mazes/s with 12 layers per visit, 16.6k with 16, 13.6k with 4 columns).
+// 8.5 ms; 2 columns and 16 layers: 12.8 ms).  Many mazes at once (batch,
+// engine) fill the device: there the bit-sliced schedule is fastest (512
+// mazes: 19.6k mazes/s against 17.9k for the active schedule with 2 columns
+// per lane and 12 layers per visit; serving capacity 198 against 180 mazes/s).
 // The dense schedule is throughput-bound: 4 columns per lane, 16 layers and
 // tall tiles.
 enum class Use { kPlan, kMany };
 static omap_status_t resolve_options(const omap_options* o, Options* out, Use use = Use::kPlan) {
     Options r;
-    const bool dense = o && o->schedule == OMAP_SCHEDULE_DENSE;
-    const bool bits = o && o->schedule == OMAP_SCHEDULE_BITS;
     const bool single = use == Use::kPlan;
+    int schedule = o ? o->schedule : OMAP_SCHEDULE_DEFAULT;
+    if (schedule != OMAP_SCHEDULE_DEFAULT && schedule != OMAP_SCHEDULE_ACTIVE && schedule != OMAP_SCHEDULE_DENSE &&
+        schedule != OMAP_SCHEDULE_BITS)
+        return fail(OMAP_ERR_INVALID_ARG, "schedule must be DEFAULT, ACTIVE, DENSE or BITS (got %d)", schedule);
+    if (schedule == OMAP_SCHEDULE_DEFAULT) {
+        // the bit-sliced schedule has its own lane layout: an explicit column
+        // count asks for the integer sweep
+        schedule = (single || (o && o->lane_columns != 0)) ? OMAP_SCHEDULE_ACTIVE : OMAP_SCHEDULE_BITS;
+        if (schedule == OMAP_SCHEDULE_BITS && o && o->temporal_depth != 0 && !bits_supported(o->temporal_depth))
+            schedule = OMAP_SCHEDULE_ACTIVE;
+    }
+    const bool dense = schedule == OMAP_SCHEDULE_DENSE;
+    const bool bits = schedule == OMAP_SCHEDULE_BITS;
     r.C = dense ? 4 : (single ? 1 : 2);
     r.T = 0;
     int th = 0;
@@ -106,35 +116,20 @@ static omap_status_t resolve_options(const omap_options* o, Options* out, Use us
                             o->tile_rows);
             th = o->tile_rows;
         }
-        if (o->schedule != OMAP_SCHEDULE_ACTIVE && o->schedule != OMAP_SCHEDULE_DENSE &&
-            o->schedule != OMAP_SCHEDULE_BITS)
-            return fail(OMAP_ERR_INVALID_ARG, "schedule must be ACTIVE, DENSE or BITS (got %d)", o->schedule);
-        r.dense = dense;
         if (o->check_interval < 0) return fail(OMAP_ERR_INVALID_ARG, "check_interval < 0");
         r.check = o->check_interval;
-        if (o->round_launch != OMAP_LAUNCH_PERSISTENT && o->round_launch != OMAP_LAUNCH_PER_ROUND &&
-            o->round_launch != OMAP_LAUNCH_ASYNC)
-            return fail(OMAP_ERR_INVALID_ARG, "round_launch must be PER_ROUND, PERSISTENT or ASYNC (got %d)",
-                        o->round_launch);
-        if (o->round_launch == OMAP_LAUNCH_ASYNC && dense)
-            return fail(OMAP_ERR_INVALID_ARG, "the asynchronous launch needs the active schedule");
-        r.per_round = o->round_launch != OMAP_LAUNCH_PERSISTENT;
-        r.async = o->round_launch == OMAP_LAUNCH_ASYNC;
-        if (o->async_budget_us != 0) {
-            if (o->async_budget_us < 10)
-                return fail(OMAP_ERR_INVALID_ARG, "async_budget_us must be 0 or >= 10 (got %d)", o->async_budget_us);
-            r.budget_us = o->async_budget_us;
-        }
+        if (o->round_launch != OMAP_LAUNCH_PER_ROUND && o->round_launch != OMAP_LAUNCH_GRAPH)
+            return fail(OMAP_ERR_INVALID_ARG, "round_launch must be PER_ROUND or GRAPH (got %d)", o->round_launch);
+        r.graph = o->round_launch == OMAP_LAUNCH_GRAPH;
     }
+    r.dense = dense;
     if (bits) {
-        // bit-sliced: 32 columns per lane, one halo word per side; rounds only
-        if (o->round_launch != OMAP_LAUNCH_PER_ROUND)
-            return fail(OMAP_ERR_INVALID_ARG, "the bit-sliced schedule runs one launch per round");
-        if (o->lane_columns != 0) return fail(OMAP_ERR_INVALID_ARG, "lane_columns must be 0 with the bit-sliced schedule");
+        // bit-sliced: 32 columns per lane, one halo word per side
+        if (o && o->lane_columns != 0)
+            return fail(OMAP_ERR_INVALID_ARG, "lane_columns must be 0 with the bit-sliced schedule");
         r.bits = 1;
-        r.dense = 0;
         r.C = 32;
-        if (o->temporal_depth == 0) r.T = 16;
+        if (r.T == 0) r.T = 16;
         if (!bits_supported(r.T))
             return fail(OMAP_ERR_INVALID_ARG, "temporal_depth %d is not available with the bit-sliced schedule (8, 16)",
                         r.T);
@@ -435,15 +430,6 @@ class Solver {
     int32_t* d_dchg = nullptr;                // [3][cap_slots] dense: changed, by round mod 3
     int32_t* d_last_round = nullptr;          // per slot
     uint8_t* d_touched = nullptr;             // per tile id
-    unsigned int* d_bar = nullptr;            // [2] grid barrier of the persistent launch
-    int32_t* d_rounds_done = nullptr;
-    int pgrid = 0;                            // blocks of the persistent launch (0 = unavailable)
-    // asynchronous launch: work queue (allocated only in that mode)
-    AsyncQueue q{};
-    uint32_t* d_qctl = nullptr;               // head, tail, pending, done, error, gathered count
-    unsigned long long* d_qtmp = nullptr;     // compaction buffer (ring size)
-    int agrid = 0;                            // blocks of an asynchronous launch
-    unsigned long long wall_khz = 0;          // device wall-clock rate
     int64_t *d_visits = nullptr, *d_cell_visits = nullptr;
     unsigned long long* d_total_cells = nullptr;
     int32_t* d_bad_slot = nullptr;            // per slot: sources found on obstacles
@@ -469,6 +455,7 @@ class Solver {
     // profiling of the sweep kernel
     bool prof = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_events;
+    std::vector<int64_t> prof_counts;         // launches each event pair brackets
     int64_t prof_launches = 0;
     double prof_ms = 0;
     unsigned long long prof_cells0 = 0;
@@ -500,6 +487,12 @@ class Solver {
             (void)hipEventDestroy(e.second);
         }
         prof_events.clear();
+        prof_counts.clear();
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        gexec = nullptr;
+        gsig.clear();
+        if (cap_stream) (void)hipStreamDestroy(cap_stream);
+        cap_stream = nullptr;
     }
 
     template <class Tp>
@@ -549,8 +542,6 @@ class Solver {
         OK_TRY(dalloc(&d_dchg, 3 * (size_t)cap_slots));
         OK_TRY(dalloc(&d_last_round, cap_slots));
         OK_TRY(dalloc(&d_touched, cap_tiles));
-        OK_TRY(dalloc(&d_bar, 2));
-        OK_TRY(dalloc(&d_rounds_done, 1));
         OK_TRY(dalloc(&d_bad_slot, cap_slots));
         HIP_TRY(hipHostMalloc((void**)&h_bad, sizeof(int32_t) * cap_slots, hipHostMallocDefault));
         h_mazes.assign(cap_slots, MazeDev());
@@ -574,7 +565,6 @@ class Solver {
         HIP_TRY(hipMemsetAsync(d_dchg, 0, 3 * sizeof(int32_t) * cap_slots, stream));
         HIP_TRY(hipMemsetAsync(d_last_round, 0, sizeof(int32_t) * cap_slots, stream));
         HIP_TRY(hipMemsetAsync(d_touched, 0, cap_tiles, stream));
-        HIP_TRY(hipMemsetAsync(d_bar, 0, 2 * sizeof(unsigned int), stream));
         HIP_TRY(hipMemsetAsync(d_bad_slot, 0, sizeof(int32_t) * cap_slots, stream));
         HIP_TRY(hipMemsetAsync(d_visits, 0, sizeof(int64_t) * cap_slots * kSpread, stream));
         HIP_TRY(hipMemsetAsync(d_cell_visits, 0, sizeof(int64_t) * cap_slots * kSpread, stream));
@@ -587,33 +577,6 @@ class Solver {
         grid = std::max(1, cus * std::max(1, waves / kWavesPerBlock));
         const int need = (cap_tiles + kWavesPerBlock - 1) / kWavesPerBlock;
         grid = std::max(1, std::min(grid, need));
-        int coop = 0;
-        HIP_TRY(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
-        const int per_cu = opt.bits ? 0 : sweep_persistent_blocks_per_cu(opt.T, opt.C);
-        pgrid = (coop && per_cu > 0) ? std::max(1, std::min(cus * per_cu, need)) : 0;
-        if (opt.async) {
-            const int64_t waves = (int64_t)cus * std::min(8, sweep_async_waves_per_cu(opt.T, opt.C));
-            uint64_t ring = 1024;
-            while (ring < 2 * ((uint64_t)cap_tiles + (uint64_t)waves)) ring <<= 1;
-            OK_TRY(dalloc(&q.ring, ring));
-            OK_TRY(dalloc(&d_qtmp, ring));
-            OK_TRY(dalloc(&q.state, cap_tiles));
-            OK_TRY(dalloc(&d_qctl, 8));
-            q.ring_mask = (uint32_t)(ring - 1);
-            q.head = d_qctl;
-            q.tail = d_qctl + 1;
-            q.pending = reinterpret_cast<int32_t*>(d_qctl + 2);
-            q.done = reinterpret_cast<int32_t*>(d_qctl + 3);
-            q.error = reinterpret_cast<int32_t*>(d_qctl + 4);
-            HIP_TRY(hipMemsetAsync(q.ring, 0, sizeof(unsigned long long) * ring, stream));
-            HIP_TRY(hipMemsetAsync(q.state, 0, sizeof(int32_t) * cap_tiles, stream));
-            HIP_TRY(hipMemsetAsync(d_qctl, 0, 8 * sizeof(uint32_t), stream));
-            int khz = 0;
-            HIP_TRY(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
-            wall_khz = (unsigned long long)std::max(khz, 1);
-            q.budget = wall_khz * (unsigned long long)opt.budget_us / 1000ull;
-            agrid = (int)std::max<int64_t>(1, std::min<int64_t>(waves / kWavesPerBlock, need));
-        }
         HIP_TRY(hipStreamSynchronize(stream));
         return OMAP_OK;
     }
@@ -621,9 +584,12 @@ class Solver {
     // Arguments of round r = next_round.  With `seeding` the "out" list,
     // count, flags and scheduled counts are those of round r itself (seeds
     // schedule tiles for the round about to run).
-    RoundArgs round_args(bool seeding = false) const {
+    RoundArgs round_args(bool seeding = false) const { return round_args_at(next_round, seeding); }
+
+    RoundArgs round_args_at(int64_t r, bool seeding = false) const {
         RoundArgs a;
-        const int r2 = (int)(next_round & 1), r3 = (int)(next_round % 3);
+        std::memset(&a, 0, sizeof a);   // padding too: graph_signature compares the bytes
+        const int r2 = (int)(r & 1), r3 = (int)(r % 3);
         const int n2 = r2 ^ 1, n3 = (r3 + 1) % 3, nn3 = (r3 + 2) % 3;
         a.mazes = d_mazes;
         a.tile_maze = d_tile_maze;
@@ -646,13 +612,12 @@ class Solver {
         a.maze_cell_visits = d_cell_visits;
         a.total_cells = d_total_cells;
         a.n_slots = cap_slots;
-        a.round_id = (int32_t)next_round;
+        a.round_id = (int32_t)r;
+        a.round_base = nullptr;
         a.parity = r2;
         a.tile_rows = opt.TH;
         a.tile_cols = opt.TW;
         a.dense = opt.dense;
-        a.async = opt.async;
-        a.q = q;
         a.md0 = h_mazes.empty() ? MazeDev() : h_mazes[0];
         return a;
     }
@@ -1013,52 +978,7 @@ class Solver {
         HIP_TRY(hipMemsetAsync(d_flags[1], 0, sizeof(int32_t) * std::max(tile_hwm, 1), stream));
         HIP_TRY(hipMemsetAsync(d_sched, 0, 3 * sizeof(int32_t) * cap_slots, stream));
         HIP_TRY(hipMemsetAsync(d_dchg, 0, 3 * sizeof(int32_t) * cap_slots, stream));
-        if (opt.async) HIP_TRY(hipMemsetAsync(d_qctl, 0, 8 * sizeof(uint32_t), stream));
         return OMAP_OK;
-    }
-
-    // Asynchronous launches until no tile needs a visit.  A launch that used
-    // up its time budget leaves the unvisited entries in the ring; they are
-    // moved to its start and the next launch continues from them.
-    omap_status_t run_async() {
-        const RoundArgs a = round_args();
-        for (;;) {
-            std::pair<hipEvent_t, hipEvent_t> ev{};
-            if (prof) {
-                HIP_TRY(hipEventCreate(&ev.first));
-                HIP_TRY(hipEventCreate(&ev.second));
-            }
-            HIP_TRY(launch_sweep_async(opt.T, opt.C, a, agrid, stream, ev.first, ev.second));
-            if (prof) prof_events.push_back(ev);
-            HIP_TRY(hipMemcpyAsync(h_pinned, d_qctl, 8 * sizeof(uint32_t), hipMemcpyDeviceToHost, stream));
-            HIP_TRY(hipStreamSynchronize(stream));
-            const int32_t pending = (int32_t)h_pinned[2], error = (int32_t)h_pinned[4];
-            uint32_t n = 0;
-            if (error == 0 && pending != 0) {
-                // paused: gather the queued entries (every pending tile has one)
-                HIP_TRY(launch_queue_compact(q, d_qtmp, d_qctl + 5, stream));
-                HIP_TRY(hipMemcpyAsync(h_pinned, d_qctl + 5, sizeof(uint32_t), hipMemcpyDeviceToHost, stream));
-                HIP_TRY(hipStreamSynchronize(stream));
-                n = (uint32_t)h_pinned[0];
-            }
-            if (error != 0 || (pending != 0 && n != (uint32_t)pending)) {
-                // cannot happen with the ring sized as it is; leave a clean queue
-                HIP_TRY(hipMemsetAsync(q.ring, 0, sizeof(unsigned long long) * (q.ring_mask + 1ull), stream));
-                HIP_TRY(hipMemsetAsync(q.state, 0, sizeof(int32_t) * cap_tiles, stream));
-                HIP_TRY(hipMemsetAsync(d_qctl, 0, 8 * sizeof(uint32_t), stream));
-                HIP_TRY(hipStreamSynchronize(stream));
-                return fail(OMAP_ERR_HIP, "asynchronous launch: inconsistent work queue (error %d, pending %d, queued %u)",
-                            error, pending, n);
-            }
-            if (pending == 0) return OMAP_OK;
-            if (n > 0)
-                HIP_TRY(hipMemcpyAsync(q.ring, d_qtmp, sizeof(unsigned long long) * n, hipMemcpyDeviceToDevice,
-                                       stream));
-            h_pinned[8] = 0;
-            h_pinned[9] = (int32_t)n;
-            HIP_TRY(hipMemcpyAsync(d_qctl, h_pinned + 8, 2 * sizeof(uint32_t), hipMemcpyHostToDevice, stream));
-            HIP_TRY(hipStreamSynchronize(stream));
-        }
     }
 
     // One round: one sweep launch.
@@ -1072,6 +992,7 @@ class Solver {
             if (opt.bits) HIP_TRY(launch_bits(opt.T, a, grid, stream, ev.first, ev.second));
             else HIP_TRY(launch_sweep(opt.T, opt.C, a, grid, stream, ev.first, ev.second));
             prof_events.push_back(ev);
+            prof_counts.push_back(1);
         } else if (opt.bits) {
             HIP_TRY(launch_bits(opt.T, a, grid, stream));
         } else {
@@ -1082,6 +1003,97 @@ class Solver {
         return OMAP_OK;
     }
 
+    // ---- rounds replayed from a captured HIP graph (OMAP_LAUNCH_GRAPH) ----
+    // A group of kGraphRounds round launches is captured once and replayed:
+    // the round buffers rotate with period 6 (lists and flags by r mod 2,
+    // counts by r mod 3), so a group that starts at a round r = 0 mod 6 has
+    // the same arguments every time except the round numbers, which the
+    // kernels take from a device counter (round_base) that a last node of the
+    // group advances.  The graph is captured again whenever another argument
+    // changes (a maze added or restarted, another tile id range).
+    static constexpr int kGraphRounds = 24;
+    hipStream_t cap_stream = nullptr;         // capture only (never runs work)
+    hipGraphExec_t gexec = nullptr;
+    std::vector<char> gsig;                   // arguments the graph was captured with
+    int32_t* d_round_base = nullptr;
+
+    std::vector<char> graph_signature() const {
+        RoundArgs a = round_args_at(0);
+        a.round_id = 0;
+        std::vector<char> sig(sizeof(RoundArgs) + 3 * sizeof(int));
+        std::memcpy(sig.data(), &a, sizeof a);
+        const int extra[3] = {grid, opt.T, opt.C + 100 * opt.bits};
+        std::memcpy(sig.data() + sizeof a, extra, sizeof extra);
+        return sig;
+    }
+
+    omap_status_t graph_ensure() {
+        std::vector<char> sig = graph_signature();
+        if (gexec && sig == gsig) return OMAP_OK;
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        gexec = nullptr;
+        gsig.clear();
+        if (!d_round_base) OK_TRY(dalloc(&d_round_base, 1));
+        if (!cap_stream) HIP_TRY(hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking));
+        HIP_TRY(hipStreamBeginCapture(cap_stream, hipStreamCaptureModeRelaxed));
+        hipError_t e = hipSuccess;
+        for (int k = 0; k < kGraphRounds && e == hipSuccess; ++k) {
+            RoundArgs a = round_args_at(k);
+            a.round_id = k;
+            a.round_base = d_round_base;
+            e = opt.bits ? launch_bits(opt.T, a, grid, cap_stream) : launch_sweep(opt.T, opt.C, a, grid, cap_stream);
+        }
+        if (e == hipSuccess) e = launch_round_advance(d_round_base, kGraphRounds, cap_stream);
+        hipGraph_t g = nullptr;
+        const hipError_t e2 = hipStreamEndCapture(cap_stream, &g);
+        if (e == hipSuccess) e = e2;
+        if (e == hipSuccess) e = hipGraphInstantiate(&gexec, g, nullptr, nullptr, 0);
+        if (g) (void)hipGraphDestroy(g);
+        if (e != hipSuccess) {
+            gexec = nullptr;
+            return fail(OMAP_ERR_HIP, "capturing the round graph: %s", hipGetErrorString(e));
+        }
+        gsig.swap(sig);
+        return OMAP_OK;
+    }
+
+    // At least `rounds` rounds: single launches up to the next multiple of 6,
+    // then whole graph replays (the rest as single launches when
+    // `exact`, else rounded up to whole replays).
+    omap_status_t graph_rounds(int64_t rounds, bool exact) {
+        int64_t done = 0;
+        while (next_round % 6 != 0 && done < rounds) {
+            OK_TRY(round());
+            ++done;
+        }
+        int64_t reps = (rounds - done) / kGraphRounds;
+        if (!exact && (rounds - done) % kGraphRounds != 0) ++reps;
+        if (reps > 0) {
+            OK_TRY(graph_ensure());
+            HIP_TRY(launch_fill(d_round_base, 1, (int32_t)next_round, stream));
+            std::pair<hipEvent_t, hipEvent_t> ev{};
+            if (prof) {
+                HIP_TRY(hipEventCreate(&ev.first));
+                HIP_TRY(hipEventCreate(&ev.second));
+                HIP_TRY(hipEventRecord(ev.first, stream));
+            }
+            for (int64_t i = 0; i < reps; ++i) HIP_TRY(hipGraphLaunch(gexec, stream));
+            if (prof) {
+                HIP_TRY(hipEventRecord(ev.second, stream));
+                prof_events.push_back(ev);
+                prof_counts.push_back(reps * kGraphRounds);
+            }
+            next_round += reps * kGraphRounds;
+            done += reps * kGraphRounds;
+            parity = (int)(next_round & 1);
+        }
+        while (done < rounds) {
+            OK_TRY(round());
+            ++done;
+        }
+        return OMAP_OK;
+    }
+
     omap_status_t scheduled_count(int32_t* n) {
         HIP_TRY(hipMemcpyAsync(h_pinned, d_count + next_round % 3, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
         HIP_TRY(hipStreamSynchronize(stream));
@@ -1089,71 +1101,29 @@ class Solver {
         return OMAP_OK;
     }
 
-    // Up to `max_rounds` rounds in one cooperative launch; returns the rounds
-    // run (it stops early after a round that schedules nothing) and the
-    // number of tiles scheduled next (synchronous).
-    omap_status_t persistent(int32_t max_rounds, int32_t* ran, int32_t* scheduled) {
-        PersistentArgs p;
-        p.base = round_args();
-        p.list[0] = d_list[0];
-        p.list[1] = d_list[1];
-        p.count = d_count;
-        p.flags[0] = d_flags[0];
-        p.flags[1] = d_flags[1];
-        p.sched = d_sched;
-        p.dchg = d_dchg;
-        p.r0_mod6 = (int32_t)(next_round % 6);
-        p.max_rounds = max_rounds;
-        p.bar_count = d_bar;
-        p.bar_gen = d_bar + 1;
-        p.rounds_done = d_rounds_done;
-        std::pair<hipEvent_t, hipEvent_t> ev{};
-        if (prof) {
-            HIP_TRY(hipEventCreate(&ev.first));
-            HIP_TRY(hipEventCreate(&ev.second));
-            HIP_TRY(hipEventRecord(ev.first, stream));
-        }
-        HIP_TRY(launch_sweep_persistent(opt.T, opt.C, p, pgrid, stream));
-        if (prof) {
-            HIP_TRY(hipEventRecord(ev.second, stream));
-            prof_events.push_back(ev);
-        }
-        HIP_TRY(hipMemcpyAsync(h_pinned, d_rounds_done, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
-        HIP_TRY(hipStreamSynchronize(stream));
-        *ran = h_pinned[0];
-        next_round += *ran;
-        parity = (int)(next_round & 1);
-        if (scheduled) OK_TRY(scheduled_count(scheduled));
-        return OMAP_OK;
-    }
-
-    bool use_persistent() const { return pgrid > 0 && !opt.per_round; }
-
     // Activity buffer holding the latest values: the round parity, except for
     // the bit-sliced schedule, which writes each reached cell's value once,
     // into buffer 0.
     int vparity() const { return opt.bits ? 0 : parity; }
 
-    // `rounds` rounds (fewer if everything converges first with the
-    // persistent launch).
+    // `rounds` rounds.
     omap_status_t run_rounds(int32_t rounds) {
-        if (rounds <= 0) return OMAP_OK;
-        if (use_persistent()) {
-            int32_t ran = 0;
-            return persistent(rounds, &ran, nullptr);
-        }
+        if (opt.graph && rounds >= kGraphRounds + 5) return graph_rounds(rounds, true);
         for (int32_t i = 0; i < rounds; ++i) OK_TRY(round());
         return OMAP_OK;
     }
 
     // Rounds until no tile is scheduled (every started maze converged).
     omap_status_t run_to_convergence() {
-        if (opt.async) return run_async();
-        if (use_persistent()) {
+        if (opt.graph) {
+            // whole replays between count reads: 1, 2, 4, 4, ...
+            int reps = 1;
             for (;;) {
-                int32_t ran = 0, n = 0;
-                OK_TRY(persistent(1 << 30, &ran, &n));
+                OK_TRY(graph_rounds((int64_t)reps * kGraphRounds, false));
+                int32_t n = 0;
+                OK_TRY(scheduled_count(&n));
                 if (n == 0) return OMAP_OK;
+                reps = std::min(reps * 2, 4);
             }
         }
         int g = opt.check > 0 ? opt.check : 2;
@@ -1421,6 +1391,7 @@ class Solver {
                 (void)hipEventDestroy(e.second);
             }
             prof_events.clear();
+            prof_counts.clear();
             prof_launches = 0;
             prof_ms = 0;
             OK_TRY(total_cells(&prof_cells0));
@@ -1431,15 +1402,17 @@ class Solver {
 
     omap_status_t profile_read(int64_t* launches, double* ms, int64_t* cell_updates) {
         HIP_TRY(hipStreamSynchronize(stream));
-        for (auto& e : prof_events) {
+        for (size_t i = 0; i < prof_events.size(); ++i) {
+            auto& e = prof_events[i];
             float t = 0;
             HIP_TRY(hipEventElapsedTime(&t, e.first, e.second));
             prof_ms += t;
-            ++prof_launches;
+            prof_launches += prof_counts[i];
             (void)hipEventDestroy(e.first);
             (void)hipEventDestroy(e.second);
         }
         prof_events.clear();
+        prof_counts.clear();
         unsigned long long cells = 0;
         OK_TRY(total_cells(&cells));
         if (launches) *launches = prof_launches;
@@ -1924,9 +1897,7 @@ omap_status_t omap_resolve_options(const omap_options* options, omap_options* re
     resolved->schedule = r.bits ? OMAP_SCHEDULE_BITS : (r.dense ? OMAP_SCHEDULE_DENSE : OMAP_SCHEDULE_ACTIVE);
     resolved->check_interval = r.check;
     resolved->lane_columns = r.bits ? 0 : r.C;
-    resolved->round_launch =
-        r.async ? OMAP_LAUNCH_ASYNC : (r.per_round ? OMAP_LAUNCH_PER_ROUND : OMAP_LAUNCH_PERSISTENT);
-    resolved->async_budget_us = r.budget_us;
+    resolved->round_launch = r.graph ? OMAP_LAUNCH_GRAPH : OMAP_LAUNCH_PER_ROUND;
     return OMAP_OK;
 }
 
@@ -2272,8 +2243,6 @@ omap_status_t omap_engine_create(omap_engine_t* out, int64_t memory_budget_bytes
         return fail(OMAP_ERR_INVALID_ARG, "need out, budget >= 1 MiB and max_slots >= 1");
     Options o;
     OK_TRY(resolve_options(opts, &o, Use::kMany));
-    o.async = 0;   // the engine advances mazes by whole rounds
-    o.per_round = 1;
     std::unique_ptr<omap_engine_s> e(new omap_engine_s());
     if (!e->mem.init((size_t)memory_budget_bytes))
         return fail(OMAP_ERR_OUT_OF_MEMORY, "engine budget of %lld bytes", (long long)memory_budget_bytes);

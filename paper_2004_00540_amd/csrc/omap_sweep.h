@@ -73,14 +73,6 @@ __device__ __forceinline__ void schedule_tile(const RoundArgs& a, const MazeDev&
     }
 }
 
-// Pushes one tile, already counted as pending, onto the asynchronous work
-// queue (see k_sweep_async).  One lane.
-__device__ __forceinline__ void queue_push(const AsyncQueue& q, int g, int slot) {
-    const uint32_t k = atomicAdd(q.tail, 1u);
-    const unsigned long long e = ((unsigned long long)(uint32_t)slot << 32) | (uint32_t)(g + 1);
-    if (atomicCAS(q.ring + (k & q.ring_mask), 0ull, e) != 0ull) atomicAdd(q.error, 1);
-}
-
 // ---------------------------------------------------------------------------
 // the sweep: T layers per tile visit, one wave per tile
 // ---------------------------------------------------------------------------
@@ -259,10 +251,7 @@ __device__ __forceinline__ void sweep_warm(uint32_t (&st)[T][3][C], typename Lan
 
 // Returns true (wave-uniform) if any interior cell of the tile changed.  The
 // wave streams the strip of 64*C columns starting T columns left of the tile.
-// In place (IN_PLACE) the tile reads and writes buffer `parity`: a row is
-// stored only after it and the T rows below it were loaded, so the visit never
-// reads its own output.
-template <int T, int C, bool IN_PLACE = false>
+template <int T, int C>
 __device__ bool sweep_tile(const MazeDev& md, int ty, int tx, int tile_rows, int parity) {
     constexpr int TW = kLanes * C - 2 * T;
     constexpr int HALO_LANES = T / C;
@@ -274,7 +263,7 @@ __device__ bool sweep_tile(const MazeDev& md, int ty, int tx, int tile_rows, int
     const bool col_ok = col >= 0 && col < md.pitch;
     const bool inner = lane >= HALO_LANES && lane < kLanes - HALO_LANES && col < md.W;
     int32_t* const Vin = parity ? md.V[1] : md.V[0];
-    int32_t* const Vout = IN_PLACE ? Vin : (parity ? md.V[0] : md.V[1]);
+    int32_t* const Vout = parity ? md.V[0] : md.V[1];
 
     uint32_t st[T][3][C];
 #pragma unroll
@@ -318,35 +307,6 @@ __device__ bool sweep_tile(const MazeDev& md, int ty, int tx, int tile_rows, int
     return __ballot(sum_in != sum_out) != 0;
 }
 
-// Loads of scheduling data that another block may have written in an earlier
-// round of the same (persistent) launch: agent-scope atomic loads bypass the
-// per-CU caches.
-__device__ __forceinline__ int32_t load_shared(const int32_t* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// The same for an 8-byte-aligned pair of int32 (low word first).
-__device__ __forceinline__ uint64_t load_shared64(const int32_t* p) {
-    return __hip_atomic_load(reinterpret_cast<const uint64_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Scheduling data of round r: written by another block in the same launch
-// (persistent launch: coherent agent-scope loads) or by an earlier launch
-// (plain loads, which may hit in the L2).
-template <bool SHARED>
-__device__ __forceinline__ int32_t load_sched(const int32_t* p) {
-    return SHARED ? load_shared(p) : *p;
-}
-template <bool SHARED>
-__device__ __forceinline__ uint64_t load_sched64(const int32_t* p) {
-    return SHARED ? load_shared64(p) : *reinterpret_cast<const uint64_t*>(p);
-}
-
-// Round r: every scheduled tile gets T layers.  Active schedule: the tiles of
-// a.list_in; a changed tile schedules itself and its 8 neighbour tiles for
-// round r+1.  Dense schedule: every tile of each maze that changed in round
-// r-1; a changed tile flags its maze for round r+1.  Block 0 also clears the
-// buffers round r+1 will fill.
 // Tile g of slot: T layers.  Returns true (wave-uniform) if the interior
 // changed; md, ty, tx describe the tile.
 template <int T, int C>
@@ -381,7 +341,12 @@ __device__ __forceinline__ void visit_bookkeeping_active(const RoundArgs& a, int
     visit_bookkeeping(a, g, slot, md, ty, tx);
 }
 
-template <int T, int C, bool SHARED>
+// Round r: every scheduled tile gets T layers.  Active schedule: the tiles of
+// a.list_in; a changed tile schedules itself and its 8 neighbour tiles for
+// round r+1.  Dense schedule: every tile of each maze that changed in round
+// r-1; a changed tile flags its maze for round r+1.  Block 0 also clears the
+// buffers round r+1 will fill.
+template <int T, int C>
 __device__ __forceinline__ void sweep_round(const RoundArgs& a) {
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = lane_id();
@@ -391,8 +356,8 @@ __device__ __forceinline__ void sweep_round(const RoundArgs& a) {
     // overlap (the entry is in bounds for any i below the tile id space, and
     // used only if i < n).
     uint64_t e = 0;
-    if (!a.dense && i < a.n_tile_ids) e = load_sched64<SHARED>(a.list_in + 2 * i);
-    const int n = a.dense ? a.n_tile_ids : __builtin_amdgcn_readfirstlane(load_sched<SHARED>(a.count_in));
+    if (!a.dense && i < a.n_tile_ids) e = *reinterpret_cast<const uint64_t*>(a.list_in + 2 * i);
+    const int n = a.dense ? a.n_tile_ids : __builtin_amdgcn_readfirstlane(*a.count_in);
     if (blockIdx.x == 0) {
         if (threadIdx.x == 0) *a.count_clear = 0;
         for (int m = threadIdx.x; m < a.n_slots; m += kBlockThreads) {
@@ -403,7 +368,7 @@ __device__ __forceinline__ void sweep_round(const RoundArgs& a) {
     if (a.dense) {
         for (; i < n; i += stride) {
             const int slot = a.tile_maze[i];
-            if (slot < 0 || __builtin_amdgcn_readfirstlane(load_sched<SHARED>(a.dchg_prev + slot)) == 0) continue;
+            if (slot < 0 || __builtin_amdgcn_readfirstlane(a.dchg_prev[slot]) == 0) continue;
             MazeDev md;
             int ty, tx;
             const bool changed = visit_tile<T, C>(a, i, slot, md, ty, tx);
@@ -432,7 +397,7 @@ __device__ __forceinline__ void sweep_round(const RoundArgs& a) {
         if (i < n) {
             g = __builtin_amdgcn_readfirstlane((int)(uint32_t)e);
             slot = __builtin_amdgcn_readfirstlane((int)(uint32_t)(e >> 32));
-            if (i + stride < n) e = load_sched64<SHARED>(a.list_in + 2 * (i + stride));
+            if (i + stride < n) e = *reinterpret_cast<const uint64_t*>(a.list_in + 2 * (i + stride));
             if (visit_tile<T, C>(a, g, slot, md, ty, tx)) {
                 // lanes 0..8 claim the 3x3 tiles around (ty, tx) for the next round
                 const int ny = ty + lane / 3 - 1, nx = tx + lane % 3 - 1;
@@ -468,171 +433,8 @@ __device__ __forceinline__ void sweep_round(const RoundArgs& a) {
 
 template <int T, int C>
 __global__ __launch_bounds__(kBlockThreads) void k_sweep(RoundArgs a) {
-    sweep_round<T, C, false>(a);
-}
-
-// Device-wide barrier of a cooperative launch (all blocks resident): the last
-// block to arrive resets the counter and advances the generation; the others
-// wait for the generation to change.  Fences on both sides publish this
-// block's writes and drop stale lines from the CU's caches.
-__device__ __forceinline__ void grid_barrier(unsigned int* count, unsigned int* gen) {
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const unsigned int g = __hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __threadfence();
-        if (atomicAdd(count, 1u) == gridDim.x - 1) {
-            __hip_atomic_store(count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __threadfence();
-            atomicAdd(gen, 1u);
-        } else {
-            while (__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g)
-                __builtin_amdgcn_s_sleep(1);
-        }
-    }
-    __syncthreads();
-    __threadfence();
-}
-
-// Up to p.max_rounds rounds in one cooperative launch, stopping after the
-// first round that schedules nothing (every resident maze converged).  The
-// stop test reads the round's final count after the barrier, so every block
-// takes the same decision.
-template <int T, int C>
-__global__ __launch_bounds__(kBlockThreads) void k_sweep_persistent(PersistentArgs p) {
-    int k = 0;
-    for (; k < p.max_rounds; ++k) {
-        RoundArgs a = p.base;
-        const int r = p.r0_mod6 + k;
-        const int r2 = r & 1, r3 = r % 3, n3 = (r3 + 1) % 3, nn3 = (r3 + 2) % 3;
-        const size_t cs = (size_t)p.base.n_slots;
-        a.list_in = p.list[r2];
-        a.count_in = p.count + r3;
-        a.flags_in = p.flags[r2];
-        a.list_out = p.list[r2 ^ 1];
-        a.count_out = p.count + n3;
-        a.flags_out = p.flags[r2 ^ 1];
-        a.count_clear = p.count + nn3;
-        a.sched_out = p.sched + n3 * cs;
-        a.sched_clear = p.sched + nn3 * cs;
-        a.dchg_prev = p.dchg + nn3 * cs;
-        a.dchg_cur = p.dchg + r3 * cs;
-        a.dchg_clear = p.dchg + n3 * cs;
-        a.round_id = p.base.round_id + k;
-        a.parity = r2;
-        sweep_round<T, C, true>(a);
-        grid_barrier(p.bar_count, p.bar_gen);
-        if (load_shared(a.count_out) == 0) {
-            ++k;
-            break;
-        }
-    }
-    if (blockIdx.x == 0 && threadIdx.x == 0) *p.rounds_done = k;
-}
-
-// ---------------------------------------------------------------------------
-// asynchronous launch: a work queue instead of rounds
-// ---------------------------------------------------------------------------
-//
-// Tiles are visited in place, in any order, by waves that take them from a
-// ring of (slot, tile) entries.  A tile whose visit changed its interior marks
-// itself and its 8 neighbour tiles as needing a visit: an idle tile is pushed,
-// a tile being visited is flagged and pushed again when its visit ends (the
-// values that visit read may predate the change).  Because the update is
-// monotone and bounded by its fixpoint, values read while a neighbour is being
-// written are lower bounds, every visit only raises values, and the launch
-// reaches the same fixpoint bits as the round schedules once no tile needs a
-// visit.  Agent-scope release / acquire fences order a tile's stores before
-// the marks it makes and a visit's loads after the mark that queued it.
-
-// Marks `slot`'s tiles around (ty, tx) (lanes 0..8, one tile each); idle tiles
-// are counted as pending and pushed with one reservation for the whole wave.
-__device__ __forceinline__ void queue_mark_neighbourhood(const AsyncQueue& q, const MazeDev& md, int slot,
-                                                         int ty, int tx) {
-    const int lane = lane_id();
-    const int ny = ty + lane / 3 - 1, nx = tx + lane % 3 - 1;
-    const int g = md.tile_base + ny * md.tiles_x + nx;
-    bool won = false;
-    if (lane < 9 && ny >= 0 && ny < md.tiles_y && nx >= 0 && nx < md.tiles_x)
-        won = atomicOr(&q.state[g], 1) == 0;
-    const uint64_t mask = __ballot(won);
-    if (mask == 0) return;
-    const int n = __popcll(mask);
-    uint32_t base = 0;
-    if (lane == 0) {
-        // pending is raised before the entries can be taken: the second
-        // atomic's operand depends on the first one's result (p >= 0 always)
-        const int p = atomicAdd(q.pending, n);
-        base = atomicAdd(q.tail, (uint32_t)n + (uint32_t)(p < 0));
-    }
-    base = __builtin_amdgcn_readfirstlane(base);
-    if (won) {
-        const uint32_t k = base + (uint32_t)__popcll(mask & ((1ull << lane) - 1));
-        const unsigned long long e = ((unsigned long long)(uint32_t)slot << 32) | (uint32_t)(g + 1);
-        if (atomicCAS(q.ring + (k & q.ring_mask), 0ull, e) != 0ull) atomicAdd(q.error, 1);
-    }
-}
-
-template <int T, int C>
-__global__ __launch_bounds__(kBlockThreads) void k_sweep_async(RoundArgs a) {
-    const AsyncQueue& q = a.q;
-    const int lane = lane_id();
-    const unsigned long long t0 = wall_clock64();
-    for (;;) {
-        if (wall_clock64() - t0 > q.budget) break;          // pause: the host relaunches
-        uint32_t ticket = 0;
-        if (lane == 0) ticket = atomicAdd(q.head, 1u);
-        ticket = __builtin_amdgcn_readfirstlane(ticket);
-        unsigned long long* ep = q.ring + (ticket & q.ring_mask);
-        unsigned long long e = 0;
-        for (int poll = 0;; ++poll) {
-            e = __hip_atomic_load(ep, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            e = ((unsigned long long)__builtin_amdgcn_readfirstlane((uint32_t)(e >> 32)) << 32) |
-                __builtin_amdgcn_readfirstlane((uint32_t)e);
-            if (e != 0) break;
-            if ((poll & 7) == 7 && (__builtin_amdgcn_readfirstlane(load_shared(q.done)) != 0 ||
-                                    wall_clock64() - t0 > q.budget))
-                break;
-            __builtin_amdgcn_s_sleep(32);
-        }
-        if (e == 0) break;   // converged, or paused with this ticket unfilled
-        const int g = (int)(uint32_t)e - 1;
-        const int slot = (int)(e >> 32);
-        if (lane == 0) {
-            __hip_atomic_store(ep, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            atomicExch(&q.state[g], 2);                      // being visited; clears "needs a visit"
-        }
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        const MazeDev md = a.n_slots == 1 ? a.md0 : a.mazes[slot];
-        const int lt = g - md.tile_base;
-        const int ty = lt / md.tiles_x;
-        const int tx = lt - ty * md.tiles_x;
-        if (lane == 0) {
-            const unsigned long long cells =
-                (unsigned long long)tile_cells(md, ty, tx, a.tile_rows, a.tile_cols);
-            const int sp = blockIdx.x & (kSpread - 1);
-            atomicAdd(reinterpret_cast<unsigned long long*>(&a.maze_visits[slot * kSpread + sp]), 1ull);
-            atomicAdd(reinterpret_cast<unsigned long long*>(&a.maze_cell_visits[slot * kSpread + sp]), cells);
-            atomicAdd(a.total_cells + sp, cells);
-            a.touched[g] = 1;
-        }
-        const bool changed = sweep_tile<T, C, true>(md, ty, tx, a.tile_rows, a.parity);
-        // Every visit publishes its stores before it ends, changed or not: a
-        // store left dirty in this XCD's L2 could otherwise be written back
-        // after a later visit (on another XCD) stored larger values, and
-        // overwrite them.
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        if (changed) queue_mark_neighbourhood(q, md, slot, ty, tx);
-        if (lane == 0) {
-            const int old = atomicCAS(&q.state[g], 2, 0);
-            if (old == 2) {
-                if (atomicSub(q.pending, 1) == 1) __hip_atomic_store(q.done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            } else {
-                // marked while being visited: needs another visit (still pending)
-                atomicExch(&q.state[g], 1);
-                queue_push(q, g, slot);
-            }
-        }
-    }
+    if (a.round_base) a.round_id += *a.round_base;
+    sweep_round<T, C>(a);
 }
 
 // Launch functions of one variant (defined in its own translation unit).
@@ -648,26 +450,9 @@ __global__ __launch_bounds__(kBlockThreads) void k_sweep_async(RoundArgs a) {
             hipLaunchKernelGGL((k_sweep<t, c>), dim3(grid), dim3(kBlockThreads), 0, s, b);           \
         return hipGetLastError();                                                                     \
     }                                                                                                 \
-    hipError_t launch_sweep_persistent_T##t##_C##c(const PersistentArgs& p, int32_t grid, hipStream_t s) { \
-        PersistentArgs q = p;                                                                         \
-        q.base.wave_stride = grid * kWavesPerBlock;                                                   \
-        void* args[] = {&q};                                                                          \
-        return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_sweep_persistent<t, c>),   \
-                                          dim3(grid), dim3(kBlockThreads), args, 0, s);               \
-    }                                                                                                 \
-    hipError_t launch_sweep_async_T##t##_C##c(const RoundArgs& a, int32_t grid, hipStream_t s, hipEvent_t e0, \
-                                              hipEvent_t e1) {                                        \
-        if (e0 != nullptr)                                                                            \
-            hipExtLaunchKernelGGL((k_sweep_async<t, c>), dim3(grid), dim3(kBlockThreads), 0, s, e0, e1, 0, a); \
-        else                                                                                          \
-            hipLaunchKernelGGL((k_sweep_async<t, c>), dim3(grid), dim3(kBlockThreads), 0, s, a);     \
-        return hipGetLastError();                                                                     \
-    }                                                                                                 \
-    int sweep_blocks_per_cu_T##t##_C##c(int kind) {                                                   \
+    int sweep_blocks_per_cu_T##t##_C##c() {                                                           \
         int blocks = 0;                                                                               \
-        hipError_t e = kind == 0   ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_sweep<t, c>, kBlockThreads, 0) \
-                       : kind == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_sweep_persistent<t, c>, kBlockThreads, 0) \
-                                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_sweep_async<t, c>, kBlockThreads, 0); \
+        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_sweep<t, c>, kBlockThreads, 0); \
         return e == hipSuccess ? blocks : 0;                                                          \
     }
 

@@ -111,29 +111,28 @@ def test_batch_validation_names_the_maze():
 def test_resolve_options_fills_defaults():
     d = omap.resolve_options()
     assert d == {"temporal_depth": 16, "tile_rows": 16, "schedule": omap.SCHEDULE_ACTIVE,
-                 "check_interval": 0, "lane_columns": 1, "round_launch": omap.LAUNCH_PER_ROUND,
-                 "async_budget_us": 50000}
+                 "check_interval": 0, "lane_columns": 1, "round_launch": omap.LAUNCH_PER_ROUND}
+    # the default schedule can also be asked for explicitly, and a plan's is the active one
+    assert omap.resolve_options(schedule=omap.SCHEDULE_ACTIVE) == d
+    assert omap.resolve_options(schedule=omap.SCHEDULE_DEFAULT) == d
     d = omap.resolve_options(schedule=omap.SCHEDULE_DENSE)
     assert (d["lane_columns"], d["tile_rows"], d["temporal_depth"]) == (4, 256, 16)
-    d = omap.resolve_options(temporal_depth=32, round_launch=omap.LAUNCH_PERSISTENT)
-    assert (d["tile_rows"], d["lane_columns"], d["round_launch"]) == (32, 2, omap.LAUNCH_PERSISTENT)
+    d = omap.resolve_options(temporal_depth=32, round_launch=omap.LAUNCH_GRAPH)
+    assert (d["tile_rows"], d["lane_columns"], d["round_launch"]) == (32, 2, omap.LAUNCH_GRAPH)
     d = omap.resolve_options(temporal_depth=16, lane_columns=2)
     assert (d["tile_rows"], d["lane_columns"]) == (16, 2)
     d = omap.resolve_options(lane_columns=2)
     assert (d["temporal_depth"], d["tile_rows"]) == (12, 16)
     d = omap.resolve_options(temporal_depth=12)
     assert (d["temporal_depth"], d["tile_rows"], d["lane_columns"]) == (12, 12, 1)
-    with pytest.raises(omap.OmapError):
-        omap.resolve_options(temporal_depth=32, lane_columns=4)
-    with pytest.raises(omap.OmapError):
-        omap.resolve_options(round_launch=omap.LAUNCH_ASYNC, schedule=omap.SCHEDULE_DENSE)
-    with pytest.raises(omap.OmapError):
-        omap.resolve_options(round_launch=omap.LAUNCH_ASYNC, async_budget_us=5)
-    assert omap.resolve_options(round_launch=omap.LAUNCH_ASYNC, async_budget_us=200)["async_budget_us"] == 200
+    for bad in (dict(temporal_depth=32, lane_columns=4), dict(round_launch=2), dict(schedule=4),
+                dict(check_interval=-1), dict(tile_rows=7)):
+        with pytest.raises(omap.OmapError):
+            omap.resolve_options(**bad)
     d = omap.resolve_options(schedule=omap.SCHEDULE_BITS)
     assert (d["schedule"], d["temporal_depth"], d["tile_rows"], d["lane_columns"]) == (omap.SCHEDULE_BITS, 16, 16, 0)
-    for bad in (dict(temporal_depth=12), dict(lane_columns=2), dict(round_launch=omap.LAUNCH_ASYNC),
-                dict(round_launch=omap.LAUNCH_PERSISTENT), dict(temporal_depth=16, tile_rows=8)):
+    assert omap.resolve_options(schedule=omap.SCHEDULE_BITS, round_launch=omap.LAUNCH_GRAPH)["round_launch"] == 1
+    for bad in (dict(temporal_depth=12), dict(lane_columns=2), dict(temporal_depth=16, tile_rows=8)):
         with pytest.raises(omap.OmapError):
             omap.resolve_options(schedule=omap.SCHEDULE_BITS, **bad)
     L = omap.lib()

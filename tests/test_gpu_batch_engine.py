@@ -30,8 +30,8 @@ def _batch_mazes(n, seed, hmax=300):
     return ms
 
 
-@pytest.mark.parametrize("T,tile_rows,schedule,launch", [(16, 64, 0, 0), (8, 16, 0, 0), (4, 8, 1, 0), (12, 24, 0, 0),
-                                                        (16, 16, 0, 2), (8, 8, 0, 2)])
+@pytest.mark.parametrize("T,tile_rows,schedule,launch", [(16, 64, 1, 0), (8, 16, 1, 0), (4, 8, 2, 0), (12, 24, 1, 0),
+                                                        (16, 16, 1, 1), (8, 8, 2, 1), (16, 16, 3, 1), (8, 16, 3, 0)])
 def test_batch_matches_oracle(T, tile_rows, schedule, launch):
     import paper_2004_00540_amd as omap
     ms = _batch_mazes(24, 50 + T + launch)

@@ -10,7 +10,7 @@ from gpu_helpers import assert_same, oracle_solution, run_plan, to_dev
 
 pytestmark = pytest.mark.gpu
 
-BITS = 2
+BITS = 3   # OMAP_SCHEDULE_BITS
 
 
 @pytest.mark.parametrize("T", [8, 16])

@@ -12,6 +12,7 @@ from gpu_helpers import assert_same, oracle_solution, run_plan, to_dev
 pytestmark = pytest.mark.gpu
 
 ALL_T = (4, 8, 12, 16)
+ACTIVE, DENSE, BITS = 1, 2, 3      # OMAP_SCHEDULE_*
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -119,7 +120,7 @@ def test_schedules_and_options_identical_bits():
     ref = oracle_solution(m, -1)
     for T, C in VARIANTS:
         for th in sorted({T, 2 * T + 2, 64, 256}):
-            for sched in (0, 1):
+            for sched in (ACTIVE, DENSE):
                 for chk in (0, 1, 5):
                     got = run_plan(m, -1, temporal_depth=T, tile_rows=th, schedule=sched, check_interval=chk,
                                    lane_columns=C)
@@ -136,39 +137,35 @@ def test_config2_full_size():
     m = workloads.config2()
     got = run_plan(m, -1)
     assert_same(m, got, oracle_solution(m, -1, closed_form=True), "config2")
-    got = run_plan(m, 1000, schedule=1)
+    got = run_plan(m, 1000, schedule=DENSE)
     assert_same(m, got, oracle_solution(m, 1000, closed_form=True), "config2 L=1000 dense")
 
 
-@pytest.mark.parametrize("launch", [0, 1, 2])
+@pytest.mark.parametrize("launch", [0, 1])
 def test_launch_modes_identical_bits(launch):
     for i, (T, C) in enumerate([(16, 2), (16, 4), (8, 2), (32, 2)]):
         m = workloads.random_maze(400, 700, 0.33, 2 + i, 30, 6060 + i)
-        for sched in ((0,) if launch == 2 else (0, 1)):
+        for sched in (ACTIVE, DENSE):
             for L in (-1, 40):
                 print(f"launch={launch} T={T} C={C} sched={sched} L={L}", flush=True)
                 got = run_plan(m, L, temporal_depth=T, lane_columns=C, schedule=sched, round_launch=launch)
                 assert_same(m, got, oracle_solution(m, L), f"launch={launch} T={T} C={C} sched={sched} L={L}")
 
 
-@pytest.mark.parametrize("T,C", [(v[0], v[1]) for v in VARIANTS])
-def test_async_launch_every_variant(T, C):
-    """The work-queue launch (in-place tile updates in any order) reaches the
-    oracle's bits with every kernel variant, on mazes of several shapes."""
-    for k, (H, W, p) in enumerate([(130, 517, 0.3), (333, 64, 0.2), (1, 900, 0.0), (257, 255, 0.38)]):
-        m = workloads.random_maze(H, W, p, 3, 20, 9100 + 17 * T + C + k)
-        for L in (-1, 25):
-            got = run_plan(m, L, temporal_depth=T, lane_columns=C, round_launch=2)
-            assert_same(m, got, oracle_solution(m, L), f"async T={T} C={C} {H}x{W} L={L}")
-
-
-def test_async_launch_pauses_and_resumes():
-    """A tiny time budget makes every launch pause with tiles still queued; the
-    queued tiles are gathered and the next launch continues from them."""
-    m = workloads.random_maze(700, 900, 0.3, 4, 40, 9200)
-    ref = oracle_solution(m, -1)
-    for budget in (10, 200):
-        got = run_plan(m, -1, round_launch=2, async_budget_us=budget)
-        assert_same(m, got, ref, f"async budget {budget} us")
-    got = run_plan(m, 60, round_launch=2, async_budget_us=50)
-    assert_same(m, got, oracle_solution(m, 60), "async budget 50 us, L=60")
+def test_graph_replays_across_propagations():
+    """Rounds replayed from captured HIP graphs: one plan propagated again and
+    again with other layer counts and other mazes of the same size (the graph
+    is captured again when its arguments change), every result against the
+    oracle, for the integer and the bit-sliced schedules."""
+    import paper_2004_00540_amd as omap
+    ms = [workloads.random_maze(700, 300, p, 3, 25, 6100 + k) for k, p in enumerate((0.3, 0.1, 0.38))]
+    for sched, T, C in ((ACTIVE, 16, 1), (ACTIVE, 12, 2), (BITS, 16, 0), (DENSE, 8, 4)):
+        with omap.Plan(to_dev(ms[0].occ), ms[0].sources, ms[0].targets, temporal_depth=T, lane_columns=C,
+                       schedule=sched, round_launch=omap.LAUNCH_GRAPH) as plan:
+            for k, L in enumerate((-1, 37, -1, 200, 5, -1)):
+                m = ms[k % len(ms)]
+                plan.load(to_dev(m.occ), m.sources, m.targets)
+                info = plan.propagate(L)
+                act = plan.activity().cpu().numpy()
+                ln, off, cells = (t.cpu().numpy() for t in plan.paths())
+                assert_same(m, (act, ln, off, cells, info), oracle_solution(m, L), f"graph sched={sched} T={T} L={L}")
