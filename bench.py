@@ -301,6 +301,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=25.0)
     ap.add_argument("--no-forms", action="store_true", help="leave the batched and serving forms out")
+    ap.add_argument("--no-tune", action="store_true", help="batched and serving forms without the autotuner")
     ap.add_argument("--serve-warmup", type=int, default=20)
     ap.add_argument("--serve-requests", type=int, default=500)
     ap.add_argument("--serve-plain", type=int, default=100, help="queries timed in the plain per-maze loop")
@@ -322,11 +323,13 @@ def main():
             torch.cuda.empty_cache()
             b = bench_batch(args)
             out["batch"] = {k: b[k] for k in ("value", "unit", "ms_per_step", "plain_loop_mazes_per_s",
-                                              "speedup_vs_plain_loop", "paths_per_s", "config")}
+                                              "speedup_vs_plain_loop", "paths_per_s", "config", "options",
+                                              "default_options_mazes_per_s")}
             torch.cuda.empty_cache()
             sv = bench_serve(args)
             out["serve"] = {k: sv[k] for k in ("capacity_mazes_per_s", "open_loop_mazes_per_s", "latency_ms",
-                                               "plain_loop_mazes_per_s", "capacity_vs_plain_loop", "config")}
+                                               "plain_loop_mazes_per_s", "capacity_vs_plain_loop", "config",
+                                               "options")}
     elif args.workload == "batch":
         from bench_forms import bench_batch
         out = bench_batch(args)

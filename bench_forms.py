@@ -47,9 +47,18 @@ def bench_batch(args):
     n_tgt = sum(len(m.targets) for m in mazes)
     opts = dict(temporal_depth=args.depth, tile_rows=args.tile_rows, schedule=args.schedule,
                 lane_columns=args.lane_columns, round_launch=args.launch)
+    items = [(occs[i], m.sources, m.targets) for i, m in enumerate(mazes)]
+    tuned = None
+    if not args.no_tune and not any(opts.values()):
+        # the tile shape and layers per visit for this workload, from the autotuner
+        t0 = time.perf_counter()
+        tuned = omap.tune(items, omap.USE_BATCH)
+        tuned["seconds"] = round(time.perf_counter() - t0, 2)
+        opts = tuned["options"]
+        _log(f"autotuner: {tuned}")
 
-    def batched():
-        with omap.Batch([(occs[i], m.sources, m.targets) for i, m in enumerate(mazes)], **opts) as b:
+    def batched(o=None):
+        with omap.Batch(items, **(opts if o is None else o)) as b:
             b.propagate(sync=False)
             out = b.paths()
         return out
@@ -71,7 +80,16 @@ def bench_batch(args):
         batched()
     torch.cuda.synchronize()
     t_batch = (time.perf_counter() - t0) / reps
-    with omap.Batch([(occs[i], m.sources, m.targets) for i, m in enumerate(mazes)], **opts) as b:
+    t_default = None
+    if tuned is not None:
+        batched({})
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            batched({})
+        torch.cuda.synchronize()
+        t_default = (time.perf_counter() - t0) / reps
+    with omap.Batch(items, **opts) as b:
         infos = b.propagate()
         b.profile(True)
         b.propagate(sync=False)
@@ -95,6 +113,9 @@ def bench_batch(args):
         "paths_per_s": round(n_tgt / t_batch, 1),
         "sweep_kernel": {"launches": prof["launches"], "ms_total": round(prof["ms"], 3),
                          "cell_updates": prof["cell_updates"]},
+        "options": omap.resolve_options(**opts) if tuned is None else tuned["options"],
+        "autotuner": tuned,
+        "default_options_mazes_per_s": round(n / t_default, 2) if t_default else None,
     }
 
 
@@ -124,6 +145,18 @@ def bench_serve(args):
     dev = torch.device("cuda:0")
     opts = dict(temporal_depth=args.depth, tile_rows=args.tile_rows, schedule=args.schedule,
                 lane_columns=args.lane_columns, round_launch=args.launch)
+    tuned = None
+    if not args.no_tune and not any(opts.values()):
+        # options for this query mix from the autotuner, on a sample of the stream
+        sample = seq[:24]
+        occ_s = [torch.from_numpy(q.occ).to(dev) for q in sample]
+        t0 = time.perf_counter()
+        tuned = omap.tune([(o, q.sources, q.targets) for o, q in zip(occ_s, sample)], omap.USE_ENGINE)
+        tuned["seconds"] = round(time.perf_counter() - t0, 2)
+        opts = tuned["options"]
+        _log(f"autotuner: {tuned}")
+        del occ_s
+        torch.cuda.empty_cache()
     free, _ = torch.cuda.mem_get_info()
     budget = int(min(args.serve_budget_gb * (1 << 30), 0.8 * free))
 
@@ -195,6 +228,8 @@ def bench_serve(args):
                        "mean": round(float(lat.mean()) * 1e3, 2)},
         "plain_loop_mazes_per_s": round(plain_rate, 2),
         "capacity_vs_plain_loop": round(capacity / plain_rate, 2),
+        "options": opts,
+        "autotuner": tuned,
     }
 
 

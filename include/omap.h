@@ -355,6 +355,37 @@ omap_status_t omap_engine_fetch_activity(omap_engine_t engine, int64_t query_id,
 omap_status_t omap_engine_destroy(omap_engine_t engine);
 
 /* ---------------------------------------------------------------------------
+ * Autotuner: the tile shape and the layers per visit for a workload
+ * ------------------------------------------------------------------------- */
+
+#define OMAP_USE_PLAN 0     /* one maze per plan (n_mazes = 1)                    */
+#define OMAP_USE_BATCH 1    /* many mazes advanced together                       */
+#define OMAP_USE_ENGINE 2   /* a serving engine (the sample stands for its mix)   */
+
+typedef struct omap_tune_result {
+    omap_options options;   /* the fastest candidate: pass it to the create call  */
+    int32_t candidates;     /* configurations timed (0 when read from the cache)  */
+    int32_t from_cache;     /* 1 = options read from the OMAP_TUNE_CACHE file     */
+    double best_ms;         /* propagation time of `options` on the sample        */
+    double default_ms;      /* propagation time of the defaults on the sample     */
+} omap_tune_result;
+
+/* Picks options for a workload like `mazes` (device occupancy, as for
+ * omap_batch_create): propagates the sample (run-time L) under the defaults
+ * and under each candidate schedule / layers per visit / columns per lane /
+ * tile rows, twice each, keeps the fastest, and checks that every candidate's
+ * activity maps and layer counts equal the defaults' bit for bit (any tile
+ * schedule reaches the same fixpoint; a difference fails the call with
+ * OMAP_ERR_HIP).  With the environment variable OMAP_TUNE_CACHE naming a
+ * file, choices are appended to it keyed by device, use, number of mazes and
+ * median maze size (powers of two), and a later call for the same key reads
+ * them back without timing anything.  Synchronous; needs device memory for
+ * two copies of the sample's activity maps.  Errors: INVALID_ARG, those of
+ * the create calls, OUT_OF_MEMORY, HIP. */
+omap_status_t omap_tune(const omap_maze_desc *mazes, int32_t n_mazes, int32_t use,
+                        omap_tune_result *result, void *stream);
+
+/* ---------------------------------------------------------------------------
  * Diagnostics
  * ------------------------------------------------------------------------- */
 

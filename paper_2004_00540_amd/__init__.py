@@ -118,6 +118,7 @@ def lib() -> ctypes.CDLL:
         "omap_profile_read": [P, i32, P, P, P],
         "omap_selftest": [P],
         "omap_resolve_options": [P, P],
+        "omap_tune": [P, i32, i32, P, P],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -153,11 +154,46 @@ def _stream(stream=None) -> int:
 
 
 LAUNCH_PER_ROUND, LAUNCH_GRAPH = 0, 1
+USE_PLAN, USE_BATCH, USE_ENGINE = 0, 1, 2
+
+
+class TuneResult(ctypes.Structure):
+    _fields_ = [("options", Options), ("candidates", ctypes.c_int32), ("from_cache", ctypes.c_int32),
+                ("best_ms", ctypes.c_double), ("default_ms", ctypes.c_double)]
 
 
 def _options(temporal_depth=0, tile_rows=0, schedule=SCHEDULE_DEFAULT, check_interval=0,
              lane_columns=0, round_launch=LAUNCH_PER_ROUND):
     return Options(temporal_depth, tile_rows, schedule, check_interval, lane_columns, round_launch)
+
+
+def _descs(mazes):
+    """MazeDesc array (and the host arrays it points into) for (occupancy,
+    sources, targets) triples."""
+    keep, descs = [], []
+    for occ, src, tgt in mazes:
+        occ = _device_u8(occ)
+        s = _rc(src)
+        t = _rc(tgt if tgt is not None else np.zeros((0, 2), np.int32))
+        keep += [occ, s, t]
+        descs.append(MazeDesc(int(occ.shape[0]), int(occ.shape[1]), occ.data_ptr(),
+                              s.ctypes.data, len(s), t.ctypes.data if len(t) else None, len(t)))
+    return (MazeDesc * len(descs))(*descs), keep
+
+
+def tune(mazes, use: int = USE_BATCH, stream=None) -> dict:
+    """omap_tune on (occupancy CUDA tensor, sources, targets) triples: the
+    fastest options for a workload like them (every candidate's maps checked
+    against the defaults'), read from OMAP_TUNE_CACHE when present.  Returns
+    {"options": keyword options for Plan / Batch / Engine, "candidates",
+    "from_cache", "best_ms", "default_ms"}."""
+    arr, keep = _descs(mazes)
+    res = TuneResult()
+    _check(lib().omap_tune(arr, len(arr), int(use), ctypes.byref(res), ctypes.c_void_p(_stream(stream))))
+    del keep
+    return {"options": {f: getattr(res.options, f) for f, _ in Options._fields_},
+            "candidates": res.candidates, "from_cache": res.from_cache,
+            "best_ms": res.best_ms, "default_ms": res.default_ms}
 
 
 def resolve_options(**options) -> dict:

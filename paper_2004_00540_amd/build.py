@@ -17,7 +17,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libomap.so")
-SOURCES = ["omap_kernels.hip", "omap_runtime.hip"]
+SOURCES = ["omap_kernels.hip", "omap_runtime.hip", "omap_tune.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 CLANG = os.environ.get("OMAP_LINKER", "/opt/rocm/lib/llvm/bin/clang++")
 ROCM_LIB = "/opt/rocm/lib"

@@ -168,3 +168,12 @@ hipError_t launch_clear_touched(const RoundArgs& a, int32_t tile_begin, int32_t 
 int sweep_max_waves_per_cu(int T, int C);
 
 }  // namespace omap
+
+#include "omap.h"
+
+namespace omap {
+
+// Records `message` as the thread's last error (omap_last_error) and returns st.
+omap_status_t report_error(omap_status_t st, const char* message);
+
+}  // namespace omap

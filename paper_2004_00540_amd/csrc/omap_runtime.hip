@@ -44,6 +44,8 @@ static omap_status_t fail(omap_status_t st, const char* fmt, ...) {
     return st;
 }
 
+omap_status_t report_error(omap_status_t st, const char* message) { return fail(st, "%s", message); }
+
 #define HIP_TRY(expr)                                                                   \
     do {                                                                                \
         hipError_t _e = (expr);                                                         \
