@@ -148,7 +148,7 @@ def bench_serve(args):
     tuned = None
     if not args.no_tune and not any(opts.values()):
         # options for this query mix from the autotuner, on a sample of the stream
-        sample = seq[:24]
+        sample = seq[:48]
         occ_s = [torch.from_numpy(q.occ).to(dev) for q in sample]
         t0 = time.perf_counter()
         tuned = omap.tune([(o, q.sources, q.targets) for o, q in zip(occ_s, sample)], omap.USE_ENGINE)
@@ -177,7 +177,9 @@ def bench_serve(args):
     plain_rate = n_plain / (time.perf_counter() - t0)
     _log(f"plain loop {plain_rate:.2f} mazes/s over {n_plain} queries")
 
-    def run(arrivals, rounds):
+    def run(arrivals, rounds, window=None):
+        # window: most queries submitted and not finished at once (None: the
+        # arrivals alone decide)
         eng = omap.Engine(budget, max_slots=args.serve_slots, **opts)
         done = {}
         ids = {}
@@ -186,18 +188,17 @@ def bench_serve(args):
         start = time.perf_counter()
         while len(done) < len(arrivals):
             now = time.perf_counter() - start
-            while k < len(arrivals) and arrivals[k] <= now:
+            while k < len(arrivals) and arrivals[k] <= now and (window is None or k - len(done) < window):
                 q = seq[k]
                 ids[eng.submit(q.occ, q.sources, q.targets)] = k
                 k += 1
             res, _ = eng.step(rounds=rounds)
             steps += 1
             now = time.perf_counter() - start
-            for qid, j in list(ids.items()):
-                if eng.poll(qid) in (omap.QUERY_DONE, omap.QUERY_FAILED):
-                    eng.fetch(qid)
-                    done[j] = now - arrivals[j]
-                    del ids[qid]
+            for qid in eng.completed():
+                eng.fetch(qid)
+                j = ids.pop(qid)
+                done[j] = now - arrivals[j]
             if res == 0 and not ids and k < len(arrivals):
                 time.sleep(max(0.0, arrivals[k] - (time.perf_counter() - start)))
         total = time.perf_counter() - start
@@ -205,8 +206,9 @@ def bench_serve(args):
         lat = np.array([done[j] for j in range(len(arrivals))])
         return total, lat, steps
 
-    # closed loop: everything queued at t = 0 -> capacity
-    t_closed, _, steps_closed = run(np.zeros(n_req), args.serve_rounds)
+    # closed loop: every query available at t = 0, kept queued two slots'
+    # worth deep -> capacity
+    t_closed, _, steps_closed = run(np.zeros(n_req), args.serve_rounds, window=2 * args.serve_slots)
     capacity = n_req / t_closed
     _log(f"engine capacity {capacity:.2f} mazes/s ({steps_closed} steps)")
     rate = 0.7 * capacity

@@ -281,12 +281,13 @@ omap_status_t omap_batch_destroy(omap_batch_t batch);
  *
  * The engine's host side does not wait for the device while there is device
  * work to enqueue: occupancy grids are copied to pinned memory at submit and
- * reach the device by DMA in stream order, convergence is read from counts
- * copied after each step (one step late), and a retirement runs in three
- * stream-ordered phases across steps (finalize and path lengths; walk and
- * copies; hand-over).  A step blocks only to stay at most two steps of
- * rounds ahead of the device, or, when nothing is left to advance, until the
- * retirement in flight completes.
+ * reach the device by DMA on a second stream while the rounds run (a query
+ * is packed and started at the step after its upload completed), convergence
+ * is read from counts copied after each step (one step late), and a
+ * retirement runs in three phases across steps (finalize and path lengths on
+ * the rounds' stream; walk and copies on the second stream; hand-over).  A
+ * step blocks only to stay at most two steps of rounds ahead of the device,
+ * or, when nothing is left to advance, until the work in flight completes.
  * ------------------------------------------------------------------------- */
 typedef struct omap_engine_s *omap_engine_t;
 
@@ -332,6 +333,12 @@ omap_status_t omap_engine_submit_ex(omap_engine_t engine, int32_t height, int32_
 omap_status_t omap_engine_step(omap_engine_t engine, int32_t rounds, int32_t *n_resident,
                                int64_t *n_done_total);
 
+/* Ids of the queries that became DONE or FAILED since the previous call, in
+ * the order they did: up to `capacity` of them go to ids_host (host) and
+ * *n_ids receives their number; the others stay for the next call.  Host
+ * only.  Errors: INVALID_ARG. */
+omap_status_t omap_engine_completed(omap_engine_t engine, int64_t *ids_host, int32_t capacity, int32_t *n_ids);
+
 /* State of a query: OMAP_QUERY_*.  NOT_FOUND for unknown / already fetched. */
 omap_status_t omap_engine_poll(omap_engine_t engine, int64_t query_id, int32_t *state);
 
@@ -373,7 +380,9 @@ typedef struct omap_tune_result {
 /* Picks options for a workload like `mazes` (device occupancy, as for
  * omap_batch_create): propagates the sample (run-time L) under the defaults
  * and under each candidate schedule / layers per visit / columns per lane /
- * tile rows, twice each, keeps the fastest, and checks that every candidate's
+ * tile rows, twice each (OMAP_USE_ENGINE: the sample propagated as one
+ * batch stands for the engine's mix), keeps the fastest, and checks that
+ * every candidate's
  * activity maps and layer counts equal the defaults' bit for bit (any tile
  * schedule reaches the same fixpoint; a difference fails the call with
  * OMAP_ERR_HIP).  With the environment variable OMAP_TUNE_CACHE naming a

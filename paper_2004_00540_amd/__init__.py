@@ -112,6 +112,7 @@ def lib() -> ctypes.CDLL:
         "omap_engine_fetch_activity": [P, i64, P, i64],
         "omap_engine_step": [P, i32, P, P],
         "omap_engine_poll": [P, i64, P],
+        "omap_engine_completed": [P, P, i32, P],
         "omap_engine_fetch": [P, i64, P, P, P, i64, P, P],
         "omap_engine_destroy": [P],
         "omap_profile_enable": [P, i32, i32],
@@ -456,6 +457,18 @@ class Engine:
         res, done = ctypes.c_int32(), ctypes.c_int64()
         _check(lib().omap_engine_step(self.handle, int(rounds), ctypes.byref(res), ctypes.byref(done)))
         return res.value, done.value
+
+    def completed(self, capacity: int = 4096) -> list:
+        """Ids of the queries that finished (DONE or FAILED) since the last call."""
+        out = []
+        buf = np.empty(capacity, np.int64)
+        n = ctypes.c_int32()
+        while True:
+            _check(lib().omap_engine_completed(self.handle, buf.ctypes.data_as(ctypes.c_void_p), capacity,
+                                               ctypes.byref(n)))
+            out += buf[: n.value].tolist()
+            if n.value < capacity:
+                return out
 
     def poll(self, qid: int) -> int:
         st = ctypes.c_int32()

@@ -1522,6 +1522,21 @@ struct omap_engine_s {
     omap::ArenaMemory mem;
     omap::Solver solver;
     omap::PinnedPool occ_pool;       // pinned copies of submitted occupancy grids
+    // Second stream (default priority) for what need not wait for the rounds:
+    // occupancy uploads of the next admissions and the walks and copies of a
+    // retirement.  The rounds stay on the solver's stream.
+    hipStream_t xfer = nullptr;
+    struct Staged {
+        int64_t id;
+        void* occ_dev;               // occupancy on the device (arena), uploaded on xfer
+        hipEvent_t ev;               // the upload's completion
+        int64_t reserve;             // bytes reserved for the maze's buffers
+    };
+    std::deque<Staged> staged;       // uploaded or uploading, admitted at a later step
+    int64_t reserved = 0;
+    std::deque<std::pair<void*, hipEvent_t>> dev_release;   // arena blocks freed once the event completes
+    std::vector<hipEvent_t> ev_spare;
+    std::deque<int64_t> completed;   // DONE / FAILED ids not yet handed out by omap_engine_completed
     int64_t budget = 0;
     int32_t max_slots = 0;
     int64_t next_id = 1;
@@ -1536,6 +1551,11 @@ struct omap_engine_s {
 
     ~omap_engine_s() {
         (void)hipStreamSynchronize(solver.stream);
+        if (xfer) (void)hipStreamSynchronize(xfer);
+        for (auto& st : staged) (void)hipEventDestroy(st.ev);
+        for (auto& r : dev_release) (void)hipEventDestroy(r.second);
+        for (hipEvent_t ev : ev_spare) (void)hipEventDestroy(ev);
+        if (xfer) (void)hipStreamDestroy(xfer);
         for (auto& sn : snap) {
             if (sn.ev) (void)hipEventDestroy(sn.ev);
             if (sn.counts) (void)hipHostFree(sn.counts);
@@ -1547,7 +1567,15 @@ struct omap_engine_s {
         if (ret.d_act) (void)hipFree(ret.d_act);
     }
     int32_t resident() const {
-        return (int32_t)(running.size() + converged.size() + ret.ids.size());
+        return (int32_t)(staged.size() + running.size() + converged.size() + ret.ids.size());
+    }
+    hipError_t event(hipEvent_t* ev) {
+        if (!ev_spare.empty()) {
+            *ev = ev_spare.back();
+            ev_spare.pop_back();
+            return hipSuccess;
+        }
+        return hipEventCreateWithFlags(ev, hipEventDisableTiming);
     }
 };
 
@@ -1570,76 +1598,130 @@ static void query_release_occ(omap_engine_s* e, Query& q) {
     q.occ.shrink_to_fit();
 }
 
-// Admits waiting queries in arrival order while a slot and device memory are
-// free: sources checked on the host copy, occupancy copied in and packed,
-// then one start for all of them.  Nothing here waits for the device.
+static void query_fail(omap_engine_s* e, Query& q, const std::string& msg) {
+    q.state = OMAP_QUERY_FAILED;
+    q.error = msg;
+    q.slot = -1;
+    query_release_occ(e, q);
+    ++e->done_total;
+    e->completed.push_back(q.id);
+}
+
+// Arena blocks whose last reader has completed go back to the arena.
+static void engine_reap(omap_engine_s* e) {
+    while (!e->dev_release.empty()) {
+        const hipError_t r = hipEventQuery(e->dev_release.front().second);
+        if (r == hipErrorNotReady) {
+            (void)hipGetLastError();
+            break;
+        }
+        e->mem.release(e->dev_release.front().first);
+        e->ev_spare.push_back(e->dev_release.front().second);
+        e->dev_release.pop_front();
+    }
+    e->occ_pool.reap(false);
+}
+
+// Admission in two steps so that no upload holds up the rounds.  Staged
+// queries whose occupancy has arrived are packed and started together on the
+// solver's stream; then waiting queries that fit (a slot, and device memory
+// for the occupancy plus a reservation for the maze's buffers) are staged:
+// sources checked on the host copy, occupancy copied to the device on the
+// transfer stream.  Nothing here waits for the device.
 static omap_status_t engine_admit(omap_engine_s* e) {
     Solver& sv = e->solver;
+    engine_reap(e);
     std::vector<int32_t> started;
     std::vector<int64_t> Ls, ids;
-    e->occ_pool.reap(false);
-    while (!e->waiting.empty() && e->resident() + (int32_t)started.size() < e->max_slots) {
+    while (!e->staged.empty()) {
+        omap_engine_s::Staged& g = e->staged.front();
+        const hipError_t r = hipEventQuery(g.ev);
+        if (r == hipErrorNotReady) {
+            (void)hipGetLastError();
+            break;   // the uploads complete in order
+        }
+        Query& q = e->queries[g.id];
+        e->reserved -= g.reserve;
+        int32_t slot = -1;
+        omap_status_t st = r == hipSuccess
+                               ? sv.add(q.H, q.W, static_cast<uint8_t*>(g.occ_dev), q.src.data(),
+                                        (int32_t)(q.src.size() / 2), q.tgt.empty() ? nullptr : q.tgt.data(),
+                                        (int32_t)(q.tgt.size() / 2), &slot, /*defer=*/true, /*check_sources=*/false)
+                               : fail(OMAP_ERR_HIP, "occupancy upload: %s", hipGetErrorString(r));
+        if (st == OMAP_ERR_OUT_OF_MEMORY && e->resident() > (int32_t)e->staged.size()) {
+            e->reserved += g.reserve;   // fragmented arena: retry when something retires
+            break;
+        }
+        // the staging block is read by the packing kernel: freed once that has run
+        hipEvent_t done = g.ev;
+        HIP_TRY(hipEventRecord(done, sv.stream));
+        e->dev_release.push_back({g.occ_dev, done});
+        const int64_t id = g.id;
+        e->staged.pop_front();
+        if (st != OMAP_OK) {
+            query_fail(e, e->queries[id], g_last_error);
+            continue;
+        }
+        e->queries[id].slot = slot;
+        started.push_back(slot);
+        Ls.push_back(e->queries[id].L);
+        ids.push_back(id);
+    }
+    if (!started.empty()) {
+        omap_status_t st = sv.start_many(started, Ls.data());
+        if (st != OMAP_OK) {
+            const std::string msg = g_last_error;
+            for (size_t i = 0; i < ids.size(); ++i) {
+                sv.remove(started[i]);
+                query_fail(e, e->queries[ids[i]], msg);
+            }
+            g_last_error = msg;
+        } else {
+            for (int64_t id : ids) {
+                e->queries[id].state = OMAP_QUERY_RUNNING;
+                e->running.push_back(id);
+            }
+        }
+    }
+    while (!e->waiting.empty() && e->resident() < e->max_slots) {
         Query& q = e->queries[e->waiting.front()];
-        if ((int64_t)e->mem.in_use() + q.bytes > (int64_t)e->mem.size()) break;   // wait for memory
+        if ((int64_t)e->mem.in_use() + e->reserved + q.bytes > (int64_t)e->mem.size()) break;   // wait for memory
         const uint8_t* occ_host = q.occ_pinned ? q.occ_pinned : q.occ.data();
         int32_t bad = 0;
         for (size_t j = 0; j < q.src.size(); j += 2)
             bad += occ_host[(int64_t)q.src[j] * q.W + q.src[j + 1]] != 0;
         if (bad) {
             e->waiting.pop_front();
-            q.state = OMAP_QUERY_FAILED;
-            q.error = std::string(omap_status_string(OMAP_ERR_SOURCE_ON_OBSTACLE)) + ": " + std::to_string(bad) +
-                      " source(s) lie on obstacles";
-            query_release_occ(e, q);
-            ++e->done_total;
+            query_fail(e, q, std::string(omap_status_string(OMAP_ERR_SOURCE_ON_OBSTACLE)) + ": " +
+                                 std::to_string(bad) + " source(s) lie on obstacles");
             continue;
         }
         const size_t n_occ = (size_t)q.H * q.W;
         void* occ_dev = e->mem.alloc(n_occ);
         if (!occ_dev) break;
+        omap_engine_s::Staged g{q.id, occ_dev, nullptr, std::max<int64_t>(0, q.bytes - (int64_t)n_occ)};
+        hipError_t r = e->event(&g.ev);
+        if (r == hipSuccess) {
+            if (q.occ_pinned) {
+                r = hipMemcpyAsync(occ_dev, q.occ_pinned, n_occ, hipMemcpyHostToDevice, e->xfer);
+                if (r == hipSuccess) r = e->occ_pool.release_after(q.occ_pinned, e->xfer);
+                if (r == hipSuccess) q.occ_pinned = nullptr;
+            } else {
+                // pageable: the copy returns once the data has left q.occ
+                r = hipMemcpyAsync(occ_dev, q.occ.data(), n_occ, hipMemcpyHostToDevice, e->xfer);
+                if (r == hipSuccess) r = hipStreamSynchronize(e->xfer);
+            }
+        }
+        if (r == hipSuccess) r = hipEventRecord(g.ev, e->xfer);
+        if (r != hipSuccess) {
+            e->mem.release(occ_dev);
+            if (g.ev) e->ev_spare.push_back(g.ev);
+            return fail(OMAP_ERR_HIP, "occupancy upload: %s", hipGetErrorString(r));
+        }
         e->waiting.pop_front();
-        if (q.occ_pinned) {
-            HIP_TRY(hipMemcpyAsync(occ_dev, q.occ_pinned, n_occ, hipMemcpyHostToDevice, sv.stream));
-            HIP_TRY(e->occ_pool.release_after(q.occ_pinned, sv.stream));
-            q.occ_pinned = nullptr;
-        } else {
-            OK_TRY(sv.upload(occ_dev, q.occ.data(), n_occ));
-        }
-        int32_t slot = -1;
-        omap_status_t st = sv.add(q.H, q.W, static_cast<uint8_t*>(occ_dev), q.src.data(),
-                                  (int32_t)(q.src.size() / 2), q.tgt.empty() ? nullptr : q.tgt.data(),
-                                  (int32_t)(q.tgt.size() / 2), &slot, /*defer=*/true, /*check_sources=*/false);
-        e->mem.release(occ_dev);   // read by the packing kernel before any later reuse (stream order)
         query_release_occ(e, q);
-        if (st != OMAP_OK) {
-            q.state = OMAP_QUERY_FAILED;
-            q.error = g_last_error;
-            ++e->done_total;
-            continue;
-        }
-        q.slot = slot;
-        started.push_back(slot);
-        Ls.push_back(q.L);
-        ids.push_back(q.id);
-    }
-    if (started.empty()) return OMAP_OK;
-    omap_status_t st = sv.start_many(started, Ls.data());
-    if (st != OMAP_OK) {
-        const std::string msg = g_last_error;
-        for (size_t i = 0; i < ids.size(); ++i) {
-            Query& q = e->queries[ids[i]];
-            sv.remove(started[i]);
-            q.slot = -1;
-            q.state = OMAP_QUERY_FAILED;
-            q.error = msg;
-            ++e->done_total;
-        }
-        g_last_error = msg;
-        return OMAP_OK;
-    }
-    for (int64_t id : ids) {
-        e->queries[id].state = OMAP_QUERY_RUNNING;
-        e->running.push_back(id);
+        e->reserved += g.reserve;
+        e->staged.push_back(g);
     }
     return OMAP_OK;
 }
@@ -1728,7 +1810,9 @@ static omap_status_t retire_begin(omap_engine_s* e) {
 }
 
 // Phase 2: with the path sizes known, walk every path and copy paths,
-// visit counters and kept activity maps to pinned host memory.
+// visit counters and kept activity maps to pinned host memory, all on the
+// transfer stream (after phase 1), so that the rounds of the mazes still
+// running go on meanwhile: the retiring mazes' buffers are no longer written.
 static omap_status_t retire_paths(omap_engine_s* e) {
     Solver& sv = e->solver;
     Retirement& R = e->ret;
@@ -1743,9 +1827,11 @@ static omap_status_t retire_paths(omap_engine_s* e) {
     const int32_t* d_trc = reinterpret_cast<const int32_t*>(base + up(4 * (n + 1)));
     const int32_t* d_len = reinterpret_cast<const int32_t*>(base + up(4 * (n + 1)) + up(8 * (n + 1)));
     const int64_t* d_off = reinterpret_cast<const int64_t*>(base + 2 * up(4 * (n + 1)) + up(8 * (n + 1)));
+    hipStream_t xs = e->xfer;
+    HIP_TRY(hipStreamWaitEvent(xs, R.ev, 0));
     if ((size_t)R.total > R.cells_cap) {
         const size_t want = std::max<size_t>((size_t)R.total, R.cells_cap * 2);
-        HIP_TRY(hipStreamSynchronize(sv.stream));
+        HIP_TRY(hipStreamSynchronize(xs));
         if (R.d_cells) (void)hipFree(R.d_cells);
         R.d_cells = nullptr;
         R.cells_cap = 0;
@@ -1753,7 +1839,7 @@ static omap_status_t retire_paths(omap_engine_s* e) {
         R.cells_cap = want;
     }
     if (n > 0 && R.total > 0)
-        HIP_TRY(launch_walk(sv.d_mazes, d_tslot, d_trc, R.n, sv.vparity(), d_len, d_off, R.d_cells, sv.stream));
+        HIP_TRY(launch_walk(sv.d_mazes, d_tslot, d_trc, R.n, sv.vparity(), d_len, d_off, R.d_cells, xs));
     // host layout: last_round | visits | cell visits | cells | activity maps
     const size_t b_lr = up(4 * (size_t)sv.cap_slots), b_v = up(8 * (size_t)sv.cap_slots * kSpread);
     size_t act_bytes = 0;
@@ -1766,17 +1852,18 @@ static omap_status_t retire_paths(omap_engine_s* e) {
         act_bytes += up(4 * (size_t)q.H * q.W);
     }
     OK_TRY(R.h_out.reserve(act_at + act_bytes));
-    HIP_TRY(hipMemcpyAsync(R.h_out.p, sv.d_last_round, 4 * (size_t)sv.cap_slots, hipMemcpyDeviceToHost, sv.stream));
+    // (the counters of the retiring slots no longer change; the other
+    // slots' entries of this snapshot are not used)
+    HIP_TRY(hipMemcpyAsync(R.h_out.p, sv.d_last_round, 4 * (size_t)sv.cap_slots, hipMemcpyDeviceToHost, xs));
     HIP_TRY(hipMemcpyAsync(R.h_out.p + b_lr, sv.d_visits, 8 * (size_t)sv.cap_slots * kSpread, hipMemcpyDeviceToHost,
-                           sv.stream));
+                           xs));
     HIP_TRY(hipMemcpyAsync(R.h_out.p + b_lr + b_v, sv.d_cell_visits, 8 * (size_t)sv.cap_slots * kSpread,
-                           hipMemcpyDeviceToHost, sv.stream));
+                           hipMemcpyDeviceToHost, xs));
     if (R.total > 0)
-        HIP_TRY(hipMemcpyAsync(R.h_out.p + cells_at, R.d_cells, 4 * (size_t)R.total, hipMemcpyDeviceToHost,
-                               sv.stream));
+        HIP_TRY(hipMemcpyAsync(R.h_out.p + cells_at, R.d_cells, 4 * (size_t)R.total, hipMemcpyDeviceToHost, xs));
     if (act_bytes > 0) {
         if (act_bytes > R.act_cap) {
-            HIP_TRY(hipStreamSynchronize(sv.stream));
+            HIP_TRY(hipStreamSynchronize(xs));
             if (R.d_act) (void)hipFree(R.d_act);
             R.d_act = nullptr;
             R.act_cap = 0;
@@ -1789,12 +1876,11 @@ static omap_status_t retire_paths(omap_engine_s* e) {
             const Slot& s = sv.slots[q.slot];
             int32_t* d = reinterpret_cast<int32_t*>(reinterpret_cast<char*>(R.d_act) + (R.act_off[i] - act_at));
             HIP_TRY(launch_activity(sv.d_mazes, q.slot, q.H, q.W, sv.vparity(), (int32_t)((int64_t)s.K - s.layers - 1),
-                                    d, q.W, sv.stream));
-            HIP_TRY(hipMemcpyAsync(R.h_out.p + R.act_off[i], d, 4 * (size_t)q.H * q.W, hipMemcpyDeviceToHost,
-                                   sv.stream));
+                                    d, q.W, xs));
+            HIP_TRY(hipMemcpyAsync(R.h_out.p + R.act_off[i], d, 4 * (size_t)q.H * q.W, hipMemcpyDeviceToHost, xs));
         }
     }
-    HIP_TRY(hipEventRecord(R.ev, sv.stream));
+    HIP_TRY(hipEventRecord(R.ev, xs));
     R.phase = 2;
     return OMAP_OK;
 }
@@ -1834,6 +1920,7 @@ static omap_status_t retire_finish(omap_engine_s* e) {
         q.slot = -1;
         q.state = OMAP_QUERY_DONE;
         ++e->done_total;
+        e->completed.push_back(q.id);
     }
     R.ids.clear();
     R.slots.clear();
@@ -2248,8 +2335,8 @@ omap_status_t omap_engine_create(omap_engine_t* out, int64_t memory_budget_bytes
     std::unique_ptr<omap_engine_s> e(new omap_engine_s());
     if (!e->mem.init((size_t)memory_budget_bytes))
         return fail(OMAP_ERR_OUT_OF_MEMORY, "engine budget of %lld bytes", (long long)memory_budget_bytes);
-    // pinned copies of queued occupancy grids: a quarter of the budget, 16 MiB .. 1 GiB
-    const int64_t pool = std::min<int64_t>(std::max<int64_t>(memory_budget_bytes / 4, 16 << 20), int64_t(1) << 30);
+    // pinned copies of queued occupancy grids: a quarter of the budget, 16 MiB .. 4 GiB
+    const int64_t pool = std::min<int64_t>(std::max<int64_t>(memory_budget_bytes / 4, 16 << 20), int64_t(4) << 30);
     if (!e->occ_pool.init((size_t)pool)) return fail(OMAP_ERR_OUT_OF_MEMORY, "pinned staging of %lld bytes", (long long)pool);
     e->budget = memory_budget_bytes;
     e->max_slots = max_slots;
@@ -2259,6 +2346,7 @@ omap_status_t omap_engine_create(omap_engine_t* out, int64_t memory_budget_bytes
     if (cap_tiles > (int64_t(1) << 28)) cap_tiles = int64_t(1) << 28;
     OK_TRY(e->solver.init(static_cast<hipStream_t>(stream), o, &e->mem, max_slots, (int32_t)cap_tiles,
                           size_t(16) << 20));
+    HIP_TRY(hipStreamCreateWithFlags(&e->xfer, hipStreamNonBlocking));
     *out = e.release();
     return OMAP_OK;
     API_GUARD_END
@@ -2343,10 +2431,25 @@ omap_status_t omap_engine_step(omap_engine_t engine, int32_t rounds, int32_t* n_
             }
         }
         OK_TRY(engine_progress(e, true));
+        if (!e->staged.empty()) HIP_TRY(hipEventSynchronize(e->staged.front().ev));
         OK_TRY(engine_admit(e));
     }
     if (n_resident) *n_resident = e->resident();
     if (n_done_total) *n_done_total = e->done_total;
+    return OMAP_OK;
+    API_GUARD_END
+}
+
+omap_status_t omap_engine_completed(omap_engine_t engine, int64_t* ids_host, int32_t capacity, int32_t* n_ids) {
+    API_GUARD_BEGIN
+    if (!engine || !n_ids || capacity < 0 || (capacity > 0 && !ids_host))
+        return fail(OMAP_ERR_INVALID_ARG, "engine, n_ids and ids_host (capacity > 0) are required");
+    int32_t n = 0;
+    while (n < capacity && !engine->completed.empty()) {
+        ids_host[n++] = engine->completed.front();
+        engine->completed.pop_front();
+    }
+    *n_ids = n;
     return OMAP_OK;
     API_GUARD_END
 }

@@ -129,6 +129,37 @@ def test_engine_results_alone_equal_mixed():
         assert r.info["layers"] == info["layers"] and r.info["reached_cells"] == info["reached_cells"], i
 
 
+def test_engine_completed_ids():
+    """omap_engine_completed hands out every finished query once, failed ones
+    included, in the order they finished."""
+    import paper_2004_00540_amd as omap
+    ms = _batch_mazes(9, 404, hmax=200)
+    bad = ms[4].occ.copy()
+    bad[ms[4].sources[0, 0], ms[4].sources[0, 1]] = 1
+    with omap.Engine(128 << 20, max_slots=3) as eng:
+        ids = [eng.submit(bad if i == 4 else m.occ, m.sources, m.targets) for i, m in enumerate(ms)]
+        seen = []
+        n = 0
+        while len(seen) < len(ms):
+            eng.step(rounds=2)
+            got = eng.completed()
+            for q in got:
+                assert eng.poll(q) in (omap.QUERY_DONE, omap.QUERY_FAILED)
+            seen += got
+            n += 1
+            assert n < 100000
+        assert sorted(seen) == sorted(ids) and len(set(seen)) == len(seen)
+        assert eng.completed() == []
+        assert eng.poll(ids[4]) == omap.QUERY_FAILED
+        for i, q in enumerate(ids):
+            if i == 4:
+                with pytest.raises(omap.OmapError):
+                    eng.fetch(q)
+            else:
+                r = eng.fetch(q)
+                assert r.info["layers"] == run_plan(ms[i], -1)[4]["layers"], i
+
+
 def test_engine_memory_admission_and_errors():
     import paper_2004_00540_amd as omap
     big = workloads.random_maze(1500, 1500, 0.3, 1, 5, 5)
