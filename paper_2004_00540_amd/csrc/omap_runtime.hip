@@ -1462,6 +1462,8 @@ struct Query {
     std::vector<int32_t> len;
     std::vector<int64_t> off;
     std::vector<int32_t> cells;
+    int32_t* cells_pinned = nullptr; // the path cells in the engine's pinned result pool (else in `cells`)
+    int64_t n_cells = 0;
     std::vector<int32_t> activity;   // kept activity map (H x W) with OMAP_QUERY_KEEP_ACTIVITY
     omap_propagate_info info{};
 };
@@ -1510,6 +1512,7 @@ struct Retirement {
     PinnedBuffer h_lo;           // lengths, offsets
     PinnedBuffer h_out;          // counters, cells, kept activity maps
     std::vector<int64_t> act_off;   // per retiring query: byte offset of its map in h_out (-1 = none)
+    std::vector<void*> cells_block; // per retiring query: its cells' block of the result pool (or null)
     int32_t* d_cells = nullptr;  // grow-only device buffers
     size_t cells_cap = 0;
     int32_t* d_act = nullptr;
@@ -1522,6 +1525,7 @@ struct omap_engine_s {
     omap::ArenaMemory mem;
     omap::Solver solver;
     omap::PinnedPool occ_pool;       // pinned copies of submitted occupancy grids
+    omap::PinnedPool res_pool;       // pinned path cells of finished queries until fetched
     // Second stream (default priority) for what need not wait for the rounds:
     // occupancy uploads of the next admissions and the walks and copies of a
     // retirement.  The rounds stay on the solver's stream.
@@ -1859,8 +1863,20 @@ static omap_status_t retire_paths(omap_engine_s* e) {
                            xs));
     HIP_TRY(hipMemcpyAsync(R.h_out.p + b_lr + b_v, sv.d_cell_visits, 8 * (size_t)sv.cap_slots * kSpread,
                            hipMemcpyDeviceToHost, xs));
-    if (R.total > 0)
-        HIP_TRY(hipMemcpyAsync(R.h_out.p + cells_at, R.d_cells, 4 * (size_t)R.total, hipMemcpyDeviceToHost, xs));
+    // each query's cells straight into a block of the result pool that
+    // omap_engine_fetch copies out and frees (else into h_out)
+    R.cells_block.assign(R.ids.size(), nullptr);
+    int64_t t0 = 0;
+    for (size_t i = 0; i < R.ids.size(); ++i) {
+        const int64_t nt = (int64_t)(e->queries[R.ids[i]].tgt.size() / 2);
+        const int64_t a = h_off[t0], b = h_off[t0 + nt];
+        t0 += nt;
+        if (b <= a) continue;
+        void* blk = e->res_pool.alloc(4 * (size_t)(b - a));
+        R.cells_block[i] = blk;
+        HIP_TRY(hipMemcpyAsync(blk ? blk : R.h_out.p + cells_at + 4 * a, R.d_cells + a, 4 * (size_t)(b - a),
+                               hipMemcpyDeviceToHost, xs));
+    }
     if (act_bytes > 0) {
         if (act_bytes > R.act_cap) {
             HIP_TRY(hipStreamSynchronize(xs));
@@ -1909,7 +1925,9 @@ static omap_status_t retire_finish(omap_engine_s* e) {
         q.len.assign(h_len + t0, h_len + t0 + nt);
         q.off.resize((size_t)nt + 1);
         for (int64_t j = 0; j <= nt; ++j) q.off[j] = h_off[t0 + j] - h_off[t0];
-        q.cells.assign(h_cells + h_off[t0], h_cells + h_off[t0 + nt]);
+        q.n_cells = h_off[t0 + nt] - h_off[t0];
+        if (R.cells_block[i]) q.cells_pinned = static_cast<int32_t*>(R.cells_block[i]);
+        else q.cells.assign(h_cells + h_off[t0], h_cells + h_off[t0 + nt]);
         if (R.act_off[i] >= 0) {
             const int32_t* a = reinterpret_cast<const int32_t*>(R.h_out.p + R.act_off[i]);
             q.activity.assign(a, a + (size_t)q.H * q.W);
@@ -2338,6 +2356,7 @@ omap_status_t omap_engine_create(omap_engine_t* out, int64_t memory_budget_bytes
     // pinned copies of queued occupancy grids: a quarter of the budget, 16 MiB .. 4 GiB
     const int64_t pool = std::min<int64_t>(std::max<int64_t>(memory_budget_bytes / 4, 16 << 20), int64_t(4) << 30);
     if (!e->occ_pool.init((size_t)pool)) return fail(OMAP_ERR_OUT_OF_MEMORY, "pinned staging of %lld bytes", (long long)pool);
+    if (!e->res_pool.init((size_t)pool)) return fail(OMAP_ERR_OUT_OF_MEMORY, "pinned results of %lld bytes", (long long)pool);
     e->budget = memory_budget_bytes;
     e->max_slots = max_slots;
     // tile ids: enough for the whole budget filled with the smallest mazes
@@ -2506,8 +2525,9 @@ omap_status_t omap_engine_fetch(omap_engine_t engine, int64_t query_id, int32_t*
     if ((nt > 0 && !len_host) || !offsets_host) return fail(OMAP_ERR_INVALID_ARG, "len/offsets pointer is NULL");
     if (nt) std::memcpy(len_host, q.len.data(), nt * sizeof(int32_t));
     std::memcpy(offsets_host, q.off.data(), (nt + 1) * sizeof(int64_t));
-    if (total) std::memcpy(cells_host, q.cells.data(), total * sizeof(int32_t));
+    if (total) std::memcpy(cells_host, q.cells_pinned ? q.cells_pinned : q.cells.data(), total * sizeof(int32_t));
     if (info_host) *info_host = q.info;
+    if (q.cells_pinned) engine->res_pool.release_now(q.cells_pinned);
     engine->queries.erase(it);
     return OMAP_OK;
     API_GUARD_END
