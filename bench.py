@@ -153,6 +153,79 @@ def measured_traffic(workload: str, options: dict):
     return t.get("bytes_per_launch")
 
 
+def _csv_rows(directory: str, suffix: str):
+    import csv
+    import glob
+    rows = []
+    for path in sorted(glob.glob(os.path.join(directory, "**", "*" + suffix), recursive=True)):
+        with open(path, newline="") as f:
+            rows += list(csv.DictReader(f))
+    return rows
+
+
+def _counter_per_dispatch(directory: str, counter: str, kernel_part: str):
+    """Mean value of a rocprofv3 --pmc counter over the dispatches of the
+    kernels whose name contains kernel_part (counter_collection.csv)."""
+    vals = {}
+    for r in _csv_rows(directory, "counter_collection.csv"):
+        name = r.get("Kernel_Name", "")
+        if kernel_part not in name or r.get("Counter_Name") != counter:
+            continue
+        key = r.get("Dispatch_Id") or r.get("Correlation_Id")
+        vals[key] = vals.get(key, 0.0) + float(r["Counter_Value"])
+    if not vals:
+        raise SystemExit(f"no {counter} rows for {kernel_prefix} under {directory}")
+    return sum(vals.values()) / len(vals), len(vals)
+
+
+def summarize_counters(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, out_path, commands):
+    """profiles/k_sweep_c3_traffic.json from four rocprofv3 --pmc runs: the
+    sweep's FETCH_SIZE and WRITE_SIZE (KiB per dispatch), each scaled by what
+    the counter reads for a plain pass of known size (bench.py --workload
+    copy: 1 GiB read + 1 GiB written per launch)."""
+    import paper_2004_00540_amd as omap
+    kern = "omap::k_sweep<"
+    f_kib, n = _counter_per_dispatch(fetch_dir, "FETCH_SIZE", kern)
+    w_kib, _ = _counter_per_dispatch(write_dir, "WRITE_SIZE", kern)
+    cf_kib, _ = _counter_per_dispatch(copy_fetch_dir, "FETCH_SIZE", "neg_kernel")
+    cw_kib, _ = _counter_per_dispatch(copy_write_dir, "WRITE_SIZE", "neg_kernel")
+    gib_kib = float(1 << 20)
+    f_scale, w_scale = gib_kib / cf_kib, gib_kib / cw_kib
+    fetch = f_kib * 1024 * f_scale
+    write = w_kib * 1024 * w_scale
+    out = {
+        "kernel": "omap::k_sweep<16, 1> (per-round launch)",
+        "workload": "config3_23170x23170_rect_overlay",
+        "options": omap.resolve_options(),
+        "kernel_source_sha256": kernel_source_hash(),
+        "kernel_sources": list(KERNEL_SOURCES),
+        "dispatches_counted": n,
+        "calibration": {"kernel": "torch neg over 1 GiB int32 (1 GiB read + 1 GiB written per launch)",
+                        "fetch_size_kib_raw": round(cf_kib, 1), "write_size_kib_raw": round(cw_kib, 1),
+                        "fetch_scale": round(f_scale, 4), "write_scale": round(w_scale, 4)},
+        "fetch_kib_raw_per_launch": round(f_kib, 1), "write_kib_raw_per_launch": round(w_kib, 1),
+        "fetch_bytes_per_launch": round(fetch), "write_bytes_per_launch": round(write),
+        "bytes_per_launch": round(fetch + write),
+        "commands": commands,
+    }
+    with open(out_path, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out))
+
+
+def summarize_trace(directory: str, top: int = 14):
+    """Markdown table of a rocprofv3 --kernel-trace --stats run (kernel_stats.csv)."""
+    rows = _csv_rows(directory, "kernel_stats.csv")
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    lines = ["| kernel | calls | total ms | avg us | min us | max us | % |", "|---|---|---|---|---|---|---|"]
+    for r in rows[:top]:
+        name = r["Name"] if len(r["Name"]) <= 70 else r["Name"][:67] + "..."
+        lines.append(f"| `{name}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.3f} | "
+                     f"{float(r['AverageNs']) / 1e3:.2f} | {float(r['MinNs']) / 1e3:.2f} | "
+                     f"{float(r['MaxNs']) / 1e3:.2f} | {float(r['Percentage']):.2f} |")
+    print("\n".join(lines))
+
+
 def copy_probe(args):
     """A plain elementwise pass over 1 GiB (torch's negation kernel: 1 GiB read,
     1 GiB written per launch), run under the same hardware counters as the
@@ -302,13 +375,25 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=25.0)
     ap.add_argument("--no-forms", action="store_true", help="leave the batched and serving forms out")
     ap.add_argument("--no-tune", action="store_true", help="batched and serving forms without the autotuner")
+    ap.add_argument("--no-plain-loop", action="store_true", help="batched form without its plain-loop baseline")
     ap.add_argument("--serve-warmup", type=int, default=20)
     ap.add_argument("--serve-requests", type=int, default=500)
     ap.add_argument("--serve-plain", type=int, default=100, help="queries timed in the plain per-maze loop")
     ap.add_argument("--serve-budget-gb", type=float, default=64.0)
     ap.add_argument("--serve-slots", type=int, default=64)
     ap.add_argument("--serve-rounds", type=int, default=4)
+    ap.add_argument("--summarize-counters", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR",
+                                                              "COPY_WRITE_DIR"),
+                    help="write profiles/k_sweep_c3_traffic.json from four rocprofv3 --pmc runs (no GPU)")
+    ap.add_argument("--summarize-trace", metavar="DIR", help="markdown table of a rocprofv3 --stats run (no GPU)")
+    ap.add_argument("--commands", nargs="*", default=[], help="commands recorded with --summarize-counters")
     args = ap.parse_args()
+    if args.summarize_counters:
+        summarize_counters(*args.summarize_counters, TRAFFIC_FILE, args.commands)
+        return
+    if args.summarize_trace:
+        summarize_trace(args.summarize_trace)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the path runs on a single MI355X "
               "(multi-GPU sharding is a design note, not part of this build)", file=sys.stderr)

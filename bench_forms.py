@@ -94,26 +94,44 @@ def bench_batch(args):
         b.profile(True)
         b.propagate(sync=False)
         prof = b.profile_read()
-    plain()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    plain()
-    torch.cuda.synchronize()
-    t_plain = time.perf_counter() - t0
+    t_plain = None
+    if not getattr(args, "no_plain_loop", False):
+        plain()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plain()
+        torch.cuda.synchronize()
+        t_plain = time.perf_counter() - t0
     eff = sum(m.H * m.W * (i["layers"] + 1) for m, i in zip(mazes, infos))
+    # roofline of the batch's sweep kernel on its own algorithmic bytes: the
+    # integer sweep 8.125 B per cell-update; the bit-sliced one 3 bits per
+    # cell and layer (reached set in and out, mask) + 4 B per reached cell
+    resolved = omap.resolve_options(**opts)
+    bits = resolved["schedule"] == omap.SCHEDULE_BITS
+    reached = sum(i["reached_cells"] for i in infos)
+    alg = prof["cell_updates"] * (0.375 if bits else 8.125) + (4 * reached if bits else 0)
+    k_s = prof["ms"] / 1e3
+    achieved = alg / k_s / 1e9 if k_s > 0 else 0.0
     return {
         "metric": "mazes/s", "value": round(n / t_batch, 2), "unit": "mazes/s", "n_gpus": 1,
         "steps": reps, "warmup": 1, "ms_per_step": round(t_batch * 1e3, 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
         "config": {"workload": "config4_512_mazes_loguniform_128_2048", "mazes": n, "cells": cells,
                    "targets": n_tgt, "max_layers_run_time": max(i["layers"] for i in infos)},
-        "plain_loop_mazes_per_s": round(n / t_plain, 2),
-        "speedup_vs_plain_loop": round(t_plain / t_batch, 2),
+        "plain_loop_mazes_per_s": round(n / t_plain, 2) if t_plain else None,
+        "speedup_vs_plain_loop": round(t_plain / t_batch, 2) if t_plain else None,
         "effective_gcell_updates_per_s": round(eff / t_batch / 1e9, 1),
         "paths_per_s": round(n_tgt / t_batch, 1),
-        "sweep_kernel": {"launches": prof["launches"], "ms_total": round(prof["ms"], 3),
-                         "cell_updates": prof["cell_updates"]},
-        "options": omap.resolve_options(**opts) if tuned is None else tuned["options"],
+        "sweep_kernel": {"kernel": f"k_bits<{resolved['temporal_depth']}>" if bits else
+                         f"k_sweep<{resolved['temporal_depth']},{resolved['lane_columns']}>",
+                         "launches": prof["launches"], "ms_total": round(prof["ms"], 3),
+                         "avg_us": round(prof["ms"] * 1e3 / max(prof["launches"], 1), 2),
+                         "cell_updates": prof["cell_updates"], "reached_cells": reached},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": 8000.0, "unit": "GB/s",
+                     "frac": round(achieved / 8000.0, 4),
+                     "algorithmic_bytes": "0.375 B per cell-layer + 4 B per reached cell" if bits
+                     else "8.125 B per cell-update"},
+        "options": resolved if tuned is None else tuned["options"],
         "autotuner": tuned,
         "default_options_mazes_per_s": round(n / t_default, 2) if t_default else None,
     }
