@@ -164,6 +164,10 @@ __device__ bool bits_tile(const MazeDev& md, int ty, int tx, int tile_rows, int 
 template <int T>
 __global__ __launch_bounds__(kBlockThreads) void k_bits(RoundArgs a) {
     if (a.round_base) a.round_id += *a.round_base;
+    if (blockIdx.x == gridDim.x - 1) {   // the accounting block (see k_sweep)
+        round_accounting<T>(a);
+        return;
+    }
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = lane_id();
     const int stride = a.wave_stride;
@@ -171,10 +175,6 @@ __global__ __launch_bounds__(kBlockThreads) void k_bits(RoundArgs a) {
     uint64_t e = 0;
     if (i < a.n_tile_ids) e = *reinterpret_cast<const uint64_t*>(a.list_in + 2 * i);
     const int n = __builtin_amdgcn_readfirstlane(*a.count_in);
-    if (blockIdx.x == 0) {
-        if (threadIdx.x == 0) *a.count_clear = 0;
-        for (int m = threadIdx.x; m < a.n_slots; m += kBlockThreads) a.sched_clear[m] = 0;
-    }
     __shared__ int s_cnt[2][kWavesPerBlock];
     __shared__ int s_base[2];
     int par = 0;
@@ -237,9 +237,9 @@ __global__ __launch_bounds__(kBlockThreads) void k_bits(RoundArgs a) {
         RoundArgs b = a;                                                                              \
         b.wave_stride = grid * kWavesPerBlock;                                                        \
         if (e0 != nullptr)                                                                            \
-            hipExtLaunchKernelGGL((k_bits<t>), dim3(grid), dim3(kBlockThreads), 0, s, e0, e1, 0, b);  \
+            hipExtLaunchKernelGGL((k_bits<t>), dim3(grid + 1), dim3(kBlockThreads), 0, s, e0, e1, 0, b); \
         else                                                                                          \
-            hipLaunchKernelGGL((k_bits<t>), dim3(grid), dim3(kBlockThreads), 0, s, b);               \
+            hipLaunchKernelGGL((k_bits<t>), dim3(grid + 1), dim3(kBlockThreads), 0, s, b);           \
         return hipGetLastError();                                                                     \
     }                                                                                                 \
     int bits_blocks_per_cu_T##t() {                                                                   \

@@ -51,6 +51,7 @@ struct RoundArgs {
     int32_t* count_out;           // their number (dense: 1 = some tile changed)
     int32_t* flags_out;           // 1 = already scheduled for round r+1
     int32_t* count_clear;         // count of round r+2, zeroed by round r
+    const int32_t* sched_in;      // per slot: tiles scheduled for round r (more than one slot)
     int32_t* sched_out;           // per slot: tiles scheduled for round r+1 (kept only with
                                   // more than one slot; with one slot it equals *count_out)
     int32_t* sched_clear;         // per slot: scheduled counts of round r+2, zeroed by round r

@@ -603,6 +603,7 @@ class Solver {
         a.count_out = d_count + (seeding ? r3 : n3);
         a.flags_out = d_flags[seeding ? r2 : n2];
         a.count_clear = d_count + nn3;
+        a.sched_in = d_sched + (size_t)r3 * cap_slots;
         a.sched_out = d_sched + (size_t)(seeding ? r3 : n3) * cap_slots;
         a.sched_clear = d_sched + (size_t)nn3 * cap_slots;
         a.dchg_prev = d_dchg + (size_t)nn3 * cap_slots;   // written in round r-1

@@ -249,10 +249,292 @@ __device__ __forceinline__ void sweep_warm(uint32_t (&st)[T][3][C], typename Lan
     }
 }
 
+// Counters and flags of one visit of the dense schedule (lane 0).  Issued
+// right after the visit's first D row loads: the vector-memory counter
+// completes in issue order, so issued earlier they would delay the first row,
+// and issued at the end of the visit their completion would delay the end of
+// the kernel.  Issued here they complete while the first D rows are computed.
+__device__ __forceinline__ void visit_bookkeeping(const RoundArgs& a, int g, int slot, const MazeDev& md,
+                                                  int ty, int tx) {
+    const unsigned long long cells = (unsigned long long)tile_cells(md, ty, tx, a.tile_rows, a.tile_cols);
+    const int sp = blockIdx.x & (kSpread - 1);
+    atomicAdd(reinterpret_cast<unsigned long long*>(&a.maze_visits[slot * kSpread + sp]), 1ull);
+    atomicAdd(reinterpret_cast<unsigned long long*>(&a.maze_cell_visits[slot * kSpread + sp]), cells);
+    atomicAdd(a.total_cells + sp, cells);
+    a.touched[g] = 1;
+    // every visiting wave of the round stores the same value (a test of the
+    // old value first would make the wave wait for a load)
+    a.maze_last_round[slot] = a.round_id;
+}
+
+// The same for a visit of a listed tile (active and bit-sliced schedules):
+// the round's accounting block has counted the visit as one of full size
+// (round_accounting), so only a tile cut by the maze's edge corrects the cell
+// counts; and the tile's scheduled flag of this round is cleared, which lets
+// the next round claim it again.
+__device__ __forceinline__ void visit_bookkeeping_active(const RoundArgs& a, int g, int slot, const MazeDev& md,
+                                                         int ty, int tx) {
+    a.flags_in[g] = 0;
+    a.touched[g] = 1;
+    a.maze_last_round[slot] = a.round_id;
+    const long long short_by = (long long)a.tile_rows * a.tile_cols - tile_cells(md, ty, tx, a.tile_rows, a.tile_cols);
+    if (short_by != 0) {
+        const int sp = blockIdx.x & (kSpread - 1);
+        atomicAdd(reinterpret_cast<unsigned long long*>(&a.maze_cell_visits[slot * kSpread + sp]),
+                  (unsigned long long)(-short_by));
+        atomicAdd(a.total_cells + sp, (unsigned long long)(-short_by));
+    }
+}
+
+// Work of the last block of a round launch, which visits no tile: it clears
+// the buffers round r+2 will fill and (listed schedules) counts round r's
+// visits from the list: per maze, its scheduled tiles (the whole list with
+// one maze) as visits of full tiles, corrected by the visits of edge tiles.
+// This replaces three same-address atomics per visit by one per maze and
+// round, off the visiting waves' path.  BITS_T (bit-sliced schedule, its
+// layers per visit): a maze whose rounds have covered its layers below K
+// visits nothing.
+template <int BITS_T>
+__device__ __forceinline__ void round_accounting(const RoundArgs& a) {
+    if (threadIdx.x == 0) *a.count_clear = 0;
+    for (int m = threadIdx.x; m < a.n_slots; m += kBlockThreads) {
+        a.sched_clear[m] = 0;
+        a.dchg_clear[m] = 0;
+    }
+    if (a.dense) return;
+    const unsigned long long full = (unsigned long long)a.tile_rows * a.tile_cols;
+    auto live = [&](const MazeDev& md) {
+        return BITS_T == 0 || (int64_t)(a.round_id - md.round0) * BITS_T + 1 < md.K;
+    };
+    if (a.n_slots == 1) {
+        if (threadIdx.x == 0) {
+            const unsigned long long v = (unsigned long long)*a.count_in;
+            if (v > 0 && live(a.md0)) {
+                atomicAdd(reinterpret_cast<unsigned long long*>(&a.maze_visits[0]), v);
+                atomicAdd(reinterpret_cast<unsigned long long*>(&a.maze_cell_visits[0]), v * full);
+                atomicAdd(a.total_cells, v * full);
+            }
+        }
+        return;
+    }
+    unsigned long long mine = 0;
+    for (int m = threadIdx.x; m < a.n_slots; m += kBlockThreads) {
+        const unsigned long long v = (unsigned long long)a.sched_in[m];
+        if (v > 0 && live(a.mazes[m])) {
+            atomicAdd(reinterpret_cast<unsigned long long*>(&a.maze_visits[m * kSpread]), v);
+            atomicAdd(reinterpret_cast<unsigned long long*>(&a.maze_cell_visits[m * kSpread]), v * full);
+            mine += v;
+        }
+    }
+    for (int o = kLanes / 2; o > 0; o >>= 1) mine += __shfl_xor(mine, o);
+    if (lane_id() == 0 && mine > 0) atomicAdd(a.total_cells + (threadIdx.x >> 6), mine * full);
+}
+
+// ---- interior visits -------------------------------------------------------
+//
+// A visit whose rows all lie inside the maze (the T rows above the tile, the
+// tile at its full height and every row prefetched below it) needs none of
+// the row clamps, row validity tests and store bounds of the general visit.
+// Its rows are addressed through buffer resources: a group of D row steps
+// shares one base per buffer, and row step J of the group lies J row strides
+// (a scalar offset) past it, so a row's loads and store cost no address
+// arithmetic beyond the lane's column offset, computed once per visit.  The
+// halo lanes' stores are dropped by the buffer range check (their offset is
+// past the store resource's extent), so a row needs no branch around its
+// store, and consecutive rows form one basic block that the compiler can
+// interleave.  Row sums include the halo lanes; the final ballot ignores them.
+
+// Lane constants of a visit.
+struct VisitLane {
+    int32_t voff;       // byte offset of the lane's first column in an activity row
+    int32_t soff;       // the same for stores: voff for interior lanes, past the store extent for halo lanes
+    int32_t moff;       // byte offset of the mask word holding the lane's columns
+    int32_t vrow;       // activity row stride, bytes
+    int32_t mrow;       // mask row stride, bytes
+    uint32_t shift;     // bit of the lane's first column in its mask word
+    bool col_ok, inner;
+};
+
+// Buffer resources of one group of D row steps starting at step i0: loads of
+// the rows D steps ahead, and the stores of the rows T steps behind.
+struct VisitGroup {
+    __amdgpu_buffer_rsrc_t ldv, ldm, stv;
+};
+
+// Word 3 of a raw (untyped, unswizzled) buffer resource on this architecture
+// family: 32-bit data format, everything else zero.
+constexpr int kRawBufferWord3 = 0x00020000;
+// Store offset of a halo lane: at or past any store resource's extent, so the
+// range check drops the store (with or without the scalar offset added).
+constexpr int32_t kDroppedStore = (int32_t)0x80000000u;
+
+// Raw buffer resource over `bytes` bytes from base (accesses at offsets
+// >= bytes are dropped: loads read 0, stores write nothing).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t raw_rsrc(const void* base, int32_t bytes = 0x7fffffff) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, bytes, kRawBufferWord3);
+}
+
+template <int C>
+__device__ __forceinline__ typename LaneVec<C>::type bload(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+    typedef typename LaneVec<C>::type V;
+    if constexpr (C == 1) {
+        V v;
+        v[0] = (int)__builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0);
+        return v;
+    } else if constexpr (C == 2) {
+        return (V)__builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0);
+    } else {
+        return (V)__builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0);
+    }
+}
+
+template <int C>
+__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, int voff, int soff, typename LaneVec<C>::type v) {
+    if constexpr (C == 1) {
+        __builtin_amdgcn_raw_buffer_store_b32((uint32_t)v[0], r, voff, soff, 0);
+    } else if constexpr (C == 2) {
+        typedef uint32_t U2 __attribute__((ext_vector_type(2)));
+        __builtin_amdgcn_raw_buffer_store_b64((U2)v, r, voff, soff, 0);
+    } else {
+        typedef uint32_t U4 __attribute__((ext_vector_type(4)));
+        __builtin_amdgcn_raw_buffer_store_b128((U4)v, r, voff, soff, 0);
+    }
+}
+
+// Bases of the group starting at step i0 (row r0 - T + i0): loads go to row
+// r0 - T + i0 + D + J, stores to row r0 - 2T + i0 + J.
+// The store resource covers exactly the group's D output rows.
+template <int T, int D>
+__device__ __forceinline__ VisitGroup visit_group(const MazeDev& md, const int32_t* Vin, int32_t* Vout, int r0,
+                                                  int i0) {
+    VisitGroup g;
+    g.ldv = raw_rsrc(Vin + (int64_t)(r0 - T + i0 + D) * md.pitch);
+    g.ldm = raw_rsrc(md.mask + (int64_t)(r0 - T + i0 + D) * md.mpitch);
+    g.stv = raw_rsrc(Vout + (int64_t)(r0 - 2 * T + i0) * md.pitch, D * md.pitch * 4);
+    return g;
+}
+
+// Row step J of a group in an interior visit (sweep_iter without the row
+// tests).  ROW is the step's index when known at compile time (warm-up), -1
+// in the steady state, where `step` holds it.  Steps [T, sum_end) carry the
+// tile's input rows, steps [2T, n_iter) emit its output rows.  In a steady
+// group, SUM is false when no step of the group is below sum_end, and TAIL
+// marks a last group that may run past n_iter.
+template <int T, int P, int C, int J, int SMAX, int ROW, bool SUM = true, bool TAIL = false>
+__device__ __forceinline__ void sweep_iter_inner(uint32_t (&st)[T][3][C], typename LaneVec<C>::type& v, uint32_t& w,
+                                                 const VisitGroup& g, const VisitLane& L, int step, int sum_end,
+                                                 int n_iter, uint64_t& sum_in, uint64_t& sum_out) {
+    uint32_t* c = st[0][P];
+    // missing columns (left of the maze, right of its pitch) decode as obstacles
+#pragma unroll
+    for (int j = 0; j < C; ++j) c[j] = L.col_ok ? (((w >> (L.shift + j)) << 31) | (uint32_t)v[j]) : kObstacleBit;
+    v = bload<C>(g.ldv, L.voff, J * L.vrow);
+    w = (uint32_t)bload<1>(g.ldm, L.moff, J * L.mrow)[0];
+    constexpr bool kMaySum = SUM && (ROW < 0 || ROW >= T);
+    if (kMaySum && (ROW < 0 ? step : ROW) < sum_end) {
+        uint64_t t = 0;
+#pragma unroll
+        for (int j = 0; j < C; ++j) t += c[j] & 0x7fffffffu;
+        sum_in += t;
+    }
+    uint32_t out[C] = {};
+    sweep_row<T, P, C, false, SMAX>(st, out, 0);
+    constexpr bool kMayStore = ROW < 0 || ROW >= 2 * T;
+    if (kMayStore && (!TAIL || step < n_iter)) {
+        typename LaneVec<C>::type o;
+        uint64_t t = 0;
+#pragma unroll
+        for (int j = 0; j < C; ++j) {
+            o[j] = (int)(out[j] & 0x7fffffffu);
+            t += (uint32_t)o[j];
+        }
+        bstore<C>(g.stv, L.soff, J * L.vrow, o);
+        sum_out += t;
+    }
+}
+
+// Steady-state group of an interior visit: steps i .. i + D - 1 (SUM: some
+// of them below sum_end; TAIL: the last group, which may run past n_iter).
+template <int T, int C, int D, bool SUM, bool TAIL, int J = 0>
+__device__ __forceinline__ void sweep_rows_inner(uint32_t (&st)[T][3][C], typename LaneVec<C>::type (&v)[D],
+                                                 uint32_t (&w)[D], const VisitGroup& g, const VisitLane& L, int i,
+                                                 int sum_end, int n_iter, uint64_t& sum_in, uint64_t& sum_out) {
+    if constexpr (J < D) {
+        sweep_iter_inner<T, J % 3, C, J, T - 1, -1, SUM, TAIL>(st, v[J], w[J], g, L, i + J, sum_end, n_iter,
+                                                               sum_in, sum_out);
+        sweep_rows_inner<T, C, D, SUM, TAIL, J + 1>(st, v, w, g, L, i, sum_end, n_iter, sum_in, sum_out);
+    }
+}
+
+// Warm-up of an interior visit: steps 0 .. KW - 1 unrolled, stage limits and
+// store steps known at compile time (KW <= n_iter, so every warm-up step at
+// or past 2T stores).
+template <int T, int C, int D, int KW, int I = 0>
+__device__ __forceinline__ void sweep_warm_inner(uint32_t (&st)[T][3][C], typename LaneVec<C>::type (&v)[D],
+                                                 uint32_t (&w)[D], VisitGroup& g, const MazeDev& md,
+                                                 const int32_t* Vin, int32_t* Vout, int r0, const VisitLane& L,
+                                                 int sum_end, int n_iter, uint64_t& sum_in, uint64_t& sum_out) {
+    if constexpr (I < KW) {
+        constexpr int SM = (I >> 1) - 1 < T - 1 ? (I >> 1) - 1 : T - 1;
+        if constexpr (I % D == 0) g = visit_group<T, D>(md, Vin, Vout, r0, I);
+        sweep_iter_inner<T, I % 3, C, I % D, SM, I>(st, v[I % D], w[I % D], g, L, I, sum_end, n_iter, sum_in,
+                                                    sum_out);
+        sweep_warm_inner<T, C, D, KW, I + 1>(st, v, w, g, md, Vin, Vout, r0, L, sum_end, n_iter, sum_in, sum_out);
+    }
+}
+
+// An interior visit (see above); same result as the general one.  on_start()
+// runs once the first D rows' loads are issued.
+template <int T, int C, class OnStart>
+__device__ __forceinline__ bool sweep_tile_inner(const MazeDev& md, int r0, int tile_rows, const VisitLane& L,
+                                                 const int32_t* Vin, int32_t* Vout, OnStart& on_start) {
+    constexpr int D = SweepPrefetch<T, C>::D;
+    constexpr int kWarm = D * ((2 * T + D - 1) / D);
+    uint32_t st[T][3][C];
+#pragma unroll
+    for (int s = 0; s < T; ++s)
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+            for (int j = 0; j < C; ++j) st[s][k][j] = kObstacleBit;
+    uint64_t sum_in = 0, sum_out = 0;
+    const int n_iter = tile_rows + 2 * T;
+    const int sum_end = T + tile_rows;
+    typename LaneVec<C>::type v[D];
+    uint32_t w[D];
+    {
+        const __amdgpu_buffer_rsrc_t rv = raw_rsrc(Vin + (int64_t)(r0 - T) * md.pitch);
+        const __amdgpu_buffer_rsrc_t rm = raw_rsrc(md.mask + (int64_t)(r0 - T) * md.mpitch);
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            v[j] = bload<C>(rv, L.voff, j * L.vrow);
+            w[j] = (uint32_t)bload<1>(rm, L.moff, j * L.mrow)[0];
+        }
+    }
+    on_start();
+    VisitGroup g;
+    sweep_warm_inner<T, C, D, kWarm>(st, v, w, g, md, Vin, Vout, r0, L, sum_end, n_iter, sum_in, sum_out);
+    int i = kWarm;
+#pragma unroll 1
+    for (; i + D <= n_iter; i += D) {
+        g = visit_group<T, D>(md, Vin, Vout, r0, i);
+        if (i < sum_end)
+            sweep_rows_inner<T, C, D, true, false>(st, v, w, g, L, i, sum_end, n_iter, sum_in, sum_out);
+        else
+            sweep_rows_inner<T, C, D, false, false>(st, v, w, g, L, i, sum_end, n_iter, sum_in, sum_out);
+    }
+    if (i < n_iter) {
+        g = visit_group<T, D>(md, Vin, Vout, r0, i);
+        sweep_rows_inner<T, C, D, true, true>(st, v, w, g, L, i, sum_end, n_iter, sum_in, sum_out);
+    }
+    return __ballot(L.inner && sum_in != sum_out) != 0;
+}
+
 // Returns true (wave-uniform) if any interior cell of the tile changed.  The
 // wave streams the strip of 64*C columns starting T columns left of the tile.
-template <int T, int C>
-__device__ bool sweep_tile(const MazeDev& md, int ty, int tx, int tile_rows, int parity) {
+// on_start() runs once the loads of the visit's first D rows are issued.
+template <int T, int C, class OnStart>
+__device__ bool sweep_tile(const MazeDev& md, int ty, int tx, int tile_rows, int parity, OnStart& on_start) {
     constexpr int TW = kLanes * C - 2 * T;
     constexpr int HALO_LANES = T / C;
     constexpr int D = SweepPrefetch<T, C>::D;
@@ -264,6 +546,26 @@ __device__ bool sweep_tile(const MazeDev& md, int ty, int tx, int tile_rows, int
     const bool inner = lane >= HALO_LANES && lane < kLanes - HALO_LANES && col < md.W;
     int32_t* const Vin = parity ? md.V[1] : md.V[0];
     int32_t* const Vout = parity ? md.V[0] : md.V[1];
+    if constexpr (C == 1) {
+        // interior visit: every loaded row inside the maze (the last group of
+        // D steps may run past n_iter and prefetch D rows beyond it), full
+        // tile height, and a warm-up that ends inside the visit
+        constexpr int kWarmI = D * ((2 * T + D - 1) / D);
+        if (r0 >= T && r_end == r0 + tile_rows && tile_rows + 2 * T >= kWarmI &&
+            (int64_t)r0 + tile_rows + T + 2 * D <= md.H) {
+            VisitLane L;
+            const int cc = col_ok ? col : 0;
+            L.voff = cc * 4;
+            L.soff = inner ? L.voff : kDroppedStore;
+            L.moff = (cc >> 5) * 4;
+            L.vrow = md.pitch * 4;
+            L.mrow = md.mpitch * 4;
+            L.shift = (uint32_t)(col & 31);
+            L.col_ok = col_ok;
+            L.inner = inner;
+            return sweep_tile_inner<T, C>(md, r0, tile_rows, L, Vin, Vout, on_start);
+        }
+    }
 
     uint32_t st[T][3][C];
 #pragma unroll
@@ -279,6 +581,7 @@ __device__ bool sweep_tile(const MazeDev& md, int ty, int tx, int tile_rows, int
     uint32_t w[D];
 #pragma unroll
     for (int j = 0; j < D; ++j) load_row<C>(md, Vin, r0 - T + j, col, col_ok, v[j], w[j]);
+    on_start();
     // Stage s at step i (input row r0 - T + i) emits row r0 - T + i - 1 - s
     // after s + 1 layers; the stored rows [r0, r_end) after T layers need
     // exactly the emissions with i >= 2s + 2 (each of which reads only
@@ -307,38 +610,26 @@ __device__ bool sweep_tile(const MazeDev& md, int ty, int tx, int tile_rows, int
     return __ballot(sum_in != sum_out) != 0;
 }
 
-// Tile g of slot: T layers.  Returns true (wave-uniform) if the interior
+// Tile g of slot: T layers, with the visit's bookkeeping (ACTIVE: also the
+// tile's scheduled flag).  Returns true (wave-uniform) if the interior
 // changed; md, ty, tx describe the tile.
-template <int T, int C>
+template <int T, int C, bool ACTIVE>
 __device__ __forceinline__ bool visit_tile(const RoundArgs& a, int g, int slot, MazeDev& md, int& ty, int& tx) {
     md = a.n_slots == 1 ? a.md0 : a.mazes[slot];
     const int lt = g - md.tile_base;
     ty = lt / md.tiles_x;
     tx = lt - ty * md.tiles_x;
-    return sweep_tile<T, C>(md, ty, tx, a.tile_rows, a.parity);
-}
-
-// Counters and flags of one visit (lane 0).  Called after the visit's own
-// scheduling work: the vector-memory counter completes in issue order, so
-// a load here issued before the tile's row loads would make the first row
-// wait for these atomics and this load as well.
-__device__ __forceinline__ void visit_bookkeeping(const RoundArgs& a, int g, int slot, const MazeDev& md,
-                                                  int ty, int tx) {
-    const unsigned long long cells = (unsigned long long)tile_cells(md, ty, tx, a.tile_rows, a.tile_cols);
-    const int sp = blockIdx.x & (kSpread - 1);
-    atomicAdd(reinterpret_cast<unsigned long long*>(&a.maze_visits[slot * kSpread + sp]), 1ull);
-    atomicAdd(reinterpret_cast<unsigned long long*>(&a.maze_cell_visits[slot * kSpread + sp]), cells);
-    atomicAdd(a.total_cells + sp, cells);
-    a.touched[g] = 1;
-    if (a.maze_last_round[slot] != a.round_id) a.maze_last_round[slot] = a.round_id;
-}
-
-// The same plus clearing the tile's scheduled flag of this round (active
-// schedule), which lets the next round claim the tile again.
-__device__ __forceinline__ void visit_bookkeeping_active(const RoundArgs& a, int g, int slot, const MazeDev& md,
-                                                         int ty, int tx) {
-    a.flags_in[g] = 0;
-    visit_bookkeeping(a, g, slot, md, ty, tx);
+    const MazeDev& m = md;
+    const int y = ty, x = tx;
+    auto on_start = [&]() {
+        if (lane_id() == 0) {
+            if (ACTIVE)
+                visit_bookkeeping_active(a, g, slot, m, y, x);
+            else
+                visit_bookkeeping(a, g, slot, m, y, x);
+        }
+    };
+    return sweep_tile<T, C>(md, ty, tx, a.tile_rows, a.parity, on_start);
 }
 
 // Round r: every scheduled tile gets T layers.  Active schedule: the tiles of
@@ -352,32 +643,28 @@ __device__ __forceinline__ void sweep_round(const RoundArgs& a) {
     const int lane = lane_id();
     const int stride = a.wave_stride;
     int i = blockIdx.x * kWavesPerBlock + wave;
-    // The first list entry is loaded before the count, so both round trips
-    // overlap (the entry is in bounds for any i below the tile id space, and
-    // used only if i < n).
-    uint64_t e = 0;
-    if (!a.dense && i < a.n_tile_ids) e = *reinterpret_cast<const uint64_t*>(a.list_in + 2 * i);
-    const int n = a.dense ? a.n_tile_ids : __builtin_amdgcn_readfirstlane(*a.count_in);
-    if (blockIdx.x == 0) {
-        if (threadIdx.x == 0) *a.count_clear = 0;
-        for (int m = threadIdx.x; m < a.n_slots; m += kBlockThreads) {
-            a.sched_clear[m] = 0;
-            a.dchg_clear[m] = 0;
-        }
-    }
+    // The wave's first list entry and the round's count are loaded together,
+    // with no branch between them, so both round trips overlap (the entry's
+    // index is clamped into the list; the entry is used only if i < n).
+    // (relaxed atomic loads of workgroup scope: plain cached loads that the
+    // compiler keeps where they are written instead of sinking the count's
+    // load into the branch that uses it; the previous round's writes are
+    // visible across the kernel boundary)
+    const uint64_t e0 = __hip_atomic_load(reinterpret_cast<const uint64_t*>(a.list_in + 2 * (i < a.n_tile_ids ? i : 0)),
+                                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    const int cnt = __hip_atomic_load(a.count_in, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    uint64_t e = e0;
+    const int n = a.dense ? a.n_tile_ids : __builtin_amdgcn_readfirstlane(cnt);
     if (a.dense) {
         for (; i < n; i += stride) {
             const int slot = a.tile_maze[i];
             if (slot < 0 || __builtin_amdgcn_readfirstlane(a.dchg_prev[slot]) == 0) continue;
             MazeDev md;
             int ty, tx;
-            const bool changed = visit_tile<T, C>(a, i, slot, md, ty, tx);
-            if (lane == 0) {
-                if (changed) {
-                    a.dchg_cur[slot] = 1;
-                    *a.count_out = 1;
-                }
-                visit_bookkeeping(a, i, slot, md, ty, tx);
+            const bool changed = visit_tile<T, C, false>(a, i, slot, md, ty, tx);
+            if (lane == 0 && changed) {
+                a.dchg_cur[slot] = 1;
+                *a.count_out = 1;
             }
         }
         return;
@@ -398,7 +685,7 @@ __device__ __forceinline__ void sweep_round(const RoundArgs& a) {
             g = __builtin_amdgcn_readfirstlane((int)(uint32_t)e);
             slot = __builtin_amdgcn_readfirstlane((int)(uint32_t)(e >> 32));
             if (i + stride < n) e = *reinterpret_cast<const uint64_t*>(a.list_in + 2 * (i + stride));
-            if (visit_tile<T, C>(a, g, slot, md, ty, tx)) {
+            if (visit_tile<T, C, true>(a, g, slot, md, ty, tx)) {
                 // lanes 0..8 claim the 3x3 tiles around (ty, tx) for the next round
                 const int ny = ty + lane / 3 - 1, nx = tx + lane % 3 - 1;
                 gn = md.tile_base + ny * md.tiles_x + nx;
@@ -427,13 +714,18 @@ __device__ __forceinline__ void sweep_round(const RoundArgs& a) {
             }
             if (a.n_slots > 1 && lane == 0) atomicAdd(&a.sched_out[slot], nwon);
         }
-        if (i < n && lane == 0) visit_bookkeeping_active(a, g, slot, md, ty, tx);
     }
 }
 
+// The grid has one block more than a.wave_stride covers: the last one does
+// the round's accounting (round_accounting) instead of visits.
 template <int T, int C>
 __global__ __launch_bounds__(kBlockThreads) void k_sweep(RoundArgs a) {
     if (a.round_base) a.round_id += *a.round_base;
+    if (blockIdx.x == gridDim.x - 1) {
+        round_accounting<0>(a);
+        return;
+    }
     sweep_round<T, C>(a);
 }
 
@@ -445,9 +737,9 @@ __global__ __launch_bounds__(kBlockThreads) void k_sweep(RoundArgs a) {
         RoundArgs b = a;                                                                              \
         b.wave_stride = grid * kWavesPerBlock;                                                        \
         if (e0 != nullptr)                                                                            \
-            hipExtLaunchKernelGGL((k_sweep<t, c>), dim3(grid), dim3(kBlockThreads), 0, s, e0, e1, 0, b); \
+            hipExtLaunchKernelGGL((k_sweep<t, c>), dim3(grid + 1), dim3(kBlockThreads), 0, s, e0, e1, 0, b); \
         else                                                                                          \
-            hipLaunchKernelGGL((k_sweep<t, c>), dim3(grid), dim3(kBlockThreads), 0, s, b);           \
+            hipLaunchKernelGGL((k_sweep<t, c>), dim3(grid + 1), dim3(kBlockThreads), 0, s, b);       \
         return hipGetLastError();                                                                     \
     }                                                                                                 \
     int sweep_blocks_per_cu_T##t##_C##c() {                                                           \
