@@ -278,41 +278,37 @@ __device__ __forceinline__ int dir_dc(int k) {
     return (k == 0 || k == 3 || k == 5) ? -1 : ((k == 1 || k == 6) ? 0 : 1);
 }
 
-// The walk is a chain of dependent loads, one step after the other, so its
-// time is the longest path times the latency of one step.  One wave follows
-// one target: it loads a kWinRows x kWinCols window of the activity around the
-// current cell into LDS with wide coalesced loads (one global round trip) and
-// then takes up to kWinSteps steps from LDS.  In a step, lane l reads
-// neighbour k = l mod 8 and forms the key (value rank << 3) | (7 - k); a
-// maximum over the lanes (three DPP rotations within a row of 16 lanes)
-// selects the largest value and, among equal values, the smallest k, which is
-// the first maximal neighbour in the fixed order.  Window cells outside the
-// grid read as -1, below every in-grid value.
+// The walk is a chain of dependent steps, so its time is the longest path
+// times the latency of one step.  One wave follows one target through the
+// activity map from a window of kWinRows x 64 cells held in LDS (one global
+// round trip per window, 16-byte loads).
+//
+// A step from a reached non-source cell with activity v0 goes to its first
+// neighbour (fixed order: row-major over the 3 x 3 block, centre skipped)
+// whose activity is v0 + 1: the map's largest neighbour value is exactly
+// v0 + 1 there (activity drops by one per move away from the sources), so
+// this is the first maximal neighbour.  Three steps are resolved per LDS
+// read: lane l reads the cell at (l / 8 - 3, l % 8 - 3) from the current
+// cell, i.e. the 8 x 8 block around it, and three ballots mark the block's
+// cells holding v0 + 1, v0 + 2 and v0 + 3.  Block cells are numbered
+// row-major, so the 8 neighbours of block cell q, in the fixed order, are the
+// set bits of kNbr << (q - 9), and step j moves to the lowest set bit of
+// ballot j among the neighbours of the cell step j - 1 reached (a cell at
+// most j - 1 from the centre, whose neighbours stay inside the block for
+// j <= 3).  Window cells outside the grid read -1 and obstacles 0, so neither
+// ever matches.  The window is placed so that the path's direction over the
+// previous window has the most room ahead; it is reloaded when the 8 x 8
+// block around the current cell no longer fits.
 #ifndef OMAP_WALK_ROWS
-#define OMAP_WALK_ROWS 32
-#define OMAP_WALK_COLS 48
+#define OMAP_WALK_ROWS 48
 #endif
 constexpr int kWinRows = OMAP_WALK_ROWS;
-constexpr int kWinCols = OMAP_WALK_COLS;       // a multiple of 4 (chunks of 4 columns)
-constexpr int kWinSteps = kWinRows / 2 - 1;    // steps per window
-// After k < kWinSteps steps from (kWinSteps, c - C0) with c - C0 in
-// [kWinSteps + 1, kWinSteps + 4], the 8 neighbours lie in rows 0 .. 2 kWinSteps
-// and columns 1 .. 2 kWinSteps + 4.
-static_assert(kWinRows >= 2 * kWinSteps + 1 && kWinCols >= 2 * kWinSteps + 5 && kWinCols % 4 == 0, "walk window");
-static_assert((kWinRows * kWinCols / 4) % kLanes == 0, "walk window chunks per lane");
+constexpr int kWinCols = 64;                       // window row: 64 cells = 16 chunks of 4
 constexpr int kWinChunks = kWinRows * kWinCols / 4;
+static_assert(kWinRows >= 16 && kWinChunks % kLanes == 0, "walk window");
 constexpr int kWalkWaves = 4;
-// (dr + 1) | (dc + 1) << 2 of neighbour k in bits 4k..4k+3
-constexpr uint32_t kDirNibbles = 0xA6291840u;
-
-// (the identity as the old value lets each DPP move fold into its max)
-__device__ __forceinline__ int row_max16(int x) {
-    constexpr int kMin = (int)0x80000000;
-    x = max(__builtin_amdgcn_update_dpp(kMin, x, 0x124, 0xF, 0xF, false), x);   // row_ror:4
-    x = max(__builtin_amdgcn_update_dpp(kMin, x, 0x122, 0xF, 0xF, false), x);   // row_ror:2
-    x = max(__builtin_amdgcn_update_dpp(kMin, x, 0x121, 0xF, 0xF, false), x);   // row_ror:1
-    return x;
-}
+// neighbours of block cell 9 (row 1, column 1): cells 0, 1, 2, 8, 10, 16, 17, 18
+constexpr uint64_t kNbr = 0x70507ull;
 
 __global__ __launch_bounds__(kLanes * kWalkWaves) void k_walk(
     const MazeDev* __restrict__ mazes, const int32_t* __restrict__ tslot, const int32_t* __restrict__ trc,
@@ -329,24 +325,29 @@ __global__ __launch_bounds__(kLanes * kWalkWaves) void k_walk(
     const MazeDev md = mazes[slot];
     const int32_t* __restrict__ V = parity ? md.V[1] : md.V[0];
     int32_t* win = win_all[wave];
-    // this lane's neighbour: k = lane mod 8, offset in the window from the
-    // current cell's upper-left neighbour (non-negative)
-    const int k8 = lane & 7;
-    const uint32_t nib = (kDirNibbles >> (4 * k8)) & 15u;
-    const int my_off = (int)(nib & 3u) * kWinCols + (int)(nib >> 2);
-    const int my_tie = 7 - k8;
+    // this lane's cell of the 8 x 8 block, relative to the current cell
+    const int my_off = ((lane >> 3) - 3) * kWinCols + ((lane & 7) - 3);
     int r = __builtin_amdgcn_readfirstlane(trc[2 * i]);
     int c = __builtin_amdgcn_readfirstlane(trc[2 * i + 1]);
     int64_t o = off[i];
     if (lane == 0) cells[o] = r * md.W + c;
     ++o;
+    // the cells of a window's steps are logged one per lane (lane k: step k
+    // of the window) as (window position of the step's 8 x 8 block centre)
+    // << 6 | (cell in the block), and stored when the window is left
+    int log = 0, nlog = 0;
+    int dr_prev = 0, dc_prev = 0;   // displacement over the previous window
+    int v0 = 0;
     for (int s = 0; s < steps;) {
-        // window rows r - kWinSteps .., columns C0 .. with C0 = 4 floor((c - kWinSteps - 1) / 4)
-        const int R0 = r - kWinSteps, C0 = (c - (kWinSteps + 1)) & ~3;
+        // place the window: the current cell at row lr, column lc, with the
+        // most room in the direction the path last went
+        const int lr0 = dr_prev < 0 ? kWinRows - 5 : (dr_prev > 0 ? 3 : kWinRows / 2);
+        const int lc0 = dc_prev < 0 ? 56 : (dc_prev > 0 ? 3 : 30);
+        const int R0 = r - lr0, C0 = (c - lc0) & ~3;
 #pragma unroll
         for (int k = 0; k < kWinChunks / kLanes; ++k) {
             const int q = lane + kLanes * k;
-            const int wr = q / (kWinCols / 4), wc = 4 * (q % (kWinCols / 4));
+            const int wr = q >> 4, wc = 4 * (q & 15);
             const int R = R0 + wr, cs = C0 + wc;
             const bool rok = R >= 0 && R < md.H;
             const bool cok = cs >= 0 && cs < md.pitch;   // a chunk lies wholly inside or outside a row
@@ -364,28 +365,44 @@ __global__ __launch_bounds__(kLanes * kWalkWaves) void k_walk(
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         int lr = r - R0, lc = c - C0;
-        int ul = (lr - 1) * kWinCols + (lc - 1);   // upper-left neighbour of the current cell
-        // the first maximal neighbour of a reached non-source cell holds its value + 1
-        int v0 = __builtin_amdgcn_readfirstlane(win[ul + kWinCols + 1]);
-        const int todo = min(kWinSteps, steps - s);
-        // lane k keeps the window position of step k; the window's cells are
-        // stored together after its last step
-        int my_rc = 0;
-        for (int k = 0; k < todo; ++k) {
-            const int v = win[ul + my_off];
-            const int key = row_max16((max(v - v0 + 2, 0) << 3) | my_tie);
-            const int best = 7 - (__builtin_amdgcn_readfirstlane(key) & 7);
-            const uint32_t d = (kDirNibbles >> (4 * best)) & 15u;
-            const int dr = (int)(d & 3u) - 1, dc = (int)(d >> 2) - 1;
-            lr += dr;
-            lc += dc;
-            ul += dr * kWinCols + dc;
-            ++v0;
-            my_rc = lane == k ? (lr << 16) | lc : my_rc;
+        if (s == 0) v0 = __builtin_amdgcn_readfirstlane(win[lr * kWinCols + lc]);
+        const int s_start = s;
+        // while the 8 x 8 block around (lr, lc) lies inside the window (and
+        // the log has room for three more steps)
+        while (s < steps && lr >= 3 && lr <= kWinRows - 5 && lc >= 3 && lc <= kWinCols - 5 && nlog <= kLanes - 3) {
+            const int pos = lr * kWinCols + lc;
+            const int v = win[pos + my_off];
+            const uint64_t m1 = __ballot(v == v0 + 1);
+            const uint64_t m2 = __ballot(v == v0 + 2);
+            const uint64_t m3 = __ballot(v == v0 + 3);
+            const int todo = min(3, steps - s);
+            int q = 27;   // the current cell
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                if (j < todo) {
+                    const uint64_t m = j == 0 ? m1 : (j == 1 ? m2 : m3);
+                    q = __builtin_ctzll(m & (kNbr << (q - 9)));
+                    log = lane == nlog + j ? (pos << 6) | q : log;
+                }
+            }
+            nlog += todo;
+            lr += (q >> 3) - 3;
+            lc += (q & 7) - 3;
+            v0 += todo;
+            s += todo;
         }
-        if (lane < todo) cells[o + lane] = (R0 + (my_rc >> 16)) * md.W + (C0 + (my_rc & 0xffff));
-        o += todo;
-        s += todo;
+        if (lane < nlog) {
+            const int q = log & 63, pos = log >> 6;
+            cells[o + lane] = (R0 + (pos >> 6) - 3 + (q >> 3)) * md.W + (C0 + (pos & 63) - 3 + (q & 7));
+        }
+        o += nlog;
+        nlog = 0;
+        dr_prev = lr - (r - R0);
+        dc_prev = lc - (c - C0);
+        // a move of less than a third of the steps counts as no direction
+        const int moved = s - s_start;
+        if (3 * abs(dr_prev) < moved) dr_prev = 0;
+        if (3 * abs(dc_prev) < moved) dc_prev = 0;
         r = R0 + lr;
         c = C0 + lc;
         // the next window overwrites this one only after every lane's reads
