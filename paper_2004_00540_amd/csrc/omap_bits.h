@@ -164,21 +164,21 @@ __device__ bool bits_tile(const MazeDev& md, int ty, int tx, int tile_rows, int 
 template <int T>
 __global__ __launch_bounds__(kBlockThreads) void k_bits(RoundArgs a) {
     if (a.round_base) a.round_id += *a.round_base;
-    if (blockIdx.x == gridDim.x - 1) {   // the accounting block (see k_sweep)
+    if (blockIdx.x == 0) {   // the accounting block (see k_sweep)
         round_accounting<T>(a);
         return;
     }
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = lane_id();
     const int stride = a.wave_stride;
-    int i = blockIdx.x * kWavesPerBlock + wave;
+    int i = (blockIdx.x - 1) * kWavesPerBlock + wave;   // block 0: the accounting block
     uint64_t e = 0;
     if (i < a.n_tile_ids) e = *reinterpret_cast<const uint64_t*>(a.list_in + 2 * i);
     const int n = __builtin_amdgcn_readfirstlane(*a.count_in);
     __shared__ int s_cnt[2][kWavesPerBlock];
     __shared__ int s_base[2];
     int par = 0;
-    for (int ib = blockIdx.x * kWavesPerBlock; ib < n; ib += stride, par ^= 1) {
+    for (int ib = (blockIdx.x - 1) * kWavesPerBlock; ib < n; ib += stride, par ^= 1) {
         i = ib + wave;
         int slot = 0, gn = 0, g = 0, ty = 0, tx = 0;
         bool won = false, visited = false;

@@ -120,6 +120,67 @@ __device__ __forceinline__ void sweep_row(uint32_t (&st)[T][3][C], uint32_t (&ou
     }
 }
 
+// One stage of one row step: o = the layer applied to the centre row b with
+// a and c above and below (C columns per lane).
+template <int C>
+__device__ __forceinline__ void sweep_stage(const uint32_t* a, const uint32_t* b, const uint32_t* c, uint32_t* o) {
+    int v[C];
+#pragma unroll
+    for (int j = 0; j < C; ++j) v[j] = max3i((int)a[j], (int)b[j], (int)c[j]);
+    const int left = from_left_lane(v[C - 1]);
+    const int right = from_right_lane(v[0]);
+#pragma unroll
+    for (int j = 0; j < C; ++j) {
+        const int l = j == 0 ? left : v[j - 1];
+        const int r = j == C - 1 ? right : v[j + 1];
+        o[j] = max(b[j], sat_dec((uint32_t)max3i(l, v[j], r)));
+    }
+}
+
+// Two independent stages computed operation by operation side by side (one
+// column per lane), so that neither's DPP move waits on the instruction
+// just before it.
+__device__ __forceinline__ void sweep_stage_x2(const uint32_t* a0, const uint32_t* b0, const uint32_t* c0,
+                                               uint32_t* o0, const uint32_t* a1, const uint32_t* b1,
+                                               const uint32_t* c1, uint32_t* o1) {
+    const int v0 = max3i((int)a0[0], (int)b0[0], (int)c0[0]);
+    const int v1 = max3i((int)a1[0], (int)b1[0], (int)c1[0]);
+    const int l0 = from_left_lane(v0);
+    const int l1 = from_left_lane(v1);
+    const int r0 = from_right_lane(v0);
+    const int r1 = from_right_lane(v1);
+    o0[0] = max(b0[0], sat_dec((uint32_t)max3i(l0, v0, r0)));
+    o1[0] = max(b1[0], sat_dec((uint32_t)max3i(l1, v1, r1)));
+}
+
+// Two consecutive row steps (slots P and P + 1, stages up to SMAX in both)
+// with their stage chains interleaved: stage s of the first step and stage
+// s - 1 of the second use nothing the other computes, so each chain's
+// instructions fill the other's DPP read-after-write gaps.  cnext is the
+// second step's decoded input row; it enters stage 0's slot P + 1 once the
+// first step's stage 0 has read the row it replaces.
+template <int T, int P, int C, int SMAX>
+__device__ __forceinline__ void sweep_row2(uint32_t (&st)[T][3][C], const uint32_t (&cnext)[C], uint32_t (&out0)[C],
+                                           uint32_t (&out1)[C]) {
+    constexpr int PA = (P + 1) % 3, PB = (P + 2) % 3;
+#pragma unroll
+    for (int s = 0; s <= T; ++s) {
+        const bool first = s < T && s <= SMAX, second = s >= 1 && s - 1 <= SMAX;
+        uint32_t* o0 = s + 1 < T ? st[s + 1 < T ? s + 1 : 0][P] : out0;
+        uint32_t* o1 = s < T ? st[s < T ? s : 0][PA] : out1;
+        if (C == 1 && first && second && s >= 1) {
+            sweep_stage_x2(st[s][PA], st[s][PB], st[s][P], o0, st[s - 1][PB], st[s - 1][P], st[s - 1][PA], o1);
+            continue;
+        }
+        if (first) sweep_stage<C>(st[s][PA], st[s][PB], st[s][P], o0);
+        if (s == 0) {
+#pragma unroll
+            for (int j = 0; j < C; ++j) st[0][PA][j] = cnext[j];
+        }
+        if (second) sweep_stage<C>(st[s - 1][PB], st[s - 1][P], st[s - 1][PA], o1);
+    }
+}
+
 // Global-memory views of the activity and mask buffers (lets the compiler use
 // global_load / global_store instead of flat accesses).
 typedef int v4i32 __attribute__((ext_vector_type(4)));
@@ -286,7 +347,7 @@ __device__ __forceinline__ void visit_bookkeeping_active(const RoundArgs& a, int
     }
 }
 
-// Work of the last block of a round launch, which visits no tile: it clears
+// Work of the first block of a round launch, which visits no tile: it clears
 // the buffers round r+2 will fill and (listed schedules) counts round r's
 // visits from the list: per maze, its scheduled tiles (the whole list with
 // one maze) as visits of full tiles, corrected by the visits of edge tiles.
@@ -453,16 +514,81 @@ __device__ __forceinline__ void sweep_iter_inner(uint32_t (&st)[T][3][C], typena
     }
 }
 
+// Row steps J and J + 1 of a group in an interior visit, their stages
+// interleaved (sweep_row2); otherwise as two sweep_iter_inner steps.  Both
+// steps share the stage limit SMAX (true for an even first warm-up step).
+template <int T, int P, int C, int J, int SMAX, int ROW, bool SUM = true, bool TAIL = false>
+__device__ __forceinline__ void sweep_iter2_inner(uint32_t (&st)[T][3][C], typename LaneVec<C>::type& v0,
+                                                  uint32_t& w0, typename LaneVec<C>::type& v1, uint32_t& w1,
+                                                  const VisitGroup& g, const VisitLane& L, int step, int sum_end,
+                                                  int n_iter, uint64_t& sum_in, uint64_t& sum_out) {
+    uint32_t* c0 = st[0][P];
+    uint32_t c1[C];
+#pragma unroll
+    for (int j = 0; j < C; ++j) {
+        c0[j] = L.col_ok ? (((w0 >> (L.shift + j)) << 31) | (uint32_t)v0[j]) : kObstacleBit;
+        c1[j] = L.col_ok ? (((w1 >> (L.shift + j)) << 31) | (uint32_t)v1[j]) : kObstacleBit;
+    }
+    v0 = bload<C>(g.ldv, L.voff, J * L.vrow);
+    w0 = (uint32_t)bload<1>(g.ldm, L.moff, J * L.mrow)[0];
+    v1 = bload<C>(g.ldv, L.voff, (J + 1) * L.vrow);
+    w1 = (uint32_t)bload<1>(g.ldm, L.moff, (J + 1) * L.mrow)[0];
+    constexpr int ROW1 = ROW < 0 ? -1 : ROW + 1;
+    constexpr bool kMaySum0 = SUM && (ROW < 0 || ROW >= T);
+    constexpr bool kMaySum1 = SUM && (ROW1 < 0 || ROW1 >= T);
+    if (kMaySum0 && (ROW < 0 ? step : ROW) < sum_end) {
+        uint64_t t = 0;
+#pragma unroll
+        for (int j = 0; j < C; ++j) t += c0[j] & 0x7fffffffu;
+        sum_in += t;
+    }
+    if (kMaySum1 && (ROW1 < 0 ? step + 1 : ROW1) < sum_end) {
+        uint64_t t = 0;
+#pragma unroll
+        for (int j = 0; j < C; ++j) t += c1[j] & 0x7fffffffu;
+        sum_in += t;
+    }
+    uint32_t out0[C] = {}, out1[C] = {};
+    sweep_row2<T, P, C, SMAX>(st, c1, out0, out1);
+    constexpr bool kMayStore0 = ROW < 0 || ROW >= 2 * T;
+    constexpr bool kMayStore1 = ROW1 < 0 || ROW1 >= 2 * T;
+    if (kMayStore0 && (!TAIL || step < n_iter)) {
+        typename LaneVec<C>::type o;
+        uint64_t t = 0;
+#pragma unroll
+        for (int j = 0; j < C; ++j) {
+            o[j] = (int)(out0[j] & 0x7fffffffu);
+            t += (uint32_t)o[j];
+        }
+        bstore<C>(g.stv, L.soff, J * L.vrow, o);
+        sum_out += t;
+    }
+    if (kMayStore1 && (!TAIL || step + 1 < n_iter)) {
+        typename LaneVec<C>::type o;
+        uint64_t t = 0;
+#pragma unroll
+        for (int j = 0; j < C; ++j) {
+            o[j] = (int)(out1[j] & 0x7fffffffu);
+            t += (uint32_t)o[j];
+        }
+        bstore<C>(g.stv, L.soff, (J + 1) * L.vrow, o);
+        sum_out += t;
+    }
+}
+
 // Steady-state group of an interior visit: steps i .. i + D - 1 (SUM: some
 // of them below sum_end; TAIL: the last group, which may run past n_iter).
 template <int T, int C, int D, bool SUM, bool TAIL, int J = 0>
 __device__ __forceinline__ void sweep_rows_inner(uint32_t (&st)[T][3][C], typename LaneVec<C>::type (&v)[D],
                                                  uint32_t (&w)[D], const VisitGroup& g, const VisitLane& L, int i,
                                                  int sum_end, int n_iter, uint64_t& sum_in, uint64_t& sum_out) {
-    if constexpr (J < D) {
+    if constexpr (J + 1 < D) {
+        sweep_iter2_inner<T, J % 3, C, J, T - 1, -1, SUM, TAIL>(st, v[J], w[J], v[J + 1], w[J + 1], g, L, i + J,
+                                                                sum_end, n_iter, sum_in, sum_out);
+        sweep_rows_inner<T, C, D, SUM, TAIL, J + 2>(st, v, w, g, L, i, sum_end, n_iter, sum_in, sum_out);
+    } else if constexpr (J < D) {
         sweep_iter_inner<T, J % 3, C, J, T - 1, -1, SUM, TAIL>(st, v[J], w[J], g, L, i + J, sum_end, n_iter,
                                                                sum_in, sum_out);
-        sweep_rows_inner<T, C, D, SUM, TAIL, J + 1>(st, v, w, g, L, i, sum_end, n_iter, sum_in, sum_out);
     }
 }
 
@@ -474,7 +600,14 @@ __device__ __forceinline__ void sweep_warm_inner(uint32_t (&st)[T][3][C], typena
                                                  uint32_t (&w)[D], VisitGroup& g, const MazeDev& md,
                                                  const int32_t* Vin, int32_t* Vout, int r0, const VisitLane& L,
                                                  int sum_end, int n_iter, uint64_t& sum_in, uint64_t& sum_out) {
-    if constexpr (I < KW) {
+    if constexpr (I + 1 < KW && I % 2 == 0 && (I + 1) % D != 0) {
+        // steps I and I + 1 (I even: same stage limit) in one group
+        constexpr int SM = (I >> 1) - 1 < T - 1 ? (I >> 1) - 1 : T - 1;
+        if constexpr (I % D == 0) g = visit_group<T, D>(md, Vin, Vout, r0, I);
+        sweep_iter2_inner<T, I % 3, C, I % D, SM, I>(st, v[I % D], w[I % D], v[(I + 1) % D], w[(I + 1) % D], g, L,
+                                                     I, sum_end, n_iter, sum_in, sum_out);
+        sweep_warm_inner<T, C, D, KW, I + 2>(st, v, w, g, md, Vin, Vout, r0, L, sum_end, n_iter, sum_in, sum_out);
+    } else if constexpr (I < KW) {
         constexpr int SM = (I >> 1) - 1 < T - 1 ? (I >> 1) - 1 : T - 1;
         if constexpr (I % D == 0) g = visit_group<T, D>(md, Vin, Vout, r0, I);
         sweep_iter_inner<T, I % 3, C, I % D, SM, I>(st, v[I % D], w[I % D], g, L, I, sum_end, n_iter, sum_in,
@@ -642,7 +775,7 @@ __device__ __forceinline__ void sweep_round(const RoundArgs& a) {
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = lane_id();
     const int stride = a.wave_stride;
-    int i = blockIdx.x * kWavesPerBlock + wave;
+    int i = (blockIdx.x - 1) * kWavesPerBlock + wave;   // block 0: the accounting block
     // The wave's first list entry and the round's count are loaded together,
     // with no branch between them, so both round trips overlap (the entry's
     // index is clamped into the list; the entry is used only if i < n).
@@ -676,7 +809,7 @@ __device__ __forceinline__ void sweep_round(const RoundArgs& a) {
     __shared__ int s_cnt[2][kWavesPerBlock];
     __shared__ int s_base[2];
     int par = 0;
-    for (int ib = blockIdx.x * kWavesPerBlock; ib < n; ib += stride, par ^= 1) {
+    for (int ib = (blockIdx.x - 1) * kWavesPerBlock; ib < n; ib += stride, par ^= 1) {
         i = ib + wave;
         int slot = 0, gn = 0, g = 0, ty = 0, tx = 0;
         bool won = false;
@@ -717,12 +850,13 @@ __device__ __forceinline__ void sweep_round(const RoundArgs& a) {
     }
 }
 
-// The grid has one block more than a.wave_stride covers: the last one does
-// the round's accounting (round_accounting) instead of visits.
+// The grid has one block more than a.wave_stride covers: the first one (the
+// first dispatched) does the round's accounting (round_accounting) instead
+// of visits.
 template <int T, int C>
 __global__ __launch_bounds__(kBlockThreads) void k_sweep(RoundArgs a) {
     if (a.round_base) a.round_id += *a.round_base;
-    if (blockIdx.x == gridDim.x - 1) {
+    if (blockIdx.x == 0) {
         round_accounting<0>(a);
         return;
     }
