@@ -11,6 +11,8 @@
 // handshake as the dominant cost of running one layer per call).
 
 #include <algorithm>
+#include <atomic>
+#include <condition_variable>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -20,6 +22,8 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <thread>
+#include <unistd.h>
 #include <unordered_map>
 #include <vector>
 
@@ -45,6 +49,99 @@ static omap_status_t fail(omap_status_t st, const char* fmt, ...) {
 }
 
 omap_status_t report_error(omap_status_t st, const char* message) { return fail(st, "%s", message); }
+
+// ---------------------------------------------------------------------------
+// host copies
+// ---------------------------------------------------------------------------
+
+// Large host-to-host copies (a query's occupancy into pinned staging memory,
+// a finished query's path cells out of it) split over a few worker threads:
+// one core copies about 8 GB/s, which at tens of megabytes per query is the
+// engine's largest host cost.  The workers are started on first use and live
+// until the process ends; a copy returns when every chunk is done.
+class CopyPool {
+public:
+    static CopyPool& get() {
+        static CopyPool pool;
+        return pool;
+    }
+
+    void copy(void* dst, const void* src, size_t n) {
+        const size_t chunks = std::min<size_t>(workers_.size() + 1, n / kChunkMin);
+        // (a process forked after the workers started has none of them)
+        if (chunks < 2 || getpid() != pid_) {
+            std::memcpy(dst, src, n);
+            return;
+        }
+        Batch b;
+        b.left = (int)chunks - 1;
+        const size_t per = (n / chunks + 63) & ~size_t(63);
+        {
+            std::lock_guard<std::mutex> lk(m_);
+            for (size_t k = 1; k < chunks; ++k) {
+                const size_t off = k * per;
+                if (off >= n) {
+                    --b.left;
+                    continue;
+                }
+                jobs_.push_back(Job{static_cast<char*>(dst) + off, static_cast<const char*>(src) + off,
+                                    std::min(per, n - off), &b});
+            }
+        }
+        cv_.notify_all();
+        std::memcpy(dst, src, std::min(per, n));
+        std::unique_lock<std::mutex> lk(m_);
+        done_.wait(lk, [&] { return b.left == 0; });
+    }
+
+private:
+    static constexpr size_t kChunkMin = size_t(1) << 20;
+    struct Batch {
+        int left = 0;
+    };
+    struct Job {
+        char* dst;
+        const char* src;
+        size_t n;
+        Batch* batch;
+    };
+
+    CopyPool() : pid_(getpid()) {
+        const unsigned hw = std::thread::hardware_concurrency();
+        const int n = (int)std::min(7u, hw > 2 ? hw / 2 : 0u);
+        for (int i = 0; i < n; ++i) workers_.emplace_back([this] { run(); });
+    }
+    ~CopyPool() {
+        {
+            std::lock_guard<std::mutex> lk(m_);
+            stop_ = true;
+        }
+        cv_.notify_all();
+        for (auto& t : workers_) t.join();
+    }
+    void run() {
+        std::unique_lock<std::mutex> lk(m_);
+        for (;;) {
+            cv_.wait(lk, [&] { return stop_ || !jobs_.empty(); });
+            if (jobs_.empty()) return;   // stop_ with nothing left
+            const Job j = jobs_.front();
+            jobs_.pop_front();
+            lk.unlock();
+            std::memcpy(j.dst, j.src, j.n);
+            lk.lock();
+            if (--j.batch->left == 0) done_.notify_all();
+        }
+    }
+
+    std::vector<std::thread> workers_;
+    std::mutex m_;
+    std::condition_variable cv_, done_;
+    std::deque<Job> jobs_;
+    bool stop_ = false;
+    const pid_t pid_;
+};
+
+static void host_copy(void* dst, const void* src, size_t n) { CopyPool::get().copy(dst, src, n); }
 
 #define HIP_TRY(expr)                                                                   \
     do {                                                                                \
@@ -513,7 +610,7 @@ class Solver {
         if (n == 0) return OMAP_OK;
         void* p = pin.alloc(n);
         if (p) {
-            std::memcpy(p, src, n);
+            host_copy(p, src, n);
             HIP_TRY(hipMemcpyAsync(dst, p, n, hipMemcpyHostToDevice, stream));
             HIP_TRY(pin.release_after(p, stream));
             return OMAP_OK;
@@ -2401,7 +2498,7 @@ omap_status_t omap_engine_submit_ex(omap_engine_t engine, int32_t height, int32_
     engine->occ_pool.reap(false);
     void* pinned = engine->occ_pool.alloc(n_occ);
     if (pinned) {
-        std::memcpy(pinned, occupancy_host, n_occ);
+        host_copy(pinned, occupancy_host, n_occ);
         q.occ_pinned = static_cast<uint8_t*>(pinned);
     } else {
         q.occ.assign(occupancy_host, occupancy_host + n_occ);
@@ -2526,7 +2623,7 @@ omap_status_t omap_engine_fetch(omap_engine_t engine, int64_t query_id, int32_t*
     if ((nt > 0 && !len_host) || !offsets_host) return fail(OMAP_ERR_INVALID_ARG, "len/offsets pointer is NULL");
     if (nt) std::memcpy(len_host, q.len.data(), nt * sizeof(int32_t));
     std::memcpy(offsets_host, q.off.data(), (nt + 1) * sizeof(int64_t));
-    if (total) std::memcpy(cells_host, q.cells_pinned ? q.cells_pinned : q.cells.data(), total * sizeof(int32_t));
+    if (total) host_copy(cells_host, q.cells_pinned ? q.cells_pinned : q.cells.data(), total * sizeof(int32_t));
     if (info_host) *info_host = q.info;
     if (q.cells_pinned) engine->res_pool.release_now(q.cells_pinned);
     engine->queries.erase(it);
