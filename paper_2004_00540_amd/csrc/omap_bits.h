@@ -205,14 +205,14 @@ __global__ __launch_bounds__(kBlockThreads) void k_bits(RoundArgs a) {
         const uint64_t wmask = __ballot(won);
         const int nwon = __popcll(wmask);
         if (lane == 0) s_cnt[par][wave] = nwon;
-        __syncthreads();
+        lds_barrier();
         if (threadIdx.x == 0) {
             int t = 0;
 #pragma unroll
             for (int w = 0; w < kWavesPerBlock; ++w) t += s_cnt[par][w];
             s_base[par] = t > 0 ? atomicAdd(a.count_out, t) : 0;
         }
-        __syncthreads();
+        lds_barrier();
         if (nwon > 0) {
             int base = s_base[par];
             for (int w = 0; w < wave; ++w) base += s_cnt[par][w];

@@ -89,6 +89,11 @@ struct RoundArgs {
 OMAP_SWEEP_VARIANTS(X)
 #undef X
 
+// Two-wave visits (omap_sweep_split.h): one column per lane, 16 layers per
+// visit, tiles of 16 rows; defined in the T = 16, C = 1 sweep variant.
+hipError_t launch_sweep_split_T16(const RoundArgs& a, int32_t grid, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
+int sweep_split_blocks_per_cu_T16();
+
 // Bit-sliced variants (layers per visit); omap_bits_variant.hip with OMAP_BITS_T.
 #define OMAP_BITS_VARIANTS(X) X(8) X(16)
 

@@ -170,7 +170,16 @@ struct Options {
     int check = 0;       // 0 = adaptive
     int bits = 0;        // 1 = bit-sliced reached-set schedule (C unused; TW = 1984)
     int graph = 0;       // 1 = rounds replayed from captured HIP graphs
+    int split = 0;       // 1 = two waves per tile visit (k_sweep_split: C = 1, T = TH = 16, active)
 };
+
+// Launch of one round's sweep kernel for the resolved options.
+static hipError_t launch_round_kernel(const Options& opt, const RoundArgs& a, int32_t grid, hipStream_t s,
+                                      hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
+    if (opt.bits) return launch_bits(opt.T, a, grid, s, e0, e1);
+    if (opt.split) return launch_sweep_split_T16(a, grid, s, e0, e1);
+    return launch_sweep(opt.T, opt.C, a, grid, s, e0, e1);
+}
 
 // Defaults (measured on MI355X).  A single maze under the active schedule is
 // latency-bound (a few hundred tiles per round on 1024 SIMDs): one column per
@@ -254,6 +263,9 @@ static omap_status_t resolve_options(const omap_options* o, Options* out, Use us
     if (r.TH < r.T)
         return fail(OMAP_ERR_INVALID_ARG, "tile_rows (%d) must be >= temporal_depth (%d)", r.TH, r.T);
     r.TW = 64 * r.C - 2 * r.T;
+    // a single maze with one column per lane and 16 layers on 16-row tiles
+    // (the latency-bound case) visits each tile with two waves
+    r.split = single && !dense && r.C == 1 && r.T == 16 && r.TH == 16;
     *out = r;
     return OMAP_OK;
 }
@@ -672,10 +684,15 @@ class Solver {
         HIP_TRY(hipGetDevice(&dev));
         int cus = 0;
         HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-        const int waves = opt.bits ? bits_max_waves_per_cu(opt.T) : sweep_max_waves_per_cu(opt.T, opt.C);
-        grid = std::max(1, cus * std::max(1, waves / kWavesPerBlock));
-        const int need = (cap_tiles + kWavesPerBlock - 1) / kWavesPerBlock;
-        grid = std::max(1, std::min(grid, need));
+        if (opt.split) {   // one tile per block of two waves
+            grid = std::max(1, cus * std::max(1, sweep_split_blocks_per_cu_T16()));
+            grid = std::max(1, std::min(grid, cap_tiles));
+        } else {
+            const int waves = opt.bits ? bits_max_waves_per_cu(opt.T) : sweep_max_waves_per_cu(opt.T, opt.C);
+            grid = std::max(1, cus * std::max(1, waves / kWavesPerBlock));
+            const int need = (cap_tiles + kWavesPerBlock - 1) / kWavesPerBlock;
+            grid = std::max(1, std::min(grid, need));
+        }
         HIP_TRY(hipStreamSynchronize(stream));
         return OMAP_OK;
     }
@@ -1089,14 +1106,11 @@ class Solver {
             // the events record the kernel's own start and end timestamps
             HIP_TRY(hipEventCreate(&ev.first));
             HIP_TRY(hipEventCreate(&ev.second));
-            if (opt.bits) HIP_TRY(launch_bits(opt.T, a, grid, stream, ev.first, ev.second));
-            else HIP_TRY(launch_sweep(opt.T, opt.C, a, grid, stream, ev.first, ev.second));
+            HIP_TRY(launch_round_kernel(opt, a, grid, stream, ev.first, ev.second));
             prof_events.push_back(ev);
             prof_counts.push_back(1);
-        } else if (opt.bits) {
-            HIP_TRY(launch_bits(opt.T, a, grid, stream));
         } else {
-            HIP_TRY(launch_sweep(opt.T, opt.C, a, grid, stream));
+            HIP_TRY(launch_round_kernel(opt, a, grid, stream));
         }
         ++next_round;
         parity = (int)(next_round & 1);
@@ -1122,7 +1136,7 @@ class Solver {
         a.round_id = 0;
         std::vector<char> sig(sizeof(RoundArgs) + 3 * sizeof(int));
         std::memcpy(sig.data(), &a, sizeof a);
-        const int extra[3] = {grid, opt.T, opt.C + 100 * opt.bits};
+        const int extra[3] = {grid, opt.T, opt.C + 100 * opt.bits + 1000 * opt.split};
         std::memcpy(sig.data() + sizeof a, extra, sizeof extra);
         return sig;
     }
@@ -1141,7 +1155,7 @@ class Solver {
             RoundArgs a = round_args_at(k);
             a.round_id = k;
             a.round_base = d_round_base;
-            e = opt.bits ? launch_bits(opt.T, a, grid, cap_stream) : launch_sweep(opt.T, opt.C, a, grid, cap_stream);
+            e = launch_round_kernel(opt, a, grid, cap_stream);
         }
         if (e == hipSuccess) e = launch_round_advance(d_round_base, kGraphRounds, cap_stream);
         hipGraph_t g = nullptr;

@@ -55,6 +55,16 @@ __device__ __forceinline__ int from_right_lane(int v) {
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & (kLanes - 1); }
 
+// Workgroup barrier for data exchanged through LDS only: the waves wait for
+// their own LDS operations, not for their global stores and atomics, which
+// __syncthreads also waits for (at the end of a visit that is the acknowledgement
+// of the tile's output rows, about a microsecond).
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 __device__ __forceinline__ int64_t tile_cells(const MazeDev& md, int ty, int tx, int tile_rows,
                                               int tile_cols) {
     return (int64_t)min(tile_rows, md.H - ty * tile_rows) * min(tile_cols, md.W - tx * tile_cols);
@@ -355,10 +365,10 @@ __device__ __forceinline__ void visit_bookkeeping_active(const RoundArgs& a, int
 // round, off the visiting waves' path.  BITS_T (bit-sliced schedule, its
 // layers per visit): a maze whose rounds have covered its layers below K
 // visits nothing.
-template <int BITS_T>
+template <int BITS_T, int NT = kBlockThreads>
 __device__ __forceinline__ void round_accounting(const RoundArgs& a) {
     if (threadIdx.x == 0) *a.count_clear = 0;
-    for (int m = threadIdx.x; m < a.n_slots; m += kBlockThreads) {
+    for (int m = threadIdx.x; m < a.n_slots; m += NT) {
         a.sched_clear[m] = 0;
         a.dchg_clear[m] = 0;
     }
@@ -379,7 +389,7 @@ __device__ __forceinline__ void round_accounting(const RoundArgs& a) {
         return;
     }
     unsigned long long mine = 0;
-    for (int m = threadIdx.x; m < a.n_slots; m += kBlockThreads) {
+    for (int m = threadIdx.x; m < a.n_slots; m += NT) {
         const unsigned long long v = (unsigned long long)a.sched_in[m];
         if (v > 0 && live(a.mazes[m])) {
             atomicAdd(reinterpret_cast<unsigned long long*>(&a.maze_visits[m * kSpread]), v);
@@ -829,14 +839,14 @@ __device__ __forceinline__ void sweep_round(const RoundArgs& a) {
         const uint64_t wmask = __ballot(won);
         const int nwon = __popcll(wmask);
         if (lane == 0) s_cnt[par][wave] = nwon;
-        __syncthreads();
+        lds_barrier();
         if (threadIdx.x == 0) {
             int t = 0;
 #pragma unroll
             for (int w = 0; w < kWavesPerBlock; ++w) t += s_cnt[par][w];
             s_base[par] = t > 0 ? atomicAdd(a.count_out, t) : 0;
         }
-        __syncthreads();
+        lds_barrier();
         if (nwon > 0) {
             int base = s_base[par];
             for (int w = 0; w < wave; ++w) base += s_cnt[par][w];
