@@ -36,7 +36,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0                  # MI355X HBM3E
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sweep_c3_traffic.json")
-KERNEL_SOURCES = ("omap_sweep.h", "omap_sweep_variant.hip", "omap_internal.h")
+KERNEL_SOURCES = ("omap_sweep.h", "omap_sweep_split.h", "omap_sweep_variant.hip", "omap_internal.h")
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12   # 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz, 32-bit ops
 BYTES_PER_CELL_UPDATE = 8.125          # int32 read + int32 write + 1 mask bit
 
@@ -184,7 +184,7 @@ def summarize_counters(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, out
     the counter reads for a plain pass of known size (bench.py --workload
     copy: 1 GiB read + 1 GiB written per launch)."""
     import paper_2004_00540_amd as omap
-    kern = "omap::k_sweep<"
+    kern = "omap::k_sweep_split<"
     f_kib, n = _counter_per_dispatch(fetch_dir, "FETCH_SIZE", kern)
     w_kib, _ = _counter_per_dispatch(write_dir, "WRITE_SIZE", kern)
     cf_kib, _ = _counter_per_dispatch(copy_fetch_dir, "FETCH_SIZE", "neg_kernel")
@@ -194,7 +194,7 @@ def summarize_counters(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, out
     fetch = f_kib * 1024 * f_scale
     write = w_kib * 1024 * w_scale
     out = {
-        "kernel": "omap::k_sweep<16, 1> (per-round launch)",
+        "kernel": "omap::k_sweep_split<16> (two waves per tile visit, per-round launch)",
         "workload": "config3_23170x23170_rect_overlay",
         "options": omap.resolve_options(),
         "kernel_source_sha256": kernel_source_hash(),
