@@ -1,5 +1,5 @@
 // Two-wave tile visits: the T stages of a one-column-per-lane visit split
-// between the two waves of a workgroup.
+// between the waves of a workgroup (two; three also build).
 //
 // A round of the active schedule on a single large maze has a few hundred
 // tiles for 1024 SIMDs, so its time is one visit's latency, and a visit is a
@@ -23,25 +23,41 @@
 
 #include "omap_sweep.h"
 
+// Waves per visit: 2 (three, with stages 0-3, 4-8 and 9-15, measured slower
+// on the 23170^2 maze: 6.48 vs 6.35 ms per propagation, as a 25 KB LDS ring
+// pair per tile leaves room for 1536 tiles in flight against 2048).
+#ifndef OMAP_SPLIT_WAVES
+#define OMAP_SPLIT_WAVES 2
+#endif
+
 namespace omap {
 
-constexpr int kSplitThreads = 2 * kLanes;
+// Waves per tile visit and the first stage of each wave (stage-rows balanced
+// over the trapezoid: the first stages have the most rows).
+constexpr int kSplitWaves = OMAP_SPLIT_WAVES;
+constexpr int kSplitThreads = kSplitWaves * kLanes;
 
 template <int T>
 struct SplitVisit {
-    static constexpr int S1 = 3 * T / 8;          // stages of wave A
-    static constexpr int S2 = T - S1;             // stages of wave B
+    static constexpr int NW = kSplitWaves;
+    static constexpr int first_stage(int k) {
+        return NW == 2 ? (k == 0 ? 0 : (k == 1 ? 3 * T / 8 : T))
+                       : (k == 0 ? 0 : (k == 1 ? T / 4 : (k == 2 ? 9 * T / 16 : T)));
+    }
+    static constexpr int S1 = first_stage(1);     // stages of wave A
     static constexpr int NSTEP = 3 * T;           // row steps of a tile with TH = T
     static constexpr int D = SweepPrefetch<T, 1>::D;
+    static_assert(NW == 2 || NW == 3, "two or three waves per visit");
     static_assert(NSTEP % 2 == 0 && D % 6 == 0, "split visit steps");
 };
 
-// LDS of one split visit.
+// LDS of one split visit: ring k carries the rows emitted by the last stage
+// of wave k to wave k + 1.
 template <int T>
 struct SplitShared {
-    int32_t ring[SplitVisit<T>::NSTEP][kLanes];   // row emitted by stage S1-1 at step i
+    int32_t ring[kSplitWaves - 1][SplitVisit<T>::NSTEP][kLanes];
     uint64_t sum_in[kLanes];                      // wave A's input sums
-    int32_t ready;                                // ring rows written (a count of steps)
+    int32_t ready[kSplitWaves - 1];               // rows written to ring k (a count of steps)
     int32_t done;                                 // 1 once sum_in is written
 };
 
@@ -101,9 +117,9 @@ __device__ __forceinline__ void split_a_pair(uint32_t (&st)[SplitVisit<T>::S1][3
     uint32_t out0[1] = {}, out1[1] = {};
     sweep_row2<S1, P, 1, SM>(st, c1, out0, out1);
     if constexpr (I + 1 >= 2 * S1) {
-        if constexpr (I >= 2 * S1) sh.ring[I][lane_id()] = (int32_t)out0[0];
-        sh.ring[I + 1][lane_id()] = (int32_t)out1[0];
-        lds_publish(&sh.ready, I + 2);
+        if constexpr (I >= 2 * S1) sh.ring[0][I][lane_id()] = (int32_t)out0[0];
+        sh.ring[0][I + 1][lane_id()] = (int32_t)out1[0];
+        lds_publish(&sh.ready[0], I + 2);
     }
 }
 
@@ -150,27 +166,30 @@ __device__ __forceinline__ void split_wave_a(const MazeDev& md, int r0, int r_en
     lds_publish(&sh.done, 1);
 }
 
-// Wave B, row steps I and I + 1: stages S1 .. T-1 on the rows wave A handed
-// over (read one pair ahead), stores of the tile's output rows.
-template <int T, int I>
-__device__ __forceinline__ void split_b_pair(uint32_t (&st)[SplitVisit<T>::S2][3][1], int32_t (&nxt)[2],
-                                             __amdgpu_buffer_rsrc_t stv, const VisitLane& L, int rows,
-                                             uint64_t& sum_out, SplitShared<T>& sh, int32_t& seen) {
+// Wave K >= 1, row steps I and I + 1: stages first_stage(K) .. first_stage(K
+// + 1) - 1 on the rows the previous wave handed over (read one pair ahead);
+// the last wave stores the tile's output rows, the others hand their rows on.
+template <int T, int K, int I>
+__device__ __forceinline__ void split_c_pair(
+    uint32_t (&st)[SplitVisit<T>::first_stage(K + 1) - SplitVisit<T>::first_stage(K)][3][1], int32_t (&nxt)[2],
+    __amdgpu_buffer_rsrc_t stv, const VisitLane& L, int rows, uint64_t& sum_out, SplitShared<T>& sh,
+    int32_t& seen) {
     using SV = SplitVisit<T>;
-    constexpr int S1 = SV::S1, S2 = SV::S2;
+    constexpr int B0 = SV::first_stage(K), B1 = SV::first_stage(K + 1), S = B1 - B0;
+    constexpr bool LAST = K == SV::NW - 1;
     constexpr int P = I % 3;
-    constexpr int SMG = (I >> 1) - 1 - S1;     // last active stage of B (local index), if >= 0
-    constexpr int SM = SMG < S2 - 1 ? SMG : S2 - 1;
+    constexpr int SMG = (I >> 1) - 1 - B0;     // last active stage of this wave (local index), if >= 0
+    constexpr int SM = SMG < S - 1 ? SMG : S - 1;
     st[0][P][0] = (uint32_t)nxt[0];
     uint32_t c1[1] = {(uint32_t)nxt[1]};
     if constexpr (I + 2 < SV::NSTEP) {
-        lds_wait_at_least(&sh.ready, I + 4, seen);
-        nxt[0] = sh.ring[I + 2][lane_id()];
-        nxt[1] = sh.ring[I + 3][lane_id()];
+        lds_wait_at_least(&sh.ready[K - 1], I + 4, seen);
+        nxt[0] = sh.ring[K - 1][I + 2][lane_id()];
+        nxt[1] = sh.ring[K - 1][I + 3][lane_id()];
     }
     uint32_t out0[1] = {}, out1[1] = {};
-    sweep_row2<S2, P, 1, SM>(st, c1, out0, out1);
-    if constexpr (I >= 2 * T) {
+    sweep_row2<S, P, 1, SM>(st, c1, out0, out1);
+    if constexpr (LAST && I >= 2 * T) {
         // rows at or past the tile's `rows` (a tile cut by the maze's bottom
         // edge) lie outside the store resource and are left out of the sums
         // (the row offset is in the lane offset, which the range check covers)
@@ -179,56 +198,80 @@ __device__ __forceinline__ void split_b_pair(uint32_t (&st)[SplitVisit<T>::S2][3
         bstore<1>(stv, L.soff + (I + 1 - 2 * T) * L.vrow, 0, v1i32{(int)o1});
         sum_out += (I - 2 * T < rows ? (uint64_t)o0 : 0) + (I + 1 - 2 * T < rows ? (uint64_t)o1 : 0);
     }
-}
-
-template <int T, int I = 2 * SplitVisit<T>::S1>
-__device__ __forceinline__ void split_b_steps(uint32_t (&st)[SplitVisit<T>::S2][3][1], int32_t (&nxt)[2],
-                                              __amdgpu_buffer_rsrc_t stv, const VisitLane& L, int rows,
-                                              uint64_t& sum_out, SplitShared<T>& sh, int32_t& seen) {
-    if constexpr (I < SplitVisit<T>::NSTEP) {
-        split_b_pair<T, I>(st, nxt, stv, L, rows, sum_out, sh, seen);
-        split_b_steps<T, I + 2>(st, nxt, stv, L, rows, sum_out, sh, seen);
+    if constexpr (!LAST && I + 1 >= 2 * B1) {
+        if constexpr (I >= 2 * B1) sh.ring[K][I][lane_id()] = (int32_t)out0[0];
+        sh.ring[K][I + 1][lane_id()] = (int32_t)out1[0];
+        lds_publish(&sh.ready[K], I + 2);
     }
 }
 
-// The visit of a tile with TH = T by both waves (wave 0 = A, wave 1 = B);
-// returns (wave-uniform, in wave B) whether the interior changed.
+template <int T, int K, int I = 2 * SplitVisit<T>::first_stage(K)>
+__device__ __forceinline__ void split_c_steps(
+    uint32_t (&st)[SplitVisit<T>::first_stage(K + 1) - SplitVisit<T>::first_stage(K)][3][1], int32_t (&nxt)[2],
+    __amdgpu_buffer_rsrc_t stv, const VisitLane& L, int rows, uint64_t& sum_out, SplitShared<T>& sh,
+    int32_t& seen) {
+    if constexpr (I < SplitVisit<T>::NSTEP) {
+        split_c_pair<T, K, I>(st, nxt, stv, L, rows, sum_out, sh, seen);
+        split_c_steps<T, K, I + 2>(st, nxt, stv, L, rows, sum_out, sh, seen);
+    }
+}
+
+// Wave K >= 1's part of a visit; the last wave returns (wave-uniform) whether
+// the interior changed.
+template <int T, int K>
+__device__ __forceinline__ bool split_wave_c(const MazeDev& md, int r0, const VisitLane& L, int32_t* Vout,
+                                             SplitShared<T>& sh) {
+    using SV = SplitVisit<T>;
+    constexpr int B0 = SV::first_stage(K), S = SV::first_stage(K + 1) - B0;
+    uint32_t st[S][3][1];
+#pragma unroll
+    for (int s = 0; s < S; ++s)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) st[s][k][0] = kObstacleBit;
+    const int rows = min(r0 + T, md.H) - r0;
+    const __amdgpu_buffer_rsrc_t stv = raw_rsrc(Vout + (int64_t)r0 * md.pitch, rows * md.pitch * 4);
+    int32_t seen = 0;
+    int32_t nxt[2];
+    lds_wait_at_least(&sh.ready[K - 1], 2 * B0 + 2, seen);
+    nxt[0] = sh.ring[K - 1][2 * B0][lane_id()];
+    nxt[1] = sh.ring[K - 1][2 * B0 + 1][lane_id()];
+    uint64_t sum_out = 0;
+    split_c_steps<T, K>(st, nxt, stv, L, rows, sum_out, sh, seen);
+    if constexpr (K == SV::NW - 1) {
+        int32_t fin = 0;
+        lds_wait_at_least(&sh.done, 1, fin);
+        const uint64_t sum_in = sh.sum_in[lane_id()];
+        return __ballot(L.inner && sum_in != sum_out) != 0;
+    }
+    return false;
+}
+
+// The visit of a tile with TH = T by the workgroup's waves (wave 0 = A);
+// returns (wave-uniform, in the last wave) whether the interior changed.
 // on_start() runs in wave A once its first D rows' loads are issued.
 template <int T, class OnStart>
 __device__ __forceinline__ bool split_visit(int wave, const MazeDev& md, int r0, int col, const VisitLane& L,
                                             const int32_t* Vin, int32_t* Vout, SplitShared<T>& sh,
                                             OnStart& on_start) {
     using SV = SplitVisit<T>;
-    const int r_end = min(r0 + T, md.H);
     if (wave == 0) {
+        const int r_end = min(r0 + T, md.H);
         if (r0 >= T && (int64_t)r0 + T + T + 2 * SV::D <= md.H)
             split_wave_a<T, false>(md, r0, r_end, col, L, Vin, sh, on_start);
         else
             split_wave_a<T, true>(md, r0, r_end, col, L, Vin, sh, on_start);
         return false;
     }
-    uint32_t st[SV::S2][3][1];
-#pragma unroll
-    for (int s = 0; s < SV::S2; ++s)
-#pragma unroll
-        for (int k = 0; k < 3; ++k) st[s][k][0] = kObstacleBit;
-    const int rows = r_end - r0;
-    const __amdgpu_buffer_rsrc_t stv = raw_rsrc(Vout + (int64_t)r0 * md.pitch, rows * md.pitch * 4);
-    int32_t seen = 0;
-    int32_t nxt[2];
-    lds_wait_at_least(&sh.ready, 2 * SV::S1 + 2, seen);
-    nxt[0] = sh.ring[2 * SV::S1][lane_id()];
-    nxt[1] = sh.ring[2 * SV::S1 + 1][lane_id()];
-    uint64_t sum_out = 0;
-    split_b_steps<T>(st, nxt, stv, L, rows, sum_out, sh, seen);
-    int32_t fin = 0;
-    lds_wait_at_least(&sh.done, 1, fin);
-    const uint64_t sum_in = sh.sum_in[lane_id()];
-    return __ballot(L.inner && sum_in != sum_out) != 0;
+    if constexpr (SV::NW == 3) {
+        if (wave == 1) return split_wave_c<T, 1>(md, r0, L, Vout, sh);
+        return split_wave_c<T, 2>(md, r0, L, Vout, sh);
+    } else {
+        return split_wave_c<T, 1>(md, r0, L, Vout, sh);
+    }
 }
 
-// A round of the active schedule with two waves per tile (block 0: the
-// round's accounting).  a.wave_stride counts tiles (visiting blocks).
+// A round of the active schedule with kSplitWaves waves per tile (block 0:
+// the round's accounting).  a.wave_stride counts tiles (visiting blocks).
 template <int T>
 __global__ __launch_bounds__(kSplitThreads) void k_sweep_split(RoundArgs a) {
     if (a.round_base) a.round_id += *a.round_base;
@@ -247,7 +290,8 @@ __global__ __launch_bounds__(kSplitThreads) void k_sweep_split(RoundArgs a) {
     uint64_t e = e0;
     const int n = __builtin_amdgcn_readfirstlane(cnt);
     if (threadIdx.x == 0) {
-        sh.ready = 0;
+#pragma unroll
+        for (int k = 0; k < kSplitWaves - 1; ++k) sh.ready[k] = 0;
         sh.done = 0;
     }
     lds_barrier();
@@ -282,9 +326,9 @@ __global__ __launch_bounds__(kSplitThreads) void k_sweep_split(RoundArgs a) {
             int32_t* const Vout = a.parity ? md.V[0] : md.V[1];
             changed = split_visit<T>(wave, md, r0, col, L, Vin, Vout, sh, on_start);
         }
-        // wave B, which knows the result, claims the 3x3 tiles around the
-        // tile for the next round and reserves their list entries
-        if (wave == 1 && changed) {
+        // the last wave, which knows the result, claims the 3x3 tiles around
+        // the tile for the next round and reserves their list entries
+        if (wave == kSplitWaves - 1 && changed) {
             const int ny = ty + lane / 3 - 1, nx = tx + lane % 3 - 1;
             const int gn = md.tile_base + ny * md.tiles_x + nx;
             bool won = false;
@@ -307,7 +351,8 @@ __global__ __launch_bounds__(kSplitThreads) void k_sweep_split(RoundArgs a) {
         // both waves are done with this tile's LDS before it is reset
         lds_barrier();
         if (threadIdx.x == 0) {
-            sh.ready = 0;
+#pragma unroll
+            for (int k = 0; k < kSplitWaves - 1; ++k) sh.ready[k] = 0;
             sh.done = 0;
         }
         lds_barrier();
