@@ -64,6 +64,19 @@ def test_edge_shapes(shape):
                 assert_same(m, got, oracle_solution(m, L), f"{shape} L={L} T={T} C={C}")
 
 
+@pytest.mark.parametrize("shape", [(1, 1), (1, 1000), (1000, 1), (15, 40), (17, 33), (33, 31), (56, 100),
+                                   (57, 100), (72, 65), (73, 97), (130, 449)])
+def test_edge_shapes_two_wave_visits(shape):
+    # the single-maze defaults (one column per lane, 16 layers, 16-row tiles)
+    # visit each tile with two waves; near the top and bottom edges wave A
+    # clamps rows and wave B drops rows cut by the edge
+    H, W = shape
+    for seed in range(3):
+        m = workloads.random_maze(H, W, 0.25, 2, 10, 9100 + seed * 7 + H)
+        for L in (-1, 0, 1, 5, 40):
+            assert_same(m, run_plan(m, L), oracle_solution(m, L), f"{shape} L={L} default options")
+
+
 def test_sources_on_borders_and_corners():
     H, W = 97, 301
     occ = workloads.bernoulli(H, W, 0.2, 55)
