@@ -146,10 +146,13 @@ hipError_t launch_reduce(const MazeDev* mazes, const int32_t* tile_maze, const u
                          unsigned long long* maze_reached, hipStream_t s);
 hipError_t launch_path_lengths(const MazeDev* mazes, const int32_t* tgt_slot, const int32_t* tgt_rc,
                                int32_t n_tgt, int32_t parity, int32_t* len, hipStream_t s);
-hipError_t launch_scan_offsets(const int32_t* len, int32_t n, int64_t* offsets, hipStream_t s);
+// order (optional): receives the targets by path length, longest first
+hipError_t launch_scan_offsets(const int32_t* len, int32_t n, int64_t* offsets, hipStream_t s,
+                               int32_t* order = nullptr);
+// order (optional): the walk's order of the targets (from launch_scan_offsets)
 hipError_t launch_walk(const MazeDev* mazes, const int32_t* tgt_slot, const int32_t* tgt_rc,
                        int32_t n_tgt, int32_t parity, const int32_t* len, const int64_t* offsets,
-                       int32_t* cells, hipStream_t s);
+                       int32_t* cells, hipStream_t s, const int32_t* order = nullptr);
 hipError_t launch_walk_random(const MazeDev* mazes, const int32_t* tgt_slot, const int32_t* tgt_rc,
                               const int32_t* tgt_local, int32_t n_tgt, int32_t parity, uint64_t seed,
                               const int32_t* len, const int64_t* offsets, int32_t* cells, hipStream_t s);

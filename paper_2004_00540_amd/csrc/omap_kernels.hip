@@ -249,8 +249,12 @@ __global__ void k_path_lengths(const MazeDev* __restrict__ mazes, const int32_t*
     len[i] = v > 0 ? md.K - v : -1;
 }
 
+// Offsets of the paths (exclusive scan of length + 1 over reached targets),
+// and optionally an order of the targets by path length, longest first (by
+// the length's bit width: a bucket order, not a full sort), so that the walk
+// starts the paths that take longest before the others.
 __global__ __launch_bounds__(1024) void k_scan(const int32_t* __restrict__ len, int32_t n,
-                                               int64_t* __restrict__ off) {
+                                               int64_t* __restrict__ off, int32_t* __restrict__ order) {
     __shared__ int64_t part[1024];
     const int t = threadIdx.x;
     const int chunk = (n + 1023) / 1024;
@@ -271,6 +275,24 @@ __global__ __launch_bounds__(1024) void k_scan(const int32_t* __restrict__ len, 
         base += len[i] >= 0 ? (int64_t)len[i] + 1 : 0;
         off[i + 1] = base;
     }
+    if (order == nullptr) return;
+    __shared__ int bucket[33];
+    if (t < 33) bucket[t] = 0;
+    __syncthreads();
+    // key 0 = the longest lengths (32 - bit width of len + 1; unreached last)
+    auto key = [&](int i) { return len[i] < 0 ? 32 : __clz(len[i] + 1); };
+    for (int i = b; i < e; ++i) atomicAdd(&bucket[key(i)], 1);
+    __syncthreads();
+    if (t == 0) {
+        int acc = 0;
+        for (int k = 0; k < 33; ++k) {
+            const int c = bucket[k];
+            bucket[k] = acc;
+            acc += c;
+        }
+    }
+    __syncthreads();
+    for (int i = b; i < e; ++i) order[atomicAdd(&bucket[key(i)], 1)] = i;
 }
 
 __device__ __forceinline__ int dir_dr(int k) { return k < 3 ? -1 : (k < 5 ? 0 : 1); }
@@ -313,12 +335,14 @@ constexpr uint64_t kNbr = 0x70507ull;
 __global__ __launch_bounds__(kLanes * kWalkWaves) void k_walk(
     const MazeDev* __restrict__ mazes, const int32_t* __restrict__ tslot, const int32_t* __restrict__ trc,
     int32_t n, int32_t parity, const int32_t* __restrict__ len, const int64_t* __restrict__ off,
-    int32_t* __restrict__ cells) {
+    int32_t* __restrict__ cells, const int32_t* __restrict__ order) {
     __shared__ __attribute__((aligned(16))) int32_t win_all[kWalkWaves][kWinRows * kWinCols];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = lane_id();
-    const int i = blockIdx.x * kWalkWaves + wave;
-    if (i >= n) return;
+    const int w = blockIdx.x * kWalkWaves + wave;
+    if (w >= n) return;
+    // (order: longest paths first, see k_scan)
+    const int i = order ? __builtin_amdgcn_readfirstlane(order[w]) : w;
     const int steps = __builtin_amdgcn_readfirstlane(len[i]);
     if (steps < 0) return;
     const int slot = __builtin_amdgcn_readfirstlane(tslot[i]);
@@ -344,6 +368,9 @@ __global__ __launch_bounds__(kLanes * kWalkWaves) void k_walk(
         const int lr0 = dr_prev < 0 ? kWinRows - 5 : (dr_prev > 0 ? 3 : kWinRows / 2);
         const int lc0 = dc_prev < 0 ? 56 : (dc_prev > 0 ? 3 : 30);
         const int R0 = r - lr0, C0 = (c - lc0) & ~3;
+        // every chunk's load is issued before the first is used, so the
+        // window costs one global round trip
+        v4i32 ld[kWinChunks / kLanes];
 #pragma unroll
         for (int k = 0; k < kWinChunks / kLanes; ++k) {
             const int q = lane + kLanes * k;
@@ -351,11 +378,18 @@ __global__ __launch_bounds__(kLanes * kWalkWaves) void k_walk(
             const int R = R0 + wr, cs = C0 + wc;
             const bool rok = R >= 0 && R < md.H;
             const bool cok = cs >= 0 && cs < md.pitch;   // a chunk lies wholly inside or outside a row
-            const v4i32 v = *(const __attribute__((address_space(1))) v4i32*)(
-                V + (int64_t)(rok ? R : 0) * md.pitch + (cok ? cs : 0));
+            ld[k] = *(const __attribute__((address_space(1))) v4i32*)(V + (int64_t)(rok ? R : 0) * md.pitch +
+                                                                      (cok ? cs : 0));
+        }
+#pragma unroll
+        for (int k = 0; k < kWinChunks / kLanes; ++k) {
+            const int q = lane + kLanes * k;
+            const int wr = q >> 4, wc = 4 * (q & 15);
+            const int R = R0 + wr, cs = C0 + wc;
+            const bool rok = R >= 0 && R < md.H;
             v4i32 m;
 #pragma unroll
-            for (int e = 0; e < 4; ++e) m[e] = (rok && cs + e >= 0 && cs + e < md.W) ? v[e] : -1;
+            for (int e = 0; e < 4; ++e) m[e] = (rok && cs + e >= 0 && cs + e < md.W) ? ld[k][e] : -1;
             *(__attribute__((address_space(3))) v4i32*)(win + wr * kWinCols + wc) = m;
         }
         // the same wave reads what its lanes wrote: LDS operations of a wave
@@ -739,17 +773,17 @@ hipError_t launch_path_lengths(const MazeDev* mazes, const int32_t* tgt_slot, co
     return hipGetLastError();
 }
 
-hipError_t launch_scan_offsets(const int32_t* len, int32_t n, int64_t* offsets, hipStream_t s) {
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, len, n, offsets);
+hipError_t launch_scan_offsets(const int32_t* len, int32_t n, int64_t* offsets, hipStream_t s, int32_t* order) {
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, len, n, offsets, order);
     return hipGetLastError();
 }
 
 hipError_t launch_walk(const MazeDev* mazes, const int32_t* tgt_slot, const int32_t* tgt_rc,
                        int32_t n_tgt, int32_t parity, const int32_t* len, const int64_t* offsets,
-                       int32_t* cells, hipStream_t s) {
+                       int32_t* cells, hipStream_t s, const int32_t* order) {
     if (n_tgt <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_walk, dim3((n_tgt + kWalkWaves - 1) / kWalkWaves), dim3(kLanes * kWalkWaves), 0, s,
-                       mazes, tgt_slot, tgt_rc, n_tgt, parity, len, offsets, cells);
+                       mazes, tgt_slot, tgt_rc, n_tgt, parity, len, offsets, cells, order);
     return hipGetLastError();
 }
 

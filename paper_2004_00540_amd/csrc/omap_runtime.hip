@@ -1400,12 +1400,12 @@ class Solver {
         auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
         const size_t b_i = up(sizeof(int32_t) * (n + 1)), b_rc = up(sizeof(int32_t) * (2 * n + 2));
         const size_t b_off = up(sizeof(int64_t) * (n + 1)), b_ss = up(sizeof(int32_t) * (ssorted.size() + 2));
-        // layout: tslot | trc | tlocal | len | off | sbase | scount | ssorted | (cells for host_out)
-        const size_t fixed = b_i + b_rc + b_i + b_i + b_off + b_i + b_i + b_ss;
+        // layout: tslot | trc | tlocal | len | off | sbase | scount | ssorted | order | (cells for host_out)
+        const size_t fixed = b_i + b_rc + b_i + b_i + b_off + b_i + b_i + b_ss + b_i;
         char* base = nullptr;
         OK_TRY(scratch(fixed, &base));
         auto carve = [&](char* b) {
-            struct P { int32_t *tslot, *trc, *tlocal, *len; int64_t* off; int32_t *sbase, *scount, *ss; char* end; } q;
+            struct P { int32_t *tslot, *trc, *tlocal, *len; int64_t* off; int32_t *sbase, *scount, *ss, *order; char* end; } q;
             q.tslot = reinterpret_cast<int32_t*>(b); b += b_i;
             q.trc = reinterpret_cast<int32_t*>(b); b += b_rc;
             q.tlocal = reinterpret_cast<int32_t*>(b); b += b_i;
@@ -1414,6 +1414,7 @@ class Solver {
             q.sbase = reinterpret_cast<int32_t*>(b); b += b_i;
             q.scount = reinterpret_cast<int32_t*>(b); b += b_i;
             q.ss = reinterpret_cast<int32_t*>(b); b += b_ss;
+            q.order = reinterpret_cast<int32_t*>(b); b += b_i;
             q.end = b;
             return q;
         };
@@ -1434,7 +1435,7 @@ class Solver {
                 else
                     HIP_TRY(launch_path_lengths(d_mazes, d.tslot, d.trc, n, vparity(), d.len, stream));
             }
-            HIP_TRY(launch_scan_offsets(d.len, n, d.off, stream));
+            HIP_TRY(launch_scan_offsets(d.len, n, d.off, stream, mode == 0 ? d.order : nullptr));
             return OMAP_OK;
         };
         OK_TRY(lengths(q));
@@ -1464,7 +1465,7 @@ class Solver {
         else if (mode == 1)
             HIP_TRY(launch_walk_random(d_mazes, q.tslot, q.trc, q.tlocal, n, vparity(), seed, q.len, q.off, walk_dst, stream));
         else
-            HIP_TRY(launch_walk(d_mazes, q.tslot, q.trc, n, vparity(), q.len, q.off, walk_dst, stream));
+            HIP_TRY(launch_walk(d_mazes, q.tslot, q.trc, n, vparity(), q.len, q.off, walk_dst, stream, q.order));
         const hipMemcpyKind kind = host_out ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
         if (src_out)
             HIP_TRY(launch_source_index(d_mazes, q.tslot, n, q.len, q.off, walk_dst, q.ss, q.sbase, q.scount,
