@@ -163,6 +163,12 @@ __device__ bool bits_tile(const MazeDev& md, int ty, int tx, int tile_rows, int 
 // visited any more.
 template <int T>
 __global__ __launch_bounds__(kBlockThreads) void k_bits(RoundArgs a) {
+    // first list entry and count issued before anything else (see k_sweep)
+    int i = ((int)blockIdx.x - 1) * kWavesPerBlock + (int)(threadIdx.x >> 6);   // block 0: the accounting block
+    const int ie = i >= 0 && i < a.n_tile_ids ? i : 0;
+    uint64_t e = __hip_atomic_load(reinterpret_cast<const uint64_t*>(a.list_in + 2 * ie), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+    const int cnt = __hip_atomic_load(a.count_in, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     if (a.round_base) a.round_id += *a.round_base;
     if (blockIdx.x == 0) {   // the accounting block (see k_sweep)
         round_accounting<T>(a);
@@ -171,10 +177,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_bits(RoundArgs a) {
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = lane_id();
     const int stride = a.wave_stride;
-    int i = (blockIdx.x - 1) * kWavesPerBlock + wave;   // block 0: the accounting block
-    uint64_t e = 0;
-    if (i < a.n_tile_ids) e = *reinterpret_cast<const uint64_t*>(a.list_in + 2 * i);
-    const int n = __builtin_amdgcn_readfirstlane(*a.count_in);
+    const int n = __builtin_amdgcn_readfirstlane(cnt);
     __shared__ int s_cnt[2][kWavesPerBlock];
     __shared__ int s_base[2];
     int par = 0;

@@ -780,22 +780,14 @@ __device__ __forceinline__ bool visit_tile(const RoundArgs& a, int g, int slot, 
 // round r+1.  Dense schedule: every tile of each maze that changed in round
 // r-1; a changed tile flags its maze for round r+1.  Block 0 also clears the
 // buffers round r+1 will fill.
+// e0 (this wave's first list entry) and cnt (the round's count) were loaded
+// by the kernel before anything else (see k_sweep).
 template <int T, int C>
-__device__ __forceinline__ void sweep_round(const RoundArgs& a) {
+__device__ __forceinline__ void sweep_round(const RoundArgs& a, uint64_t e0, int cnt) {
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = lane_id();
     const int stride = a.wave_stride;
     int i = (blockIdx.x - 1) * kWavesPerBlock + wave;   // block 0: the accounting block
-    // The wave's first list entry and the round's count are loaded together,
-    // with no branch between them, so both round trips overlap (the entry's
-    // index is clamped into the list; the entry is used only if i < n).
-    // (relaxed atomic loads of workgroup scope: plain cached loads that the
-    // compiler keeps where they are written instead of sinking the count's
-    // load into the branch that uses it; the previous round's writes are
-    // visible across the kernel boundary)
-    const uint64_t e0 = __hip_atomic_load(reinterpret_cast<const uint64_t*>(a.list_in + 2 * (i < a.n_tile_ids ? i : 0)),
-                                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-    const int cnt = __hip_atomic_load(a.count_in, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     uint64_t e = e0;
     const int n = a.dense ? a.n_tile_ids : __builtin_amdgcn_readfirstlane(cnt);
     if (a.dense) {
@@ -865,12 +857,24 @@ __device__ __forceinline__ void sweep_round(const RoundArgs& a) {
 // of visits.
 template <int T, int C>
 __global__ __launch_bounds__(kBlockThreads) void k_sweep(RoundArgs a) {
+    // This wave's first list entry and the round's count start the round's
+    // longest chain of dependent loads: they are issued before anything else,
+    // together, with no branch between them (the entry's index is clamped
+    // into the list and the entry used only if it is below the count; relaxed
+    // atomic loads of workgroup scope are plain cached loads that the
+    // compiler keeps where they are written; the previous round's writes are
+    // visible across the kernel boundary).
+    const int i = ((int)blockIdx.x - 1) * kWavesPerBlock + (int)(threadIdx.x >> 6);
+    const int ie = i >= 0 && i < a.n_tile_ids ? i : 0;
+    const uint64_t e0 = __hip_atomic_load(reinterpret_cast<const uint64_t*>(a.list_in + 2 * ie), __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_WORKGROUP);
+    const int cnt = __hip_atomic_load(a.count_in, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     if (a.round_base) a.round_id += *a.round_base;
     if (blockIdx.x == 0) {
         round_accounting<0>(a);
         return;
     }
-    sweep_round<T, C>(a);
+    sweep_round<T, C>(a, e0, cnt);
 }
 
 // Launch functions of one variant (defined in its own translation unit).

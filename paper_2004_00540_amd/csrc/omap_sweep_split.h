@@ -274,6 +274,15 @@ __device__ __forceinline__ bool split_visit(int wave, const MazeDev& md, int r0,
 // the round's accounting).  a.wave_stride counts tiles (visiting blocks).
 template <int T>
 __global__ __launch_bounds__(kSplitThreads) void k_sweep_split(RoundArgs a) {
+    // The block's first list entry and the round's count are the start of
+    // the round's longest chain of dependent loads: they are issued before
+    // anything else (the entry index is clamped into the list; block 0, the
+    // accounting block, reads entry 0 and ignores it).
+    int i = (int)blockIdx.x - 1;
+    const int ie = i >= 0 && i < a.n_tile_ids ? i : 0;
+    const uint64_t e0 = __hip_atomic_load(reinterpret_cast<const uint64_t*>(a.list_in + 2 * ie), __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_WORKGROUP);
+    const int cnt = __hip_atomic_load(a.count_in, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     if (a.round_base) a.round_id += *a.round_base;
     if (blockIdx.x == 0) {
         round_accounting<0, kSplitThreads>(a);
@@ -283,10 +292,6 @@ __global__ __launch_bounds__(kSplitThreads) void k_sweep_split(RoundArgs a) {
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = lane_id();
     const int stride = a.wave_stride;
-    int i = blockIdx.x - 1;
-    const uint64_t e0 = __hip_atomic_load(reinterpret_cast<const uint64_t*>(a.list_in + 2 * (i < a.n_tile_ids ? i : 0)),
-                                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-    const int cnt = __hip_atomic_load(a.count_in, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     uint64_t e = e0;
     const int n = __builtin_amdgcn_readfirstlane(cnt);
     if (threadIdx.x == 0) {
