@@ -283,6 +283,9 @@ __global__ __launch_bounds__(kSplitThreads) void k_sweep_split(RoundArgs a) {
     const uint64_t e0 = __hip_atomic_load(reinterpret_cast<const uint64_t*>(a.list_in + 2 * ie), __ATOMIC_RELAXED,
                                           __HIP_MEMORY_SCOPE_WORKGROUP);
     const int cnt = __hip_atomic_load(a.count_in, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    // the one maze's description, read while those loads are in flight
+    const MazeDev md_one = a.md0;
+    const bool one = a.n_slots == 1;
     if (a.round_base) a.round_id += *a.round_base;
     if (blockIdx.x == 0) {
         round_accounting<0, kSplitThreads>(a);
@@ -304,7 +307,7 @@ __global__ __launch_bounds__(kSplitThreads) void k_sweep_split(RoundArgs a) {
         const int g = __builtin_amdgcn_readfirstlane((int)(uint32_t)e);
         const int slot = __builtin_amdgcn_readfirstlane((int)(uint32_t)(e >> 32));
         if (i + stride < n) e = *reinterpret_cast<const uint64_t*>(a.list_in + 2 * (i + stride));
-        const MazeDev md = a.n_slots == 1 ? a.md0 : a.mazes[slot];
+        const MazeDev md = one ? md_one : a.mazes[slot];
         const int lt = g - md.tile_base;
         const int ty = lt / md.tiles_x, tx = lt - ty * md.tiles_x;
         auto on_start = [&]() {
