@@ -66,10 +66,11 @@ __device__ __forceinline__ void lds_publish(int32_t* p, int32_t v) {
 }
 
 // Waits until *p >= need (wave-uniform); `seen` caches the last value read.
-// Wave A never waits on wave B, so the wait ends; the spin bound only keeps
-// a broken invariant from hanging the GPU.
+// The waves of a workgroup run (and are suspended) together and wave A never
+// waits on a later wave, so the wait ends within a visit (microseconds); the
+// spin bound (about 30 ms) only keeps a broken invariant from hanging the GPU.
 __device__ __forceinline__ void lds_wait_at_least(const int32_t* p, int32_t need, int32_t& seen) {
-    for (int spin = 0; seen < need && spin < (1 << 16); ++spin) {
+    for (int spin = 0; seen < need && spin < (1 << 20); ++spin) {
         seen = __builtin_amdgcn_readfirstlane(__hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP));
         if (seen < need) __builtin_amdgcn_s_sleep(1);
     }
