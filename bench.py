@@ -39,6 +39,13 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sweep_c3_traffic.json")
 KERNEL_SOURCES = ("omap_sweep.h", "omap_sweep_split.h", "omap_sweep_variant.hip", "omap_internal.h")
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12   # 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz, 32-bit ops
 BYTES_PER_CELL_UPDATE = 8.125          # int32 read + int32 write + 1 mask bit
+LDS_FILE = os.path.join(ROOT, "profiles", "lds_c3_23170.json")
+LDS_SOURCES = KERNEL_SOURCES + ("omap_kernels.hip",)
+# LDS: 256 CUs x 128 B per clock (32 banks of 4 B) x 2.4 GHz
+LDS_PEAK_GBS = 256 * 128 * 2.4
+# kernels whose LDS use is summarized: (part of the name in the counter files, label)
+LDS_KERNELS = (("omap::k_sweep_split<", "k_sweep_split<16>"), ("omap::k_walk(", "k_walk"))
+LDS_COUNTERS = ("SQ_INSTS_LDS", "SQ_LDS_IDX_ACTIVE", "SQ_LDS_BANK_CONFLICT", "SQ_WAVES")
 
 
 def log(*a):
@@ -129,10 +136,10 @@ def cpu_baseline(m, gpu_step_s: float, gpu_cell_updates: int, effective_layers: 
     }
 
 
-def kernel_source_hash() -> str:
+def kernel_source_hash(files=KERNEL_SOURCES) -> str:
     import hashlib
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in files:
         with open(os.path.join(ROOT, "paper_2004_00540_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
@@ -174,7 +181,7 @@ def _counter_per_dispatch(directory: str, counter: str, kernel_part: str):
         key = r.get("Dispatch_Id") or r.get("Correlation_Id")
         vals[key] = vals.get(key, 0.0) + float(r["Counter_Value"])
     if not vals:
-        raise SystemExit(f"no {counter} rows for {kernel_prefix} under {directory}")
+        raise SystemExit(f"no {counter} rows for {kernel_part} under {directory}")
     return sum(vals.values()) / len(vals), len(vals)
 
 
@@ -211,6 +218,99 @@ def summarize_counters(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, out
     with open(out_path, "w") as f:
         json.dump(out, f, indent=1)
     print(json.dumps(out))
+
+
+def _kernel_avg_us(trace_dir: str, kernel_part: str) -> float:
+    """Average duration of the kernels whose name contains kernel_part in a
+    rocprofv3 --kernel-trace --stats run (kernel_stats.csv)."""
+    calls, total_ns = 0, 0.0
+    for r in _csv_rows(trace_dir, "kernel_stats.csv"):
+        if kernel_part in r["Name"]:
+            calls += int(r["Calls"])
+            total_ns += float(r["TotalDurationNs"])
+    if calls == 0:
+        raise SystemExit(f"no {kernel_part} in the kernel trace under {trace_dir}")
+    return total_ns / calls / 1e3
+
+
+def summarize_lds(pmc_dir: str, trace_dir: str, out_path: str, commands):
+    """profiles/lds_c3_23170.json from one rocprofv3 --pmc run with the LDS
+    counters (SQ_INSTS_LDS, SQ_LDS_IDX_ACTIVE, SQ_LDS_BANK_CONFLICT, SQ_WAVES)
+    and the kernel trace of the same command.  LDS bytes are counted as 256 per
+    LDS instruction (64 lanes x 4 B: the ring rows, windows and counters are
+    32-bit accesses; the two-wave visit's input sums, 64-bit, are one
+    instruction per visit), an estimate of the data the instructions move."""
+    import paper_2004_00540_amd as omap
+    kernels = {}
+    for part, label in LDS_KERNELS:
+        vals = {}
+        for c in LDS_COUNTERS:
+            vals[c], n = _counter_per_dispatch(pmc_dir, c, part)
+        us = _kernel_avg_us(trace_dir, part)
+        lds_bytes = vals["SQ_INSTS_LDS"] * 256
+        active, conflict = vals["SQ_LDS_IDX_ACTIVE"], vals["SQ_LDS_BANK_CONFLICT"]
+        kernels[label] = {
+            "dispatches_counted": n, "avg_us": round(us, 2),
+            "lds_instructions_per_launch": round(vals["SQ_INSTS_LDS"]),
+            "waves_per_launch": round(vals["SQ_WAVES"]),
+            "lds_bytes_per_launch_est": round(lds_bytes),
+            "lds_gbs": round(lds_bytes / (us * 1e-6) / 1e9, 1),
+            "lds_peak_gbs": round(LDS_PEAK_GBS, 1),
+            "lds_frac": round(lds_bytes / (us * 1e-6) / 1e9 / LDS_PEAK_GBS, 5),
+            "lds_active_cycles_per_launch": round(active),
+            "bank_conflict_cycles_per_launch": round(conflict),
+            "bank_conflicts_per_access": round(conflict / (active - conflict), 4) if active > conflict else None,
+        }
+    out = {"workload": "config3_23170x23170_rect_overlay", "options": omap.resolve_options(),
+           "kernel_source_sha256": kernel_source_hash(LDS_SOURCES), "kernel_sources": list(LDS_SOURCES),
+           "kernels": kernels, "commands": commands}
+    with open(out_path, "w") as f:
+        json.dump(out, f, indent=1)
+    lines = ["| kernel | avg us | LDS instr. per launch | waves | est. LDS GB/s | of peak | LDS active cycles | "
+             "bank-conflict cycles | conflicts per access |", "|---|---|---|---|---|---|---|---|---|"]
+    for label, k in kernels.items():
+        lines.append(f"| `{label}` | {k['avg_us']} | {k['lds_instructions_per_launch']} | {k['waves_per_launch']} | "
+                     f"{k['lds_gbs']} | {k['lds_frac'] * 100:.2f} % | {k['lds_active_cycles_per_launch']} | "
+                     f"{k['bank_conflict_cycles_per_launch']} | {k['bank_conflicts_per_access']} |")
+    print("\n".join(lines))
+
+
+def measured_lds(workload: str, options: dict):
+    """The committed LDS counter summary of the sweep and walk kernels, or None
+    when it was taken on other kernel sources or another configuration."""
+    try:
+        with open(LDS_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_sha256") != kernel_source_hash(LDS_SOURCES) or t.get("workload") != workload \
+            or t.get("options") != options:
+        return None
+    return t.get("kernels")
+
+
+def stream_copy_gbs(dev, reps: int = 5) -> dict:
+    """Device-to-device copy of 1 GiB (1 GiB read + 1 GiB written per copy),
+    timed with events: the HBM rate a plain streaming kernel reaches."""
+    import torch
+    n = 1 << 28
+    src = torch.ones(n, dtype=torch.int32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    torch.cuda.synchronize()
+    ev[0].record()
+    for _ in range(reps):
+        dst.copy_(src)
+    ev[1].record()
+    torch.cuda.synchronize()
+    s = ev[0].elapsed_time(ev[1]) / 1e3 / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    gbs = 2 * 4 * n / s / 1e9
+    return {"gbs": round(gbs, 1), "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4),
+            "kernel": "torch copy_ of 1 GiB int32, device to device (1 GiB read + 1 GiB written), "
+                      f"mean of {reps}"}
 
 
 def summarize_trace(directory: str, top: int = 14):
@@ -355,6 +455,8 @@ def bench_plain(args):
                          "unit": "Tops/s", "frac": round(alu_tops / VALU_PEAK_TOPS, 4),
                          "ops_per_cell_update": ops_per_cell},
     }
+    out["stream_copy"] = stream_copy_gbs(dev)
+    out["lds"] = measured_lds(m.name, resolved)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(m, step_s, executed, S_J, args.cpu_budget)
     return out
@@ -386,10 +488,16 @@ def main():
                                                               "COPY_WRITE_DIR"),
                     help="write profiles/k_sweep_c3_traffic.json from four rocprofv3 --pmc runs (no GPU)")
     ap.add_argument("--summarize-trace", metavar="DIR", help="markdown table of a rocprofv3 --stats run (no GPU)")
+    ap.add_argument("--summarize-lds", nargs=2, metavar=("PMC_DIR", "TRACE_DIR"),
+                    help="write profiles/lds_c3_23170.json from a rocprofv3 --pmc run of the LDS counters and "
+                         "the kernel trace of the same command (no GPU)")
     ap.add_argument("--commands", nargs="*", default=[], help="commands recorded with --summarize-counters")
     args = ap.parse_args()
     if args.summarize_counters:
         summarize_counters(*args.summarize_counters, TRAFFIC_FILE, args.commands)
+        return
+    if args.summarize_lds:
+        summarize_lds(*args.summarize_lds, LDS_FILE, args.commands)
         return
     if args.summarize_trace:
         summarize_trace(args.summarize_trace)
