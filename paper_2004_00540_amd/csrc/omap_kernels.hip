@@ -356,10 +356,11 @@ __global__ __launch_bounds__(kLanes * kWalkWaves) void k_walk(
     int64_t o = off[i];
     if (lane == 0) cells[o] = r * md.W + c;
     ++o;
-    // the cells of a window's steps are logged one per lane (lane k: step k
-    // of the window) as (window position of the step's 8 x 8 block centre)
-    // << 6 | (cell in the block), and stored when the window is left
-    int log = 0, nlog = 0;
+    // the cells of a window's steps are logged one iteration (three steps)
+    // per lane (lane k: iteration k of the window) as (window position of the
+    // iteration's 8 x 8 block centre) << 18 | q1 << 12 | q2 << 6 | q3 (the
+    // cells reached, numbered in the block), and stored when the window is left
+    int log = 0, it = 0;
     int dr_prev = 0, dc_prev = 0;   // displacement over the previous window
     int v0 = 0;
     for (int s = 0; s < steps;) {
@@ -401,42 +402,69 @@ __global__ __launch_bounds__(kLanes * kWalkWaves) void k_walk(
         int lr = r - R0, lc = c - C0;
         if (s == 0) v0 = __builtin_amdgcn_readfirstlane(win[lr * kWinCols + lc]);
         const int s_start = s;
-        // while the 8 x 8 block around (lr, lc) lies inside the window (and
-        // the log has room for three more steps)
-        while (s < steps && lr >= 3 && lr <= kWinRows - 5 && lc >= 3 && lc <= kWinCols - 5 && nlog <= kLanes - 3) {
-            const int pos = lr * kWinCols + lc;
-            const int v = win[pos + my_off];
-            const uint64_t m1 = __ballot(v == v0 + 1);
-            const uint64_t m2 = __ballot(v == v0 + 2);
-            const uint64_t m3 = __ballot(v == v0 + 3);
-            const int todo = min(3, steps - s);
-            int q = 27;   // the current cell
-#pragma unroll
-            for (int j = 0; j < 3; ++j) {
-                if (j < todo) {
-                    const uint64_t m = j == 0 ? m1 : (j == 1 ? m2 : m3);
-                    q = __builtin_ctzll(m & (kNbr << (q - 9)));
-                    log = lane == nlog + j ? (pos << 6) | q : log;
-                }
+        // Whole iterations of three steps.  An iteration moves at most three
+        // rows and three columns, so from the current cell the next n
+        // iterations all start with their 8 x 8 block inside the window; the
+        // bounds are checked once per such run.
+        for (;;) {
+            const int room = min(min(lr - 3, kWinRows - 5 - lr), min(lc - 3, kWinCols - 5 - lc));
+            int n = room < 0 ? 0 : room / 3 + 1;
+            n = min(n, min((steps - s) / 3, kLanes - it));
+            if (n <= 0) break;
+            for (int k = 0; k < n; ++k) {
+                const int pos = lr * kWinCols + lc;
+                const int d = win[pos + my_off] - v0;
+                const uint64_t m1 = __ballot(d == 1);
+                const uint64_t m2 = __ballot(d == 2);
+                const uint64_t m3 = __ballot(d == 3);
+                const int q1 = __builtin_ctzll(m1 & (kNbr << 18));   // neighbours of the centre, cell 27
+                const int q2 = __builtin_ctzll(m2 & (kNbr << (q1 - 9)));
+                const int q3 = __builtin_ctzll(m3 & (kNbr << (q2 - 9)));
+                const int e = (pos << 18) | (q1 << 12) | (q2 << 6) | q3;
+                log = lane == it + k ? e : log;
+                lr += (q3 >> 3) - 3;
+                lc += (q3 & 7) - 3;
+                v0 += 3;
             }
-            nlog += todo;
+            it += n;
+            s += 3 * n;
+        }
+        // the path's last one or two steps, once their block fits
+        if (s < steps && steps - s < 3 && it < kLanes && lr >= 3 && lr <= kWinRows - 5 && lc >= 3 &&
+            lc <= kWinCols - 5) {
+            const int pos = lr * kWinCols + lc;
+            const int d = win[pos + my_off] - v0;
+            const uint64_t m1 = __ballot(d == 1);
+            const uint64_t m2 = __ballot(d == 2);
+            const int todo = steps - s;
+            const int q1 = __builtin_ctzll(m1 & (kNbr << 18));
+            const int q2 = todo > 1 ? __builtin_ctzll(m2 & (kNbr << (q1 - 9))) : 0;
+            const int q = todo > 1 ? q2 : q1;
+            log = lane == it ? (pos << 18) | (q1 << 12) | (q2 << 6) : log;
+            ++it;
             lr += (q >> 3) - 3;
             lc += (q & 7) - 3;
             v0 += todo;
             s += todo;
         }
-        if (lane < nlog) {
-            const int q = log & 63, pos = log >> 6;
-            cells[o + lane] = (R0 + (pos >> 6) - 3 + (q >> 3)) * md.W + (C0 + (pos & 63) - 3 + (q & 7));
+        const int nst = s - s_start;   // steps taken in this window
+        if (lane < it) {
+            const int pos = log >> 18, pr = pos >> 6, pc = pos & 63;
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                if (3 * lane + j < nst) {
+                    const int q = (log >> (12 - 6 * j)) & 63;
+                    cells[o + 3 * lane + j] = (R0 + pr - 3 + (q >> 3)) * md.W + (C0 + pc - 3 + (q & 7));
+                }
+            }
         }
-        o += nlog;
-        nlog = 0;
+        o += nst;
+        it = 0;
         dr_prev = lr - (r - R0);
         dc_prev = lc - (c - C0);
         // a move of less than a third of the steps counts as no direction
-        const int moved = s - s_start;
-        if (3 * abs(dr_prev) < moved) dr_prev = 0;
-        if (3 * abs(dc_prev) < moved) dc_prev = 0;
+        if (3 * abs(dr_prev) < nst) dr_prev = 0;
+        if (3 * abs(dc_prev) < nst) dc_prev = 0;
         r = R0 + lr;
         c = C0 + lc;
         // the next window overwrites this one only after every lane's reads
