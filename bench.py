@@ -517,12 +517,12 @@ def main():
             b = bench_batch(args)
             out["batch"] = {k: b[k] for k in ("value", "unit", "ms_per_step", "plain_loop_mazes_per_s",
                                               "speedup_vs_plain_loop", "paths_per_s", "config", "options",
-                                              "default_options_mazes_per_s")}
+                                              "options_source", "default_options_mazes_per_s")}
             torch.cuda.empty_cache()
             sv = bench_serve(args)
             out["serve"] = {k: sv[k] for k in ("capacity_mazes_per_s", "open_loop_mazes_per_s", "latency_ms",
                                                "plain_loop_mazes_per_s", "capacity_vs_plain_loop", "config",
-                                               "options")}
+                                               "options", "options_source")}
     elif args.workload == "batch":
         from bench_forms import bench_batch
         out = bench_batch(args)

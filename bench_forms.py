@@ -132,6 +132,9 @@ def bench_batch(args):
                      "algorithmic_bytes": "0.375 B per cell-layer + 4 B per reached cell" if bits
                      else "8.125 B per cell-update"},
         "options": resolved if tuned is None else tuned["options"],
+        "options_source": ("command line or built-in defaults" if tuned is None else
+                           "autotuner" if any(tuned["options"].values()) else
+                           "autotuner: the built-in batch defaults won (zero fields = the defaults)"),
         "autotuner": tuned,
         "default_options_mazes_per_s": round(n / t_default, 2) if t_default else None,
     }
@@ -249,6 +252,9 @@ def bench_serve(args):
         "plain_loop_mazes_per_s": round(plain_rate, 2),
         "capacity_vs_plain_loop": round(capacity / plain_rate, 2),
         "options": opts,
+        "options_source": ("command line or built-in defaults" if tuned is None else
+                           "autotuner" if any(tuned["options"].values()) else
+                           "autotuner: the built-in engine defaults won (zero fields = the defaults)"),
         "autotuner": tuned,
     }
 
