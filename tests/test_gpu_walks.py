@@ -98,3 +98,43 @@ def test_bad_walk_mode():
         with pytest.raises(omap.OmapError) as e:
             plan.paths(7)
         assert e.value.name == "OMAP_ERR_INVALID_ARG"
+
+
+def _comb(H, W, vertical=False):
+    """A serpentine maze: walls on every other row (column), each with one gap,
+    alternating between the two ends, so the path from the corner source winds
+    through the whole grid."""
+    occ = np.zeros((H, W), np.uint8)
+    for k, r in enumerate(range(1, H - 1, 2)):
+        occ[r, :] = 1
+        occ[r, W - 1 if k % 2 == 0 else 0] = 0
+    if vertical:
+        occ = np.ascontiguousarray(occ.T)
+    return occ
+
+
+def test_walk_winding_paths_and_short_tails():
+    """Walks whose many three-step iterations stay inside one LDS window (the
+    window is left because its log is full, not because the path leaves it),
+    windows at the grid's edges and corners, and paths of every length modulo
+    three (the last one or two steps of a path), against the oracle."""
+    from gpu_helpers import assert_same, oracle_solution, run_plan
+    cases = []
+    # (a 20 x 30 comb lies inside the first window of a path from its far end,
+    # so its ~300-step paths fill the 64-entry log before leaving the window)
+    for H, W, vert in ((20, 30, False), (30, 20, True), (39, 57, False), (57, 39, True), (121, 203, False),
+                       (203, 121, True), (5, 300, False)):
+        occ = _comb(H, W, vert)
+        free = np.argwhere(occ == 0).astype(np.int32)
+        for src in ([[0, 0]], [[occ.shape[0] - 1, occ.shape[1] - 1]], [[0, 0], [occ.shape[0] // 2, 0]]):
+            src = np.array(src, np.int32)
+            src = src[occ[src[:, 0], src[:, 1]] == 0]
+            cases.append(workloads.Maze(occ, src, free[::5].copy(), f"comb_{H}x{W}_{len(src)}"))
+    # short paths: targets 0..8 cells from a source in an open grid, at the edges
+    occ = np.zeros((9, 11), np.uint8)
+    cases.append(workloads.Maze(occ, np.array([[4, 5]], np.int32), np.argwhere(occ == 0).astype(np.int32), "open_9x11"))
+    cases.append(workloads.Maze(occ, np.array([[0, 0]], np.int32), np.argwhere(occ == 0).astype(np.int32),
+                                "open_9x11_corner"))
+    for m in cases:
+        assert len(m.sources) > 0
+        assert_same(m, run_plan(m, -1), oracle_solution(m, -1), m.name)
