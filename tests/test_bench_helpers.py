@@ -54,3 +54,28 @@ def test_committed_summaries_match_their_sources():
             t = json.load(f)
         assert t["kernel_sources"] == list(files)
         assert len(t["kernel_source_sha256"]) == 64
+
+
+def test_more_than_one_gpu_is_refused():
+    import subprocess
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def test_summaries_of_other_sources_are_not_reported(tmp_path, monkeypatch):
+    """measured_traffic / measured_lds give None when the summary's source hash,
+    workload or options differ from the run's."""
+    t = {"kernel_source_sha256": "0" * 64, "workload": "w", "options": {"a": 1}, "bytes_per_launch": 5,
+         "kernels": {"k": {}}}
+    for attr, fn in (("TRAFFIC_FILE", bench.measured_traffic), ("LDS_FILE", bench.measured_lds)):
+        path = tmp_path / (attr + ".json")
+        path.write_text(json.dumps(t))
+        monkeypatch.setattr(bench, attr, str(path))
+        assert fn("w", {"a": 1}) is None            # other sources
+        good = dict(t, kernel_source_sha256=bench.kernel_source_hash(
+            bench.KERNEL_SOURCES if attr == "TRAFFIC_FILE" else bench.LDS_SOURCES))
+        path.write_text(json.dumps(good))
+        assert fn("w", {"a": 1}) is not None
+        assert fn("other", {"a": 1}) is None
+        assert fn("w", {"a": 2}) is None
