@@ -253,6 +253,26 @@ __global__ void k_path_lengths(const MazeDev* __restrict__ mazes, const int32_t*
 // and optionally an order of the targets by path length, longest first (by
 // the length's bit width: a bucket order, not a full sort), so that the walk
 // starts the paths that take longest before the others.
+// Takes a slot in bucket k for every lane with k >= 0 (wave-uniform call):
+// one LDS atomic per distinct key in the wave, the lanes of a key numbered in
+// lane order.  Returns the lane's slot, or -1 for k < 0.
+__device__ __forceinline__ int wave_bucket_slot(int* bucket, int k) {
+    const int lane = lane_id();
+    int slot = -1;
+    uint64_t todo = __ballot(k >= 0);
+    while (todo != 0) {
+        const int leader = __builtin_ctzll(todo);
+        const int kk = __shfl(k, leader);
+        const uint64_t same = __ballot(k == kk);
+        int base = 0;
+        if (lane == leader) base = atomicAdd(&bucket[kk], __popcll(same));
+        base = __shfl(base, leader);
+        if (k == kk) slot = base + __popcll(same & ((1ull << lane) - 1));
+        todo &= ~same;
+    }
+    return slot;
+}
+
 __global__ __launch_bounds__(1024) void k_scan(const int32_t* __restrict__ len, int32_t n,
                                                int64_t* __restrict__ off, int32_t* __restrict__ order) {
     __shared__ int64_t part[1024];
@@ -260,6 +280,7 @@ __global__ __launch_bounds__(1024) void k_scan(const int32_t* __restrict__ len, 
     const int chunk = (n + 1023) / 1024;
     const int b = min(n, t * chunk), e = min(n, b + chunk);
     int64_t s = 0;
+#pragma unroll 8
     for (int i = b; i < e; ++i) s += len[i] >= 0 ? (int64_t)len[i] + 1 : 0;
     part[t] = s;
     __syncthreads();
@@ -271,6 +292,7 @@ __global__ __launch_bounds__(1024) void k_scan(const int32_t* __restrict__ len, 
     }
     int64_t base = t ? part[t - 1] : 0;
     if (t == 0) off[0] = 0;
+#pragma unroll 8
     for (int i = b; i < e; ++i) {
         base += len[i] >= 0 ? (int64_t)len[i] + 1 : 0;
         off[i + 1] = base;
@@ -279,9 +301,20 @@ __global__ __launch_bounds__(1024) void k_scan(const int32_t* __restrict__ len, 
     __shared__ int bucket[33];
     if (t < 33) bucket[t] = 0;
     __syncthreads();
-    // key 0 = the longest lengths (32 - bit width of len + 1; unreached last)
-    auto key = [&](int i) { return len[i] < 0 ? 32 : __clz(len[i] + 1); };
-    for (int i = b; i < e; ++i) atomicAdd(&bucket[key(i)], 1);
+    // key 0 = the longest lengths (32 - bit width of len + 1; unreached last);
+    // elements in rows of 1024 (every thread runs the same number of rounds,
+    // -1: past the end), eight rows' keys loaded together, one LDS atomic per
+    // distinct key of a wave
+    auto key = [&](int i) { return i >= n ? -1 : (len[i] < 0 ? 32 : __clz(len[i] + 1)); };
+    constexpr int kRows = 8;
+    const int rows = (n + 1023) / 1024;
+    for (int j0 = 0; j0 < rows; j0 += kRows) {
+        int kb[kRows];
+#pragma unroll
+        for (int u = 0; u < kRows; ++u) kb[u] = key((j0 + u) * 1024 + t);
+#pragma unroll
+        for (int u = 0; u < kRows; ++u) (void)wave_bucket_slot(bucket, kb[u]);
+    }
     __syncthreads();
     if (t == 0) {
         int acc = 0;
@@ -292,7 +325,16 @@ __global__ __launch_bounds__(1024) void k_scan(const int32_t* __restrict__ len, 
         }
     }
     __syncthreads();
-    for (int i = b; i < e; ++i) order[atomicAdd(&bucket[key(i)], 1)] = i;
+    for (int j0 = 0; j0 < rows; j0 += kRows) {
+        int kb[kRows];
+#pragma unroll
+        for (int u = 0; u < kRows; ++u) kb[u] = key((j0 + u) * 1024 + t);
+#pragma unroll
+        for (int u = 0; u < kRows; ++u) {
+            const int slot = wave_bucket_slot(bucket, kb[u]);
+            if (slot >= 0) order[slot] = (j0 + u) * 1024 + t;
+        }
+    }
 }
 
 __device__ __forceinline__ int dir_dr(int k) { return k < 3 ? -1 : (k < 5 ? 0 : 1); }
